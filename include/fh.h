@@ -1,0 +1,173 @@
+/*
+ * fh.h -- C-ABI of the MI355X FFT-preconditioned finite-element
+ * homogenization solver (Ladecky et al., "Optimal FFT-accelerated Finite
+ * Element Solver for Homogenization").
+ *
+ * What the library computes
+ *   For a periodic cell discretised on a regular grid with a one-node
+ *   stencil (Sec. 3, Fig. tiling) and an element-wise constant linear
+ *   material, it solves for every macroscopic load e_j the linear system
+ *   K u_j = b_j with K = D^T W C D and b_j = -D^T W C e_j (eq. lin_system with
+ *   u_(0) = 0) by PCG (Sec. 4.1, Alg. 1) preconditioned with the pseudo-inverse
+ *   of the reference stiffness Kref = D^T W Cref D (eq. Kref), applied as
+ *   F^H K^+ F (eq. M_inverse) with K^ assembled by Alg. 2.  PCG stops when the
+ *   Kref^-1-norm of the residual has dropped by eta (Sec. 6, termination
+ *   criteria).  The homogenized tensor is returned in energy form
+ *   C_hom[i][j] = (1/|Y|) sum_Q w_Q (e_i + D u_i)^T C (e_j + D u_j).
+ *
+ * Conventions
+ *   Grid n = (nx, ny, nz) (nz = 1 in 2D), cell lengths l (h = l/n).  Every
+ *   grid array is x-fastest: element (x, y, z) at x + nx*(y + ny*z).  A voxel
+ *   (pixel) belongs to its lowest corner node.  Nodal fields are
+ *   component-major: u[c][z][y][x], c < nd (nd = d for elasticity, 1 for
+ *   scalar problems).  Strains and materials use Mandel notation
+ *   (Sec. 2, eq. mandel_grad): 3D order 11, 22, 33, 23, 13, 12 with sqrt(2)
+ *   on shear; 2D order 11, 22, 12.  A scalar material is the d x d
+ *   conductivity (App. A).
+ *
+ * Memory
+ *   Pointers whose name ends in _dev are device pointers (HBM of the device
+ *   given to fh_create); all other array pointers are host pointers.  The
+ *   caller owns every array it passes; the library copies host inputs and
+ *   reads device inputs during the call (a device phase/conductivity field
+ *   must stay alive until the next fh_set_* call or fh_destroy).  Device work
+ *   runs on the stream set by fh_set_stream (default: the null stream); calls
+ *   that return results to the host synchronise that stream.  Device scratch
+ *   comes from a caller-bound workspace (fh_bind_workspace) or, if none is
+ *   bound, from hipMalloc inside the library.
+ *
+ * Errors
+ *   0 = success; > 0 warning with a valid result (FH_NOT_CONVERGED);
+ *   < 0 error, no result.  fh_last_error() returns a message for the last
+ *   failing call on the context.  A context is not thread-safe.
+ */
+#ifndef FH_H
+#define FH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FH_OK 0
+#define FH_NOT_CONVERGED 1
+#define FH_EINVAL (-1)
+#define FH_ENOMEM (-2)
+#define FH_EDEVICE (-3)
+#define FH_ENOTSPD (-4)
+#define FH_ESTATE (-5)
+
+#define FH_SCALAR 0  /* thermal conduction (App. A)            */
+#define FH_ELASTIC 1 /* small-strain elasticity (Sec. 2)       */
+
+#define FH_HEX8 0  /* 3D trilinear hexahedron, 2x2x2 Gauss points, w = V_p/8 */
+#define FH_QUAD4 1 /* 2D bilinear quadrilateral, 2x2 Gauss points, w = V_p/4 (Fig. tiling a.2) */
+#define FH_TRI2 2  /* 2D two linear triangles per pixel, split along (0,0)-(1,1),
+                      one centroid point each, w = V_p/2 (Fig. tiling b.2) */
+
+#define FH_FP64 0          /* every kernel in FP64                                 */
+#define FH_FP32_REFINED 1  /* FP32 operator/FFT/solve inside FP64 refinement       */
+
+#define FH_MAX_LOADS 32
+
+typedef struct fh_ctx fh_ctx;
+
+typedef struct fh_opts {
+  double eta;       /* relative Kref^-1-norm tolerance (Sec. 6); e.g. 1e-10       */
+  int itmax;        /* PCG iteration cap per load case (Alg. 1 it_max^CG)         */
+  int precision;    /* FH_FP64 or FH_FP32_REFINED                                 */
+  int poll;         /* iterations between host convergence polls (0 = default)   */
+  int reserved_i;   /* must be 0                                                  */
+  double eta_inner; /* inner FP32 tolerance for FH_FP32_REFINED (0 = default)    */
+} fh_opts;
+
+typedef struct fh_stats {
+  int nload;
+  int iterations[FH_MAX_LOADS]; /* PCG iterations per load case (inner, summed)  */
+  int status[FH_MAX_LOADS];     /* 0 converged, 1 not converged, < 0 error       */
+  double rel_res[FH_MAX_LOADS]; /* final sqrt(r.z / r0.z0)                        */
+  int outer[FH_MAX_LOADS];      /* refinement sweeps (FH_FP32_REFINED)            */
+  double setup_ms;              /* Cref, Alg. 2 symbol, right-hand sides          */
+  double solve_ms;              /* PCG loops of all load cases                    */
+  double chom_ms;               /* homogenized-tensor reduction                   */
+  long long dof;                /* nd * N                                         */
+} fh_stats;
+
+/* Context on HIP device `device`.  Returns FH_EDEVICE if it cannot be used. */
+int fh_create(fh_ctx **out, int device);
+void fh_destroy(fh_ctx *ctx);
+const char *fh_last_error(const fh_ctx *ctx);
+
+/* HIP stream (hipStream_t) all device work is issued on; NULL = null stream. */
+int fh_set_stream(fh_ctx *ctx, void *hip_stream);
+
+/* Grid and discretisation (Sec. 3).  dim = 2 or 3; n[2] ignored (taken as 1)
+ * in 2D; l = cell edge lengths (NULL = all 1).  problem = FH_SCALAR or
+ * FH_ELASTIC; element = FH_HEX8 (dim 3) or FH_QUAD4 / FH_TRI2 (dim 2).
+ * nx and ny must be even; every n must be a product of 2, 3 and 5 and at
+ * most 512.  Invalidates phases, loads and results.                          */
+int fh_set_grid(fh_ctx *ctx, int dim, const int n[3], const double l[3], int problem,
+                int element);
+
+/* Element-wise constant material (Sec. 4.3): phase_dev = uint8 per voxel
+ * (device, N bytes), mat = nphase tables (host), each m x m row-major with
+ * m = d_m (elastic, Mandel) or d (scalar conductivity).  Tables must be
+ * symmetric; nphase in 1..256.  Phase ids >= nphase make fh_solve fail.   */
+int fh_set_phases(fh_ctx *ctx, const uint8_t *phase_dev, int nphase, const double *mat);
+
+/* Per-voxel scalar conductivity A = k I (scalar problems, FH_HEX8):
+ * k_dev = N doubles on the device, all > 0.                                 */
+int fh_set_conductivity_field(fh_ctx *ctx, const double *k_dev);
+
+/* Reference material Cref (eq. Kref), m x m host, symmetric positive
+ * definite; NULL = quadrature-weighted mean of the material (Sec. 6.2).    */
+int fh_set_reference(fh_ctx *ctx, const double *Cref);
+
+/* Macroscopic strains / gradients e_j (Sec. 2, App. A): nload x m host
+ * (Mandel for elasticity), nload in 1..FH_MAX_LOADS.                        */
+int fh_set_load(fh_ctx *ctx, int nload, const double *E);
+
+/* Device bytes the next fh_solve needs for the current grid and loads, and
+ * binding of a caller-owned device buffer of at least that size (256-byte
+ * aligned).  Binding NULL returns to library-owned memory.                 */
+int fh_workspace_size(fh_ctx *ctx, size_t *bytes);
+int fh_bind_workspace(fh_ctx *ctx, void *dev, size_t bytes);
+
+/* Setup (Alg. 2 and right-hand sides) followed by one PCG solve per load
+ * case, then the homogenized tensor.  opt may be NULL (eta 1e-10, itmax
+ * 10000, FP64).  Returns FH_NOT_CONVERGED if any load case hit itmax,
+ * FH_ENOTSPD on PCG breakdown (p.q <= 0) or a non-SPD Cref block.         */
+int fh_solve(fh_ctx *ctx, const fh_opts *opt, fh_stats *st);
+
+/* Results of the last fh_solve: fluctuation u_j (device, nd*N doubles,
+ * zero-mean representative) and the homogenized tensor (host, nload x nload,
+ * the full m x m tensor when the loads are the m unit vectors).            */
+int fh_get_fluctuation(fh_ctx *ctx, int load, double *u_dev);
+int fh_get_homogenized(fh_ctx *ctx, double *Chom);
+/* Reference material actually used (host, m x m) and the convergence
+ * history sqrt(r_k.z_k / r0.z0), k = 1..iterations (host, up to max).     */
+int fh_get_reference(fh_ctx *ctx, double *Cref);
+int fh_get_history(fh_ctx *ctx, int load, double *hist, int max, int *count);
+
+/* Step-level entry points (same kernels as fh_solve, for parity checks).
+ * All need fh_set_grid and a material; the symbol is (re)built if needed.
+ *   q_dev = K u_dev                     (eq. lin_system, matrix-free)
+ *   z_dev = M^+ r_dev = F^H K^+ F r     (eq. M_inverse)
+ *   b_dev = -D^T W C e                  for the macroscopic strain E (host)
+ *   kplus_dev = K^+(xi)/N, [s][kx][ky][kz], kx < nx/2+1, s over the
+ *     nd(nd+1)/2 symmetric entries ordered as the Mandel pairs
+ *     (00, 11, 22, 12, 02, 01) in 3D, (00, 11, 01) in 2D, (00) scalar.
+ *   fh_solve_rhs: PCG for K u = b_dev (b_dev zero-mean), result in u_dev. */
+int fh_apply_operator(fh_ctx *ctx, const double *u_dev, double *q_dev);
+int fh_apply_preconditioner(fh_ctx *ctx, const double *r_dev, double *z_dev);
+int fh_compute_rhs(fh_ctx *ctx, const double *E, double *b_dev);
+int fh_get_symbol(fh_ctx *ctx, double *kplus_dev);
+int fh_solve_rhs(fh_ctx *ctx, const double *b_dev, double *u_dev, const fh_opts *opt,
+                 fh_stats *st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FH_H */

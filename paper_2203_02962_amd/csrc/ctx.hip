@@ -1,0 +1,1106 @@
+// Host side of the C-ABI: context, setup (reference material, Alg. 2 symbol,
+// right-hand sides), the PCG driver and the homogenized tensor.
+//
+// Setup follows the paper: Cref defaults to the quadrature-weighted mean of
+// the material (Sec. 6.2); K^ comes from Alg. 2 -- the operator kernel is
+// applied to the nd unit impulses with the uniform reference material and the
+// responses are transformed with the forward FFT passes -- and every block is
+// inverted (zero block at zero frequency, eq. block_inversion).  The PCG loop
+// (Sec. 4.1, Alg. 1 with a linear material) runs entirely on the device; the
+// host only enqueues iterations and polls the per-load status every `poll`
+// iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fh.h"
+#include "fh_internal.h"
+
+using fh::cplx;
+
+struct fh_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  bool has_grid = false;
+  fh::Grid g{};
+  int problem = FH_SCALAR, element = FH_HEX8;
+  double l[3] = {1, 1, 1};
+  fh::AxisPlan px{}, py{}, pz{};
+  cplx<double>* twx = nullptr;
+  cplx<double>* twy = nullptr;
+  cplx<double>* twz = nullptr;
+
+  int mat_kind = 0;  // 0 none, 1 phases, 2 conductivity field
+  const uint8_t* phase_dev = nullptr;
+  const double* kfield_dev = nullptr;
+  int nphase = 0;
+  std::vector<double> mat;  // nphase * m * m
+
+  bool cref_user = false;
+  std::vector<double> cref_in, cref;  // m * m
+
+  int nload = 0;
+  std::vector<double> loads;  // nload * m
+
+  void* ws_user = nullptr;
+  size_t ws_user_bytes = 0;
+  void* ws_own = nullptr;
+  size_t ws_own_bytes = 0;
+
+  // small device tables (library-owned)
+  double* mat_dev = nullptr;   // K operator tables (double)
+  float* mat_dev_f = nullptr;  // float copy
+  double* ref_dev = nullptr;   // Kref operator tables
+  double* fe_dev = nullptr;    // RHS element forces
+  size_t mat_dev_n = 0, ref_dev_n = 0, fe_dev_n = 0;
+  unsigned long long* counts_dev = nullptr;
+  int* flag_dev = nullptr;
+  double* host_pinned = nullptr;  // pinned staging
+  size_t host_pinned_n = 0;
+
+  // workspace carve (set by bind_layout)
+  struct Layout {
+    size_t bytes = 0;
+    double *x, *r, *p, *q, *b;
+    cplx<double> *A, *B, *spec;
+    double* kplus;
+    float* kplus_f;
+    float *x32, *r32, *p32, *q32;
+    cplx<float> *A32, *B32;
+    double *d64;  // refinement: correction accumulator
+    fh::PcgState* st;
+    double *pq_part, *rz_part, *hist, *dot_part, *scal;
+    uint8_t* phase0;
+    int nb_kop, nb_z, nb_z32, hist_len;
+  } L{};
+  bool layout_ok = false;
+  int layout_nload = -1;
+
+  bool symbol_ok = false;
+  bool rhs_ok = false;
+  bool solved = false;
+  std::vector<double> chom;
+  std::vector<double> cmean;
+  std::vector<std::vector<double>> history;
+  fh_stats last{};
+};
+
+namespace {
+
+int fail(fh_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                           \
+  do {                                                                              \
+    hipError_t _e = (expr);                                                         \
+    if (_e != hipSuccess)                                                           \
+      return fail(ctx, FH_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+int mdim(const fh_ctx* c) {
+  const int d = c->g.dim;
+  return c->problem == FH_ELASTIC ? d * (d + 1) / 2 : d;
+}
+
+bool factor_ok(int n) {
+  if (n < 1) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  while (n % 5 == 0) n /= 5;
+  return n == 1;
+}
+
+fh::AxisPlan make_plan(int n) {
+  fh::AxisPlan p{};
+  p.n = n;
+  int m = n;
+  auto push = [&](unsigned r) { p.code |= r << (4 * p.nstage); ++p.nstage; };
+  while (m % 4 == 0) { push(4); m /= 4; }
+  while (m % 2 == 0) { push(2); m /= 2; }
+  while (m % 3 == 0) { push(3); m /= 3; }
+  while (m % 5 == 0) { push(5); m /= 5; }
+  return p;
+}
+
+// exp(-2 pi i k / n) with the angle reduced to [0, pi/4] by symmetry and
+// evaluated in long double.
+std::vector<cplx<double>> twiddle_table(int n) {
+  std::vector<cplx<double>> t(n);
+  for (int k = 0; k < n; ++k) {
+    // angle = 2 pi k / n, use exact integer reduction modulo n
+    const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)k /
+                          (long double)n;
+    t[k].re = (double)cosl(a);
+    t[k].im = (double)(-sinl(a));
+    // exact values at multiples of quarter turns
+    if ((4LL * k) % n == 0) {
+      const int q = (int)((4LL * k) / n) % 4;
+      const double cs[4] = {1, 0, -1, 0}, sn[4] = {0, 1, 0, -1};
+      t[k].re = cs[q];
+      t[k].im = -sn[q];
+    }
+  }
+  return t;
+}
+
+// ---------------------------------------------------- element definitions
+// Reference stencils of the paper's Fig. tiling (one-node, N_n = 1):
+//   hex8 / quad4: corners a with bit k = offset along axis k, Gauss points
+//   1/2 -+ 1/(2 sqrt 3) per axis, weights V_p/2^d;
+//   tri2: pixel split along (0,0)-(1,1), centroid points, weights V_p/2.
+struct ElemDef {
+  int dim, nc, nq;
+  std::vector<double> grad;  // [q][a][k] reference gradients
+  std::vector<double> wfrac;
+};
+
+ElemDef make_element(int element) {
+  ElemDef e{};
+  if (element == FH_TRI2) {
+    e.dim = 2; e.nc = 4; e.nq = 2;
+    e.grad.assign(2 * 4 * 2, 0.0);
+    auto G = [&](int q, int a, double gx, double gy) {
+      e.grad[(q * 4 + a) * 2 + 0] = gx;
+      e.grad[(q * 4 + a) * 2 + 1] = gy;
+    };
+    // lower triangle (0,0),(1,0),(1,1): lambda = 1-x, x-y, y
+    G(0, 0, -1, 0); G(0, 1, 1, -1); G(0, 3, 0, 1);
+    // upper triangle (0,0),(1,1),(0,1): lambda = 1-y, x, y-x
+    G(1, 0, 0, -1); G(1, 3, 1, 0); G(1, 2, -1, 1);
+    e.wfrac = {0.5, 0.5};
+    return e;
+  }
+  const int dim = element == FH_HEX8 ? 3 : 2;
+  e.dim = dim; e.nc = 1 << dim; e.nq = 1 << dim;
+  const double gp[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+  e.grad.assign((size_t)e.nq * e.nc * dim, 0.0);
+  for (int q = 0; q < e.nq; ++q) {
+    double xi[3];
+    for (int k = 0; k < dim; ++k) xi[k] = gp[(q >> k) & 1];
+    for (int a = 0; a < e.nc; ++a)
+      for (int k = 0; k < dim; ++k) {
+        double v = ((a >> k) & 1) ? 1.0 : -1.0;
+        for (int j = 0; j < dim; ++j)
+          if (j != k) v *= ((a >> j) & 1) ? xi[j] : 1.0 - xi[j];
+        e.grad[((size_t)q * e.nc + a) * dim + k] = v;
+      }
+  }
+  e.wfrac.assign(e.nq, 1.0 / e.nq);
+  return e;
+}
+
+// strain row m receives coef * d u_alpha / d x_beta (Mandel, eq. mandel_grad)
+struct GradRow { int m, alpha, beta; double coef; };
+std::vector<GradRow> grad_rows(int problem, int dim) {
+  const double s = std::sqrt(0.5);
+  if (problem == FH_SCALAR) {
+    std::vector<GradRow> r;
+    for (int b = 0; b < dim; ++b) r.push_back({b, 0, b, 1.0});
+    return r;
+  }
+  if (dim == 2) return {{0, 0, 0, 1}, {1, 1, 1, 1}, {2, 0, 1, s}, {2, 1, 0, s}};
+  return {{0, 0, 0, 1}, {1, 1, 1, 1}, {2, 2, 2, 1}, {3, 1, 2, s}, {3, 2, 1, s},
+          {4, 0, 2, s}, {4, 2, 0, s}, {5, 0, 1, s}, {5, 1, 0, s}};
+}
+
+// B_q (m x nc*nd) in physical coordinates
+std::vector<double> bmat(const fh_ctx* c, const ElemDef& e, int q) {
+  const int m = mdim(c), nd = c->g.nd, nk = e.nc * nd;
+  std::vector<double> B((size_t)m * nk, 0.0);
+  for (const GradRow& r : grad_rows(c->problem, e.dim))
+    for (int a = 0; a < e.nc; ++a)
+      B[(size_t)r.m * nk + a * nd + r.alpha] +=
+          r.coef * e.grad[((size_t)q * e.nc + a) * e.dim + r.beta] / c->g.h[r.beta];
+  return B;
+}
+
+double voxel_volume(const fh_ctx* c) {
+  double v = 1.0;
+  for (int k = 0; k < c->g.dim; ++k) v *= c->g.h[k];
+  return v;
+}
+
+// K_e = sum_q w_q B_q^T C B_q
+std::vector<double> element_matrix(const fh_ctx* c, const double* C) {
+  const ElemDef e = make_element(c->element);
+  const int m = mdim(c), nk = e.nc * c->g.nd;
+  const double Vp = voxel_volume(c);
+  std::vector<double> K((size_t)nk * nk, 0.0);
+  for (int q = 0; q < e.nq; ++q) {
+    const std::vector<double> B = bmat(c, e, q);
+    const double w = e.wfrac[q] * Vp;
+    std::vector<double> CB((size_t)m * nk, 0.0);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < nk; ++j) {
+        double s = 0;
+        for (int k = 0; k < m; ++k) s += C[i * m + k] * B[(size_t)k * nk + j];
+        CB[(size_t)i * nk + j] = s;
+      }
+    for (int i = 0; i < nk; ++i)
+      for (int j = 0; j < nk; ++j) {
+        double s = 0;
+        for (int k = 0; k < m; ++k) s += B[(size_t)k * nk + i] * CB[(size_t)k * nk + j];
+        K[(size_t)i * nk + j] += w * s;
+      }
+  }
+  return K;
+}
+
+// Element force of a uniform strain: f = (int_e B dx)^T (C E); the integral
+// of every shape-function derivative over a pixel is +-V_p / (2^(d-1) h_beta)
+// for all three stencils (divergence theorem), so antipodal corners get
+// exactly opposite forces.
+std::vector<double> uniform_strain_force(const fh_ctx* c, const double* C, const double* E) {
+  const int m = mdim(c), nd = c->g.nd, dim = c->g.dim, nc = 1 << dim;
+  const double Vp = voxel_volume(c);
+  std::vector<double> sig(m, 0.0);
+  for (int i = 0; i < m; ++i)
+    for (int k = 0; k < m; ++k) sig[i] += C[i * m + k] * E[k];
+  std::vector<double> f((size_t)nc * nd, 0.0);
+  const double scale = Vp / (double)(1 << (dim - 1));
+  for (int a = 0; a < nc; ++a) {
+    for (const GradRow& r : grad_rows(c->problem, dim)) {
+      const double g = (((a >> r.beta) & 1) ? 1.0 : -1.0) * scale / c->g.h[r.beta];
+      f[(size_t)a * nd + r.alpha] += r.coef * g * sig[r.m];
+    }
+  }
+  return f;
+}
+
+bool cholesky_ok(const std::vector<double>& A, int m) {
+  std::vector<double> L(A);
+  for (int j = 0; j < m; ++j) {
+    double d = L[j * m + j];
+    for (int k = 0; k < j; ++k) d -= L[j * m + k] * L[j * m + k];
+    if (!(d > 0.0)) return false;
+    d = std::sqrt(d);
+    L[j * m + j] = d;
+    for (int i = j + 1; i < m; ++i) {
+      double s = L[i * m + j];
+      for (int k = 0; k < j; ++k) s -= L[i * m + k] * L[j * m + k];
+      L[i * m + j] = s / d;
+    }
+  }
+  return true;
+}
+
+bool hex_elastic(const fh_ctx* c) { return c->element == FH_HEX8 && c->problem == FH_ELASTIC; }
+
+void free_tables(fh_ctx* c) {
+  hipFree(c->mat_dev); c->mat_dev = nullptr;
+  hipFree(c->mat_dev_f); c->mat_dev_f = nullptr;
+  hipFree(c->ref_dev); c->ref_dev = nullptr;
+  hipFree(c->fe_dev); c->fe_dev = nullptr;
+  c->mat_dev_n = c->ref_dev_n = c->fe_dev_n = 0;
+}
+
+// Operator tables: hex8 elastic -> V_p * C per phase (36); otherwise the
+// element matrices per phase (or the unit-conductivity matrix for a field).
+std::vector<double> operator_tables(const fh_ctx* c, const double* mats, int count) {
+  const int m = mdim(c);
+  std::vector<double> out;
+  if (hex_elastic(c)) {
+    const double Vp = voxel_volume(c);
+    for (int p = 0; p < count; ++p)
+      for (int i = 0; i < 36; ++i) out.push_back(Vp * mats[(size_t)p * m * m + i]);
+    return out;
+  }
+  for (int p = 0; p < count; ++p) {
+    std::vector<double> K = element_matrix(c, mats + (size_t)p * m * m);
+    out.insert(out.end(), K.begin(), K.end());
+  }
+  return out;
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Compute the workspace layout (offsets relative to base; base may be null
+// for sizing).
+size_t layout(fh_ctx* c, char* base, fh_ctx::Layout* Lout) {
+  fh_ctx::Layout L{};
+  const fh::Grid& g = c->g;
+  const int nl = std::max(1, c->nload);
+  const long long F = (long long)g.nd * g.N;
+  const long long S = (long long)g.nd * g.nxh * g.ny * g.nz;
+  const long long nfreq = (long long)g.nxh * g.ny * g.nz;
+  const int nsym = g.nd * (g.nd + 1) / 2;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += align_up(bytes);
+    return p;
+  };
+  L.x = (double*)take(sizeof(double) * F * nl);
+  L.r = (double*)take(sizeof(double) * F * nl);
+  L.p = (double*)take(sizeof(double) * F * nl);
+  L.q = (double*)take(sizeof(double) * F * nl);
+  L.b = (double*)take(sizeof(double) * F * nl);
+  L.A = (cplx<double>*)take(sizeof(cplx<double>) * S * nl);
+  L.B = (cplx<double>*)take(sizeof(cplx<double>) * S * nl);
+  L.spec = (cplx<double>*)take(sizeof(cplx<double>) * S * g.nd);
+  L.kplus = (double*)take(sizeof(double) * nfreq * nsym);
+  L.kplus_f = (float*)take(sizeof(float) * nfreq * nsym);
+  L.x32 = (float*)take(sizeof(float) * F * nl);
+  L.r32 = (float*)take(sizeof(float) * F * nl);
+  L.p32 = (float*)take(sizeof(float) * F * nl);
+  L.q32 = (float*)take(sizeof(float) * F * nl);
+  L.A32 = (cplx<float>*)take(sizeof(cplx<float>) * S * nl);
+  L.B32 = (cplx<float>*)take(sizeof(cplx<float>) * S * nl);
+  L.d64 = (double*)take(sizeof(double) * F * nl);
+  L.st = (fh::PcgState*)take(sizeof(fh::PcgState) * nl);
+  L.nb_kop = fh::kop_nblocks(g, hex_elastic(c));
+  L.nb_z = fh::zpass_nblocks<double>(g);
+  L.nb_z32 = fh::zpass_nblocks<float>(g);
+  const int nbz = std::max(L.nb_z, L.nb_z32);
+  L.pq_part = (double*)take(sizeof(double) * (size_t)L.nb_kop * nl);
+  L.rz_part = (double*)take(sizeof(double) * (size_t)nbz * nl);
+  L.hist_len = 20000;
+  L.hist = (double*)take(sizeof(double) * (size_t)L.hist_len * nl);
+  L.dot_part = (double*)take(sizeof(double) * 1024);
+  L.scal = (double*)take(sizeof(double) * 64);
+  L.phase0 = (uint8_t*)take((size_t)g.N);
+  L.bytes = off;
+  if (Lout) *Lout = L;
+  return off;
+}
+
+int ensure_layout(fh_ctx* c) {
+  if (c->layout_ok && c->layout_nload == c->nload) return FH_OK;
+  size_t need = layout(c, nullptr, nullptr);
+  char* base = nullptr;
+  if (c->ws_user) {
+    if (c->ws_user_bytes < need)
+      return fail(c, FH_ENOMEM, "bound workspace too small: need " + std::to_string(need) +
+                                    " bytes");
+    base = (char*)c->ws_user;
+  } else {
+    if (c->ws_own_bytes < need) {
+      hipFree(c->ws_own);
+      c->ws_own = nullptr;
+      c->ws_own_bytes = 0;
+      if (hipMalloc(&c->ws_own, need) != hipSuccess)
+        return fail(c, FH_ENOMEM, "hipMalloc of workspace failed (" + std::to_string(need) +
+                                      " bytes)");
+      c->ws_own_bytes = need;
+    }
+    base = (char*)c->ws_own;
+  }
+  layout(c, base, &c->L);
+  c->layout_ok = true;
+  c->layout_nload = c->nload;
+  c->symbol_ok = false;
+  c->rhs_ok = false;
+  HIPCHK(c, hipMemsetAsync(c->L.phase0, 0, (size_t)c->g.N, c->stream));
+  return FH_OK;
+}
+
+int ensure_pinned(fh_ctx* c, size_t n) {
+  if (c->host_pinned_n >= n) return FH_OK;
+  if (c->host_pinned) hipHostFree(c->host_pinned);
+  c->host_pinned = nullptr;
+  c->host_pinned_n = 0;
+  HIPCHK(c, hipHostMalloc((void**)&c->host_pinned, n * sizeof(double), hipHostMallocDefault));
+  c->host_pinned_n = n;
+  return FH_OK;
+}
+
+int upload(fh_ctx* c, double** dst, size_t* dst_n, const std::vector<double>& v) {
+  if (*dst_n < v.size()) {
+    hipFree(*dst);
+    *dst = nullptr;
+    HIPCHK(c, hipMalloc((void**)dst, v.size() * sizeof(double)));
+    *dst_n = v.size();
+  }
+  HIPCHK(c, hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice,
+                           c->stream));
+  // the host vector is a temporary of the caller: wait until it is copied
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FH_OK;
+}
+
+// Apply K (or Kref when `ref`) to nload fields (double).
+int apply_K(fh_ctx* c, bool ref, const double* u, double* q, int nload, long long stride,
+            const fh::PcgState* st, double* pq) {
+  const fh::Grid& g = c->g;
+  const uint8_t* ph = ref ? c->L.phase0 : (c->mat_kind == 1 ? c->phase_dev : nullptr);
+  const double* kf = ref ? nullptr : (c->mat_kind == 2 ? c->kfield_dev : nullptr);
+  const double* tab = ref ? c->ref_dev : c->mat_dev;
+  int nb = 0;
+  if (hex_elastic(c)) {
+    HIPCHK(c, fh::launch_kop_hex8_elastic<double>(g, u, q, ph, tab, nload, stride, stride, st,
+                                                  pq, &nb, c->stream));
+  } else {
+    if (!ph && !kf) ph = c->L.phase0;
+    HIPCHK(c, fh::launch_kop_generic<double>(g, c->element, u, q, ph, kf, tab, nload, stride,
+                                             stride, st, pq, &nb, c->stream));
+  }
+  return FH_OK;
+}
+
+int apply_K32(fh_ctx* c, const float* u, float* q, int nload, long long stride,
+              const fh::PcgState* st, double* pq) {
+  const fh::Grid& g = c->g;
+  const uint8_t* ph = c->mat_kind == 1 ? c->phase_dev : nullptr;
+  int nb = 0;
+  if (hex_elastic(c)) {
+    HIPCHK(c, fh::launch_kop_hex8_elastic<float>(g, u, q, ph, c->mat_dev_f, nload, stride,
+                                                 stride, st, pq, &nb, c->stream));
+  } else {
+    return fail(c, FH_EINVAL, "FP32 operator only for hex8 elasticity in this build");
+  }
+  return FH_OK;
+}
+
+// M^+ on nload fields (double): r -> z in `out` (plain mode) using A/B.
+int precond_fields(fh_ctx* c, double* r, double* out, int nload, long long fstride) {
+  const fh::Grid& g = c->g;
+  const long long S = (long long)g.nd * g.nxh * g.ny * g.nz;
+  HIPCHK(c, fh::launch_xfwd<double>(g, c->px, c->twx, fh::XF_PLAIN, r, fstride, nullptr, 0,
+                                    c->L.A, S, nload, nullptr, c->stream));
+  HIPCHK(c, fh::launch_yfwd<double>(g, c->py, c->twy, c->L.A, c->L.B, S, nload, nullptr,
+                                    c->stream));
+  int nb = 0;
+  HIPCHK(c, fh::launch_zpass<double>(g, c->pz, c->twz, fh::Z_SOLVE, c->L.B, S, c->L.kplus,
+                                     nload, nullptr, nullptr, &nb, c->stream));
+  HIPCHK(c, fh::launch_yinv<double>(g, c->py, c->twy, c->L.B, c->L.A, S, nload, nullptr,
+                                    c->stream));
+  HIPCHK(c, fh::launch_xinv<double>(g, c->px, c->twx, fh::XI_PLAIN, c->L.A, S, out, nullptr,
+                                    nullptr, fstride, nload, nullptr, c->stream));
+  return FH_OK;
+}
+
+int check_material(fh_ctx* c) {
+  if (!c->has_grid) return fail(c, FH_ESTATE, "fh_set_grid not called");
+  if (c->mat_kind == 0) return fail(c, FH_ESTATE, "no material set");
+  return FH_OK;
+}
+
+// Reference material, symbol (Alg. 2) and Kref tables.
+int build_symbol(fh_ctx* c) {
+  int rc = check_material(c);
+  if (rc) return rc;
+  rc = ensure_layout(c);
+  if (rc) return rc;
+  if (c->symbol_ok) return FH_OK;
+  const fh::Grid& g = c->g;
+  const int m = mdim(c);
+  // quadrature-weighted mean of the material (Sec. 6.2)
+  c->cmean.assign((size_t)m * m, 0.0);
+  HIPCHK(c, hipMemsetAsync(c->flag_dev, 0, sizeof(int), c->stream));
+  if (c->mat_kind == 1) {
+    HIPCHK(c, hipMemsetAsync(c->counts_dev, 0, 256 * sizeof(unsigned long long), c->stream));
+    HIPCHK(c, fh::launch_phase_count(c->phase_dev, g.N, c->nphase, c->counts_dev, c->flag_dev,
+                                     c->stream));
+    unsigned long long counts[256];
+    int bad = 0;
+    HIPCHK(c, hipMemcpyAsync(counts, c->counts_dev, sizeof(counts), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(&bad, c->flag_dev, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (bad) return fail(c, FH_EINVAL, "phase id >= nphase in phase field");
+    for (int p = 0; p < c->nphase; ++p)
+      for (int i = 0; i < m * m; ++i)
+        c->cmean[i] += (double)counts[p] * c->mat[(size_t)p * m * m + i];
+    for (double& v : c->cmean) v /= (double)g.N;
+  } else {
+    const int nb = 1024;
+    HIPCHK(c, fh::launch_field_sum(c->kfield_dev, g.N, c->L.dot_part, nb, c->stream));
+    HIPCHK(c, fh::launch_sum_partials(c->L.dot_part, nb, c->L.scal, c->stream));
+    double ks = 0;
+    HIPCHK(c, hipMemcpyAsync(&ks, c->L.scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (!(ks > 0.0)) return fail(c, FH_EINVAL, "conductivity field must be positive");
+    for (int i = 0; i < m; ++i) c->cmean[i * m + i] = ks / (double)g.N;
+  }
+  c->cref = c->cref_user ? c->cref_in : c->cmean;
+  if (!cholesky_ok(c->cref, m)) return fail(c, FH_ENOTSPD, "reference material is not SPD");
+  rc = upload(c, &c->ref_dev, &c->ref_dev_n, operator_tables(c, c->cref.data(), 1));
+  if (rc) return rc;
+  // Alg. 2: impulse responses of Kref, forward FFT, per-frequency inverse
+  const long long F = (long long)g.nd * g.N;
+  const long long S = (long long)g.nd * g.nxh * g.ny * g.nz;
+  for (int be = 0; be < g.nd; ++be) {
+    HIPCHK(c, fh::launch_impulse(c->L.x, F, (long long)be * g.N, c->stream));
+    rc = apply_K(c, true, c->L.x, c->L.q, 1, F, nullptr, nullptr);
+    if (rc) return rc;
+    HIPCHK(c, fh::launch_xfwd<double>(g, c->px, c->twx, fh::XF_PLAIN, c->L.q, F, nullptr, 0,
+                                      c->L.A, S, 1, nullptr, c->stream));
+    HIPCHK(c, fh::launch_yfwd<double>(g, c->py, c->twy, c->L.A, c->L.spec + be * S, S, 1,
+                                      nullptr, c->stream));
+    int nb = 0;
+    HIPCHK(c, fh::launch_zpass<double>(g, c->pz, c->twz, fh::Z_FORWARD_ONLY, c->L.spec + be * S,
+                                       S, nullptr, 1, nullptr, nullptr, &nb, c->stream));
+  }
+  HIPCHK(c, hipMemsetAsync(c->flag_dev, 0, sizeof(int), c->stream));
+  HIPCHK(c, fh::launch_symbol(g, c->L.spec, S, c->L.kplus, c->flag_dev, c->stream));
+  const long long nsym_n = (long long)g.nxh * g.ny * g.nz * (g.nd * (g.nd + 1) / 2);
+  HIPCHK(c, fh::launch_cast_symbol(nsym_n, c->L.kplus, c->L.kplus_f, c->stream));
+  int bad = 0;
+  HIPCHK(c, hipMemcpyAsync(&bad, c->flag_dev, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (bad) return fail(c, FH_ENOTSPD, "reference symbol has a non-SPD block");
+  c->symbol_ok = true;
+  return FH_OK;
+}
+
+int build_rhs(fh_ctx* c) {
+  if (c->rhs_ok) return FH_OK;
+  if (c->nload < 1) return fail(c, FH_ESTATE, "fh_set_load not called");
+  const fh::Grid& g = c->g;
+  const int m = mdim(c);
+  const int ntab = c->mat_kind == 1 ? c->nphase : 1;
+  std::vector<double> fe;
+  const std::vector<double> unit = [&] {
+    std::vector<double> I((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i) I[i * m + i] = 1.0;
+    return I;
+  }();
+  for (int t = 0; t < ntab; ++t) {
+    const double* C = c->mat_kind == 1 ? c->mat.data() + (size_t)t * m * m : unit.data();
+    for (int j = 0; j < c->nload; ++j) {
+      std::vector<double> f = uniform_strain_force(c, C, c->loads.data() + (size_t)j * m);
+      fe.insert(fe.end(), f.begin(), f.end());
+    }
+  }
+  int rc = upload(c, &c->fe_dev, &c->fe_dev_n, fe);
+  if (rc) return rc;
+  const long long F = (long long)g.nd * g.N;
+  HIPCHK(c, fh::launch_rhs(g, c->element, c->mat_kind == 1 ? c->phase_dev : nullptr,
+                           c->mat_kind == 2 ? c->kfield_dev : nullptr, c->fe_dev, ntab,
+                           c->nload, c->L.b, F, c->stream));
+  c->rhs_ok = true;
+  return FH_OK;
+}
+
+// ------------------------------------------------------------ FP64 PCG
+// Solves K x = b for nload right-hand sides held in L.b (or `bsrc`), result
+// in L.x.  Everything stays on the device; status polled every `poll`.
+int pcg64(fh_ctx* c, int nload, double eta, int itmax, int poll, std::vector<fh::PcgState>& out) {
+  const fh::Grid& g = c->g;
+  const long long F = (long long)g.nd * g.N;
+  const long long S = (long long)g.nd * g.nxh * g.ny * g.nz;
+  fh_ctx::Layout& L = c->L;
+  std::vector<fh::PcgState> hs(nload);
+  for (auto& s : hs) {
+    s = fh::PcgState{};
+    s.status = fh::ST_ACTIVE;
+    s.eta2 = eta * eta;
+    s.itmax = itmax;
+  }
+  HIPCHK(c, hipMemcpyAsync(L.st, hs.data(), sizeof(fh::PcgState) * nload, hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, fh::launch_fill<double>(L.x, 0.0, F * nload, c->stream));
+  HIPCHK(c, fh::launch_copy(L.r, L.b, F * nload, c->stream));
+  // z0 = M r0, p0 = z0, rho0 = r0.z0
+  int nbz = 0;
+  HIPCHK(c, fh::launch_xfwd<double>(g, c->px, c->twx, fh::XF_PLAIN, L.r, F, nullptr, 0, L.A, S,
+                                    nload, L.st, c->stream));
+  HIPCHK(c, fh::launch_yfwd<double>(g, c->py, c->twy, L.A, L.B, S, nload, L.st, c->stream));
+  HIPCHK(c, fh::launch_zpass<double>(g, c->pz, c->twz, fh::Z_SOLVE, L.B, S, L.kplus, nload, L.st,
+                                     L.rz_part, &nbz, c->stream));
+  HIPCHK(c, fh::launch_yinv<double>(g, c->py, c->twy, L.B, L.A, S, nload, L.st, c->stream));
+  HIPCHK(c, fh::launch_xinv<double>(g, c->px, c->twx, fh::XI_INIT_P, L.A, S, nullptr, nullptr,
+                                    L.p, F, nload, L.st, c->stream));
+  HIPCHK(c, fh::launch_finalize_init(L.st, L.rz_part, nbz, nload, c->stream));
+  int done_iters = 0;
+  const int cap = itmax + 2;
+  while (true) {
+    for (int k = 0; k < poll && done_iters < cap; ++k, ++done_iters) {
+      int rc = apply_K(c, false, L.p, L.q, nload, F, L.st, L.pq_part);
+      if (rc) return rc;
+      HIPCHK(c, fh::launch_finalize_alpha(L.st, L.pq_part, L.nb_kop, nload, c->stream));
+      HIPCHK(c, fh::launch_xfwd<double>(g, c->px, c->twx, fh::XF_UPDATE_R, L.r, F, L.q, F, L.A,
+                                        S, nload, L.st, c->stream));
+      HIPCHK(c, fh::launch_yfwd<double>(g, c->py, c->twy, L.A, L.B, S, nload, L.st, c->stream));
+      HIPCHK(c, fh::launch_zpass<double>(g, c->pz, c->twz, fh::Z_SOLVE, L.B, S, L.kplus, nload,
+                                         L.st, L.rz_part, &nbz, c->stream));
+      HIPCHK(c, fh::launch_finalize_beta(L.st, L.rz_part, nbz, nload, L.hist, L.hist_len,
+                                         c->stream));
+      HIPCHK(c, fh::launch_yinv<double>(g, c->py, c->twy, L.B, L.A, S, nload, L.st, c->stream));
+      HIPCHK(c, fh::launch_xinv<double>(g, c->px, c->twx, fh::XI_PCG, L.A, S, nullptr, L.x, L.p,
+                                        F, nload, L.st, c->stream));
+    }
+    HIPCHK(c, hipMemcpyAsync(hs.data(), L.st, sizeof(fh::PcgState) * nload,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    bool any = false;
+    for (auto& s : hs) any |= (s.status == fh::ST_ACTIVE);
+    if (!any || done_iters >= cap) break;
+  }
+  out = hs;
+  return FH_OK;
+}
+
+void record_history(fh_ctx* c, const std::vector<fh::PcgState>& hs, int nload) {
+  c->history.assign(nload, {});
+  std::vector<double> h((size_t)c->L.hist_len * nload);
+  hipMemcpyAsync(h.data(), c->L.hist, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                 c->stream);
+  hipStreamSynchronize(c->stream);
+  for (int j = 0; j < nload; ++j) {
+    const int n = std::min(hs[j].iter, c->L.hist_len);
+    c->history[j].assign(h.begin() + (size_t)j * c->L.hist_len,
+                         h.begin() + (size_t)j * c->L.hist_len + n);
+  }
+}
+
+int status_code(int st) {
+  switch (st) {
+    case fh::ST_CONVERGED:
+    case fh::ST_CONVERGED_PENDING: return 0;
+    case fh::ST_MAXIT:
+    case fh::ST_MAXIT_PENDING: return 1;
+    default: return FH_ENOTSPD;
+  }
+}
+
+int fill_stats(fh_ctx* c, const std::vector<fh::PcgState>& hs, int nload, fh_stats* st) {
+  fh_stats s{};
+  s.nload = nload;
+  s.dof = (long long)c->g.nd * c->g.N;
+  int rc = FH_OK;
+  for (int j = 0; j < nload && j < FH_MAX_LOADS; ++j) {
+    s.iterations[j] = hs[j].iter;
+    s.status[j] = status_code(hs[j].status);
+    s.rel_res[j] = hs[j].last;
+    s.outer[j] = 0;
+    if (s.status[j] < 0) rc = FH_ENOTSPD;
+    else if (s.status[j] > 0 && rc == FH_OK) rc = FH_NOT_CONVERGED;
+  }
+  c->last = s;
+  if (st) *st = s;
+  if (rc == FH_ENOTSPD) fail(c, rc, "PCG breakdown (p.q <= 0 or r.z < 0)");
+  return rc;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+// ================================================================ C-ABI
+extern "C" {
+
+int fh_create(fh_ctx** out, int device) {
+  if (!out) return FH_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return FH_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return FH_EDEVICE;
+  fh_ctx* c = new fh_ctx();
+  c->device = device;
+  if (hipMalloc((void**)&c->counts_dev, 256 * sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc((void**)&c->flag_dev, sizeof(int)) != hipSuccess) {
+    delete c;
+    return FH_EDEVICE;
+  }
+  *out = c;
+  return FH_OK;
+}
+
+void fh_destroy(fh_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  hipFree(c->ws_own);
+  free_tables(c);
+  hipFree(c->counts_dev);
+  hipFree(c->flag_dev);
+  hipFree(c->twx);
+  hipFree(c->twy);
+  hipFree(c->twz);
+  if (c->host_pinned) hipHostFree(c->host_pinned);
+  delete c;
+}
+
+const char* fh_last_error(const fh_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int fh_set_stream(fh_ctx* c, void* s) {
+  if (!c) return FH_EINVAL;
+  c->stream = (hipStream_t)s;
+  return FH_OK;
+}
+
+int fh_set_grid(fh_ctx* c, int dim, const int n[3], const double l[3], int problem,
+                int element) {
+  if (!c || !n) return FH_EINVAL;
+  hipSetDevice(c->device);
+  if (dim != 2 && dim != 3) return fail(c, FH_EINVAL, "dim must be 2 or 3");
+  if (problem != FH_SCALAR && problem != FH_ELASTIC) return fail(c, FH_EINVAL, "bad problem");
+  if ((dim == 3) != (element == FH_HEX8) ||
+      (element != FH_HEX8 && element != FH_QUAD4 && element != FH_TRI2))
+    return fail(c, FH_EINVAL, "element does not match dim");
+  int nn[3] = {n[0], n[1], dim == 3 ? n[2] : 1};
+  for (int k = 0; k < 3; ++k)
+    if (nn[k] < 1 || nn[k] > 512 || !factor_ok(nn[k]))
+      return fail(c, FH_EINVAL, "grid sizes must be products of 2, 3, 5 and at most 512");
+  if (nn[0] % 2 || nn[1] % 2) return fail(c, FH_EINVAL, "nx and ny must be even");
+  if (dim == 3 && nn[2] < 2) return fail(c, FH_EINVAL, "nz must be >= 2 in 3D");
+  for (int k = 0; k < dim; ++k)
+    if (l && !(l[k] > 0.0)) return fail(c, FH_EINVAL, "cell lengths must be positive");
+  c->g = fh::Grid{};
+  c->g.nx = nn[0];
+  c->g.ny = nn[1];
+  c->g.nz = nn[2];
+  c->g.dim = dim;
+  c->g.nd = problem == FH_ELASTIC ? dim : 1;
+  c->g.nxh = nn[0] / 2 + 1;
+  c->g.N = (long long)nn[0] * nn[1] * nn[2];
+  for (int k = 0; k < 3; ++k) {
+    c->l[k] = (l && k < dim) ? l[k] : 1.0;
+    c->g.h[k] = c->l[k] / nn[k];
+  }
+  c->problem = problem;
+  c->element = element;
+  c->px = make_plan(nn[0]);
+  c->py = make_plan(nn[1]);
+  c->pz = make_plan(nn[2]);
+  auto up = [&](cplx<double>** dst, int len) -> int {
+    hipFree(*dst);
+    *dst = nullptr;
+    std::vector<cplx<double>> t = twiddle_table(len);
+    HIPCHK(c, hipMalloc((void**)dst, sizeof(cplx<double>) * len));
+    HIPCHK(c, hipMemcpy(*dst, t.data(), sizeof(cplx<double>) * len, hipMemcpyHostToDevice));
+    return FH_OK;
+  };
+  int rc;
+  if ((rc = up(&c->twx, nn[0])) || (rc = up(&c->twy, nn[1])) || (rc = up(&c->twz, nn[2])))
+    return rc;
+  c->has_grid = true;
+  c->mat_kind = 0;
+  c->nload = 0;
+  c->layout_ok = false;
+  c->symbol_ok = c->rhs_ok = c->solved = false;
+  free_tables(c);
+  return FH_OK;
+}
+
+int fh_set_phases(fh_ctx* c, const uint8_t* phase_dev, int nphase, const double* mat) {
+  if (!c) return FH_EINVAL;
+  hipSetDevice(c->device);
+  if (!c->has_grid) return fail(c, FH_ESTATE, "fh_set_grid not called");
+  if (!phase_dev || !mat || nphase < 1 || nphase > 256)
+    return fail(c, FH_EINVAL, "bad phase arguments");
+  const int m = mdim(c);
+  for (int p = 0; p < nphase; ++p)
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) {
+        const double a = mat[(size_t)p * m * m + i * m + j], b = mat[(size_t)p * m * m + j * m + i];
+        if (!std::isfinite(a) || std::fabs(a - b) > 1e-12 * (std::fabs(a) + std::fabs(b)))
+          return fail(c, FH_EINVAL, "material tables must be finite and symmetric");
+      }
+  c->phase_dev = phase_dev;
+  c->nphase = nphase;
+  c->mat.assign(mat, mat + (size_t)nphase * m * m);
+  c->kfield_dev = nullptr;
+  c->mat_kind = 1;
+  std::vector<double> tab = operator_tables(c, c->mat.data(), nphase);
+  int rc = upload(c, &c->mat_dev, &c->mat_dev_n, tab);
+  if (rc) return rc;
+  if (hex_elastic(c)) {
+    hipFree(c->mat_dev_f);
+    c->mat_dev_f = nullptr;
+    std::vector<float> tf(tab.begin(), tab.end());
+    HIPCHK(c, hipMalloc((void**)&c->mat_dev_f, tf.size() * sizeof(float)));
+    HIPCHK(c, hipMemcpy(c->mat_dev_f, tf.data(), tf.size() * sizeof(float),
+                        hipMemcpyHostToDevice));
+  }
+  c->symbol_ok = c->rhs_ok = c->solved = false;
+  return FH_OK;
+}
+
+int fh_set_conductivity_field(fh_ctx* c, const double* k_dev) {
+  if (!c) return FH_EINVAL;
+  hipSetDevice(c->device);
+  if (!c->has_grid) return fail(c, FH_ESTATE, "fh_set_grid not called");
+  if (c->problem != FH_SCALAR) return fail(c, FH_EINVAL, "conductivity field needs FH_SCALAR");
+  if (!k_dev) return fail(c, FH_EINVAL, "null field");
+  c->kfield_dev = k_dev;
+  c->phase_dev = nullptr;
+  c->mat_kind = 2;
+  c->nphase = 0;
+  std::vector<double> I((size_t)c->g.dim * c->g.dim, 0.0);
+  for (int i = 0; i < c->g.dim; ++i) I[i * c->g.dim + i] = 1.0;
+  c->mat = I;
+  int rc = upload(c, &c->mat_dev, &c->mat_dev_n, operator_tables(c, I.data(), 1));
+  if (rc) return rc;
+  c->symbol_ok = c->rhs_ok = c->solved = false;
+  return FH_OK;
+}
+
+int fh_set_reference(fh_ctx* c, const double* Cref) {
+  if (!c) return FH_EINVAL;
+  if (!c->has_grid) return fail(c, FH_ESTATE, "fh_set_grid not called");
+  const int m = mdim(c);
+  if (!Cref) {
+    c->cref_user = false;
+  } else {
+    std::vector<double> v(Cref, Cref + (size_t)m * m);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j)
+        if (std::fabs(v[i * m + j] - v[j * m + i]) > 1e-12 * (std::fabs(v[i * m + j]) + 1e-300))
+          return fail(c, FH_EINVAL, "Cref must be symmetric");
+    if (!cholesky_ok(v, m)) return fail(c, FH_ENOTSPD, "Cref is not positive definite");
+    c->cref_in = v;
+    c->cref_user = true;
+  }
+  c->symbol_ok = false;
+  c->solved = false;
+  return FH_OK;
+}
+
+int fh_set_load(fh_ctx* c, int nload, const double* E) {
+  if (!c) return FH_EINVAL;
+  if (!c->has_grid) return fail(c, FH_ESTATE, "fh_set_grid not called");
+  if (nload < 1 || nload > FH_MAX_LOADS || !E) return fail(c, FH_EINVAL, "bad loads");
+  const int m = mdim(c);
+  for (int i = 0; i < nload * m; ++i)
+    if (!std::isfinite(E[i])) return fail(c, FH_EINVAL, "loads must be finite");
+  c->nload = nload;
+  c->loads.assign(E, E + (size_t)nload * m);
+  c->rhs_ok = false;
+  c->solved = false;
+  return FH_OK;
+}
+
+int fh_workspace_size(fh_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return FH_EINVAL;
+  if (!c->has_grid) return fail(c, FH_ESTATE, "fh_set_grid not called");
+  *bytes = layout(c, nullptr, nullptr);
+  return FH_OK;
+}
+
+int fh_bind_workspace(fh_ctx* c, void* dev, size_t bytes) {
+  if (!c) return FH_EINVAL;
+  if (dev && ((uintptr_t)dev % 256)) return fail(c, FH_EINVAL, "workspace must be 256-byte aligned");
+  c->ws_user = dev;
+  c->ws_user_bytes = dev ? bytes : 0;
+  c->layout_ok = false;
+  c->symbol_ok = c->rhs_ok = c->solved = false;
+  return FH_OK;
+}
+
+int fh_solve(fh_ctx* c, const fh_opts* opt, fh_stats* st) {
+  if (!c) return FH_EINVAL;
+  hipSetDevice(c->device);
+  fh_opts o{1e-10, 10000, FH_FP64, 0, 0, 0.0};
+  if (opt) o = *opt;
+  if (!(o.eta > 0.0) || o.itmax < 1) return fail(c, FH_EINVAL, "bad eta/itmax");
+  if (o.precision != FH_FP64 && o.precision != FH_FP32_REFINED)
+    return fail(c, FH_EINVAL, "bad precision");
+  if (o.precision == FH_FP32_REFINED)
+    return fail(c, FH_EINVAL, "FP32 refinement not available in this build");
+  if (c->nload < 1) return fail(c, FH_ESTATE, "fh_set_load not called");
+  const int poll = o.poll > 0 ? o.poll : 16;
+  auto t0 = std::chrono::steady_clock::now();
+  c->solved = false;
+  int rc = build_symbol(c);
+  if (rc) return rc;
+  rc = build_rhs(c);
+  if (rc) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const double setup_ms = ms_since(t0);
+  auto t1 = std::chrono::steady_clock::now();
+  std::vector<fh::PcgState> hs;
+  rc = pcg64(c, c->nload, o.eta, o.itmax, poll, hs);
+  if (rc) return rc;
+  const double solve_ms = ms_since(t1);
+  auto t2 = std::chrono::steady_clock::now();
+  // homogenized tensor, energy form:
+  // C[i][j] = e_i.Cmean e_j + (-b_i.u_j - b_j.u_i + u_i.K u_j) / |Y|
+  const fh::Grid& g = c->g;
+  const long long F = (long long)g.nd * g.N;
+  const int nl = c->nload, m = mdim(c);
+  rc = apply_K(c, false, c->L.x, c->L.q, nl, F, nullptr, nullptr);
+  if (rc) return rc;
+  std::vector<double> bu((size_t)nl * nl), uKu((size_t)nl * nl);
+  double* scal = c->L.scal;
+  const int nb = 1024;
+  std::vector<double> vals;
+  for (int i = 0; i < nl; ++i)
+    for (int j = 0; j < nl; ++j) {
+      HIPCHK(c, fh::launch_dot_partials(c->L.b + i * F, c->L.x + j * F, F, c->L.dot_part, nb,
+                                        c->stream));
+      HIPCHK(c, fh::launch_sum_partials(c->L.dot_part, nb, scal, c->stream));
+      double v = 0;
+      HIPCHK(c, hipMemcpyAsync(&v, scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, fh::launch_dot_partials(c->L.x + i * F, c->L.q + j * F, F, c->L.dot_part, nb,
+                                        c->stream));
+      HIPCHK(c, fh::launch_sum_partials(c->L.dot_part, nb, scal + 1, c->stream));
+      double w = 0;
+      HIPCHK(c, hipMemcpyAsync(&w, scal + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      bu[(size_t)i * nl + j] = v;
+      uKu[(size_t)i * nl + j] = w;
+    }
+  double vol = 1.0;
+  for (int k = 0; k < g.dim; ++k) vol *= c->l[k];
+  c->chom.assign((size_t)nl * nl, 0.0);
+  for (int i = 0; i < nl; ++i)
+    for (int j = 0; j < nl; ++j) {
+      double e = 0;
+      const double* Ei = c->loads.data() + (size_t)i * m;
+      const double* Ej = c->loads.data() + (size_t)j * m;
+      for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) e += Ei[a] * c->cmean[a * m + b] * Ej[b];
+      c->chom[(size_t)i * nl + j] =
+          e + (-bu[(size_t)i * nl + j] - bu[(size_t)j * nl + i] + uKu[(size_t)i * nl + j]) / vol;
+    }
+  const double chom_ms = ms_since(t2);
+  record_history(c, hs, nl);
+  c->solved = true;
+  rc = fill_stats(c, hs, nl, st);
+  c->last.setup_ms = setup_ms;
+  c->last.solve_ms = solve_ms;
+  c->last.chom_ms = chom_ms;
+  if (st) {
+    st->setup_ms = setup_ms;
+    st->solve_ms = solve_ms;
+    st->chom_ms = chom_ms;
+  }
+  return rc;
+}
+
+int fh_get_fluctuation(fh_ctx* c, int load, double* u_dev) {
+  if (!c || !u_dev) return FH_EINVAL;
+  if (!c->solved) return fail(c, FH_ESTATE, "no solution available");
+  if (load < 0 || load >= c->nload) return fail(c, FH_EINVAL, "bad load index");
+  const long long F = (long long)c->g.nd * c->g.N;
+  HIPCHK(c, hipMemcpyAsync(u_dev, c->L.x + load * F, F * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FH_OK;
+}
+
+int fh_get_homogenized(fh_ctx* c, double* Chom) {
+  if (!c || !Chom) return FH_EINVAL;
+  if (!c->solved) return fail(c, FH_ESTATE, "no solution available");
+  std::memcpy(Chom, c->chom.data(), c->chom.size() * sizeof(double));
+  return FH_OK;
+}
+
+int fh_get_reference(fh_ctx* c, double* Cref) {
+  if (!c || !Cref) return FH_EINVAL;
+  if (!c->symbol_ok) return fail(c, FH_ESTATE, "reference not built yet");
+  std::memcpy(Cref, c->cref.data(), c->cref.size() * sizeof(double));
+  return FH_OK;
+}
+
+int fh_get_history(fh_ctx* c, int load, double* hist, int max, int* count) {
+  if (!c || !count) return FH_EINVAL;
+  if (load < 0 || load >= (int)c->history.size()) return fail(c, FH_EINVAL, "bad load index");
+  const std::vector<double>& h = c->history[load];
+  const int n = std::min((int)h.size(), max);
+  if (hist && n > 0) std::memcpy(hist, h.data(), n * sizeof(double));
+  *count = (int)h.size();
+  return FH_OK;
+}
+
+int fh_apply_operator(fh_ctx* c, const double* u_dev, double* q_dev) {
+  if (!c || !u_dev || !q_dev) return FH_EINVAL;
+  hipSetDevice(c->device);
+  int rc = check_material(c);
+  if (rc) return rc;
+  const long long F = (long long)c->g.nd * c->g.N;
+  rc = apply_K(c, false, u_dev, q_dev, 1, F, nullptr, nullptr);
+  if (rc) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FH_OK;
+}
+
+int fh_apply_preconditioner(fh_ctx* c, const double* r_dev, double* z_dev) {
+  if (!c || !r_dev || !z_dev) return FH_EINVAL;
+  hipSetDevice(c->device);
+  int rc = build_symbol(c);
+  if (rc) return rc;
+  const long long F = (long long)c->g.nd * c->g.N;
+  HIPCHK(c, fh::launch_copy(c->L.r, r_dev, F, c->stream));
+  rc = precond_fields(c, c->L.r, z_dev, 1, F);
+  if (rc) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FH_OK;
+}
+
+int fh_compute_rhs(fh_ctx* c, const double* E, double* b_dev) {
+  if (!c || !E || !b_dev) return FH_EINVAL;
+  hipSetDevice(c->device);
+  int rc = check_material(c);
+  if (rc) return rc;
+  const int m = mdim(c);
+  const int ntab = c->mat_kind == 1 ? c->nphase : 1;
+  std::vector<double> unit((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) unit[i * m + i] = 1.0;
+  std::vector<double> fe;
+  for (int t = 0; t < ntab; ++t) {
+    const double* C = c->mat_kind == 1 ? c->mat.data() + (size_t)t * m * m : unit.data();
+    std::vector<double> f = uniform_strain_force(c, C, E);
+    fe.insert(fe.end(), f.begin(), f.end());
+  }
+  double* tmp = nullptr;
+  HIPCHK(c, hipMalloc((void**)&tmp, fe.size() * sizeof(double)));
+  hipError_t e1 = hipMemcpyAsync(tmp, fe.data(), fe.size() * sizeof(double),
+                                 hipMemcpyHostToDevice, c->stream);
+  hipError_t e2 = fh::launch_rhs(c->g, c->element, c->mat_kind == 1 ? c->phase_dev : nullptr,
+                                 c->mat_kind == 2 ? c->kfield_dev : nullptr, tmp, ntab, 1, b_dev,
+                                 0, c->stream);
+  hipError_t e3 = hipStreamSynchronize(c->stream);
+  hipFree(tmp);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
+    return fail(c, FH_EDEVICE, "rhs kernel failed");
+  return FH_OK;
+}
+
+int fh_get_symbol(fh_ctx* c, double* kplus_dev) {
+  if (!c || !kplus_dev) return FH_EINVAL;
+  hipSetDevice(c->device);
+  int rc = build_symbol(c);
+  if (rc) return rc;
+  const fh::Grid& g = c->g;
+  const long long n = (long long)g.nxh * g.ny * g.nz * (g.nd * (g.nd + 1) / 2);
+  HIPCHK(c, hipMemcpyAsync(kplus_dev, c->L.kplus, n * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FH_OK;
+}
+
+int fh_solve_rhs(fh_ctx* c, const double* b_dev, double* u_dev, const fh_opts* opt,
+                 fh_stats* st) {
+  if (!c || !b_dev || !u_dev) return FH_EINVAL;
+  hipSetDevice(c->device);
+  fh_opts o{1e-10, 10000, FH_FP64, 0, 0, 0.0};
+  if (opt) o = *opt;
+  if (!(o.eta > 0.0) || o.itmax < 1) return fail(c, FH_EINVAL, "bad eta/itmax");
+  if (c->nload < 1) {
+    // a single slot is enough
+    c->nload = 1;
+    c->loads.assign(mdim(c), 0.0);
+    c->rhs_ok = false;
+  }
+  int rc = build_symbol(c);
+  if (rc) return rc;
+  const long long F = (long long)c->g.nd * c->g.N;
+  HIPCHK(c, fh::launch_copy(c->L.b, b_dev, F, c->stream));
+  c->rhs_ok = false;  // slot 0 of b now holds the caller's vector
+  c->solved = false;
+  std::vector<fh::PcgState> hs;
+  rc = pcg64(c, 1, o.eta, o.itmax, o.poll > 0 ? o.poll : 16, hs);
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(u_dev, c->L.x, F * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  record_history(c, hs, 1);
+  return fill_stats(c, hs, 1, st);
+}
+
+}  // extern "C"

@@ -1,0 +1,626 @@
+// Real 3D FFT passes, per-frequency block solve and symbol assembly.
+//
+// Paper Sec. 4.2 (eq. M_inverse): the reference stiffness is block-circulant,
+// so F K_ab F^H is diagonal and M^+ r = F^H K^+ F r; Sec. 5.1: F and F^H are
+// applied with FFTs; Sec. 5.2-5.3 (Alg. 2, eq. block_inversion): diag K^_ab
+// is the FFT of the impulse response of Kref and every frequency block is
+// inverted (pseudo-inverted at the zero frequency).
+//
+// Transform convention: forward X(k) = sum_j x(j) exp(-2 pi i jk/n)
+// (unnormalised); the inverse carries no 1/N here -- the 1/N is folded into
+// the stored K^+ (kplus = K^+ / N).
+//
+// Layouts (per load case, per component c < nd):
+//   real field        r[c][z][y][x]
+//   A (after x pass)  A[c][z][kx][y]     kx < nxh = nx/2+1, y contiguous
+//   B (after y pass)  B[c][kx][ky][z]    z contiguous
+// Every pass reads whole lines that are contiguous in memory and writes
+// transposed tiles of 16 lines, so each global access is a contiguous run of
+// at least 16 complex values.  The z pass works in place on B and, in solve
+// mode, applies K^+ per frequency between its forward and inverse FFTs and
+// accumulates the Parseval form of r.z.
+//
+// Each block transforms a batch of lines held in LDS with a Stockham
+// autosort FFT (mixed radix 4/2/3/5, ping-pong buffers, one barrier per
+// stage); twiddles come from a per-length table staged in LDS.
+#include "fh_internal.h"
+
+namespace fh {
+
+constexpr int kRows = 16;   // rows per block in x passes (8 complex lines)
+constexpr int kZB = 16;     // lines per block in y passes
+constexpr int kThreads = 256;
+
+template <typename T>
+__device__ __forceinline__ cplx<T> conjg(cplx<T> a) { return {a.re, -a.im}; }
+// i*a for sign s: s*i*a
+template <typename T>
+__device__ __forceinline__ cplx<T> muli(cplx<T> a, int s) {
+  return s > 0 ? cplx<T>{-a.im, a.re} : cplx<T>{a.im, -a.re};
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dft_small(cplx<T>* x, int s) {
+  if constexpr (R == 2) {
+    cplx<T> a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  } else if constexpr (R == 4) {
+    cplx<T> a0 = cadd(x[0], x[2]), a1 = csub(x[0], x[2]);
+    cplx<T> b0 = cadd(x[1], x[3]), b1 = muli(csub(x[1], x[3]), s);
+    x[0] = cadd(a0, b0);
+    x[2] = csub(a0, b0);
+    x[1] = cadd(a1, b1);
+    x[3] = csub(a1, b1);
+  } else if constexpr (R == 3) {
+    const T h = T(0.86602540378443864676372317075294);  // sqrt(3)/2
+    cplx<T> t1 = cadd(x[1], x[2]), t2 = csub(x[1], x[2]);
+    cplx<T> a = {x[0].re - T(0.5) * t1.re, x[0].im - T(0.5) * t1.im};
+    cplx<T> b = muli(cplx<T>{h * t2.re, h * t2.im}, s);
+    x[0] = cadd(x[0], t1);
+    x[1] = cadd(a, b);
+    x[2] = csub(a, b);
+  } else if constexpr (R == 5) {
+    const T c1 = T(0.30901699437494742410229341718282);   // cos(2pi/5)
+    const T c2 = T(-0.80901699437494742410229341718282);  // cos(4pi/5)
+    const T s1 = T(0.95105651629515357211643933337938);   // sin(2pi/5)
+    const T s2 = T(0.58778525229247312916870595463907);   // sin(4pi/5)
+    cplx<T> t1 = cadd(x[1], x[4]), t2 = cadd(x[2], x[3]);
+    cplx<T> t3 = csub(x[1], x[4]), t4 = csub(x[2], x[3]);
+    cplx<T> a1 = {x[0].re + c1 * t1.re + c2 * t2.re, x[0].im + c1 * t1.im + c2 * t2.im};
+    cplx<T> a2 = {x[0].re + c2 * t1.re + c1 * t2.re, x[0].im + c2 * t1.im + c1 * t2.im};
+    cplx<T> b1 = muli(cplx<T>{s1 * t3.re + s2 * t4.re, s1 * t3.im + s2 * t4.im}, s);
+    cplx<T> b2 = muli(cplx<T>{s2 * t3.re - s1 * t4.re, s2 * t3.im - s1 * t4.im}, s);
+    x[0] = cadd(x[0], cadd(t1, t2));
+    x[1] = cadd(a1, b1);
+    x[4] = csub(a1, b1);
+    x[2] = cadd(a2, b2);
+    x[3] = csub(a2, b2);
+  }
+}
+
+// One Stockham stage on `nlines` lines of length n (line stride n) from `in`
+// to `out`; L = product of the radices of the earlier stages.
+template <typename T, int R>
+__device__ __forceinline__ void stockham_stage(const cplx<T>* in, cplx<T>* out, int n,
+                                               int nlines, int L, const cplx<T>* tw,
+                                               int sign) {
+  const int m = n / R;
+  const int items = nlines * m;
+  const int twstep = n / (L * R);
+  for (int it = threadIdx.x; it < items; it += blockDim.x) {
+    const int line = it / m;
+    const int j = it - line * m;
+    const int k = j % L;
+    const cplx<T>* src = in + (size_t)line * n;
+    cplx<T> v[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+      cplx<T> a = src[j + t * m];
+      if (t > 0) {
+        // t*k < R*L, so the index stays below n
+        cplx<T> w = tw[t * k * twstep];
+        if (sign > 0) w.im = -w.im;
+        a = cmul(a, w);
+      }
+      v[t] = a;
+    }
+    dft_small<T, R>(v, sign);
+    cplx<T>* dst = out + (size_t)line * n + (j / L) * L * R + k;
+#pragma unroll
+    for (int t = 0; t < R; ++t) dst[t * L] = v[t];
+  }
+}
+
+// Runs all stages; returns the buffer holding the result.  Caller must have
+// synchronised after filling `a`; returns after a final barrier.
+template <typename T>
+__device__ cplx<T>* fft_lines(cplx<T>* a, cplx<T>* b, const AxisPlan& plan, int nlines,
+                              const cplx<T>* tw, int sign) {
+  int L = 1;
+  const int n = plan.n;
+  for (int st = 0; st < plan.nstage; ++st) {
+    const int R = (plan.code >> (4 * st)) & 15u;
+    switch (R) {
+      case 4: stockham_stage<T, 4>(a, b, n, nlines, L, tw, sign); break;
+      case 2: stockham_stage<T, 2>(a, b, n, nlines, L, tw, sign); break;
+      case 3: stockham_stage<T, 3>(a, b, n, nlines, L, tw, sign); break;
+      default: stockham_stage<T, 5>(a, b, n, nlines, L, tw, sign); break;
+    }
+    L *= R;
+    __syncthreads();
+    cplx<T>* t = a;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+template <typename T>
+__device__ __forceinline__ void load_twiddles(cplx<T>* tw, const cplx<double>* g, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = {T(g[i].re), T(g[i].im)};
+}
+
+__device__ __forceinline__ int load_status(const PcgState* st, int ld) {
+  return st ? st[ld].status : ST_ACTIVE;
+}
+
+// Deterministic block sum (wave shuffles, then waves in order).
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) s += sh[w];
+  }
+  return s;
+}
+
+// ------------------------------------------------------------- x forward
+// grid (ceil(ny/16), nz, nload*nd).  Optionally r -= alpha q first.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_xfwd(Grid g, AxisPlan px, const cplx<double>* twx,
+                                                  int mode, T* r, long long rstride, const T* q,
+                                                  long long qstride, cplx<T>* A,
+                                                  long long sstride, const PcgState* st) {
+  const int ld = blockIdx.z / g.nd, c = blockIdx.z % g.nd;
+  if (load_status(st, ld) != ST_ACTIVE) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nx = g.nx, ny = g.ny, nxh = g.nxh;
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* a = tw + nx;
+  cplx<T>* b = a + (kRows / 2) * nx;
+  load_twiddles(tw, twx, nx);
+  const int y0 = blockIdx.x * kRows, z = blockIdx.y;
+  const long long rbase = (long long)ld * rstride + ((long long)c * g.nz + z) * ny * nx;
+  const T alpha = (mode == XF_UPDATE_R) ? T(st[ld].alpha) : T(0);
+  for (int idx = threadIdx.x; idx < kRows * nx; idx += blockDim.x) {
+    const int row = idx / nx, x = idx - row * nx, y = y0 + row;
+    T v = T(0);
+    if (y < ny) {
+      const long long o = rbase + (long long)y * nx + x;
+      v = r[o];
+      if (mode == XF_UPDATE_R) {
+        v -= alpha * q[(long long)ld * qstride + ((long long)c * g.nz + z) * ny * nx +
+                       (long long)y * nx + x];
+        r[o] = v;
+      }
+    }
+    cplx<T>& d = a[(row >> 1) * nx + x];
+    if (row & 1) d.im = v; else d.re = v;
+  }
+  __syncthreads();
+  cplx<T>* res = fft_lines(a, b, px, kRows / 2, tw, -1);
+  const long long abase = (long long)ld * sstride + ((long long)c * g.nz + z) * nxh * ny;
+  for (int idx = threadIdx.x; idx < kRows * nxh; idx += blockDim.x) {
+    const int yl = idx % kRows, kx = idx / kRows, y = y0 + yl;
+    if (y >= ny) continue;
+    const cplx<T>* line = res + (yl >> 1) * nx;
+    const cplx<T> ck = line[kx];
+    const cplx<T> cn = line[(nx - kx) % nx];
+    cplx<T> X;
+    if ((yl & 1) == 0) {
+      X = {T(0.5) * (ck.re + cn.re), T(0.5) * (ck.im - cn.im)};
+    } else {
+      // (ck - conj(cn)) / (2i)
+      const T dr = ck.re - cn.re, di = ck.im + cn.im;
+      X = {T(0.5) * di, -T(0.5) * dr};
+    }
+    A[abase + (long long)kx * ny + y] = X;
+  }
+}
+
+// ------------------------------------------------------------- y forward
+// grid (ceil(nz/16), nxh, nload*nd)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_yfwd(Grid g, AxisPlan py, const cplx<double>* twy,
+                                                  const cplx<T>* A, cplx<T>* B,
+                                                  long long sstride, const PcgState* st) {
+  const int ld = blockIdx.z / g.nd, c = blockIdx.z % g.nd;
+  if (load_status(st, ld) != ST_ACTIVE) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int ny = g.ny, nz = g.nz, nxh = g.nxh;
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* a = tw + ny;
+  cplx<T>* b = a + kZB * ny;
+  load_twiddles(tw, twy, ny);
+  const int z0 = blockIdx.x * kZB, kx = blockIdx.y;
+  const long long base = (long long)ld * sstride;
+  for (int idx = threadIdx.x; idx < kZB * ny; idx += blockDim.x) {
+    const int zl = idx / ny, y = idx - zl * ny, z = z0 + zl;
+    cplx<T> v = {T(0), T(0)};
+    if (z < nz) v = A[base + (((long long)c * nz + z) * nxh + kx) * ny + y];
+    a[idx] = v;
+  }
+  __syncthreads();
+  cplx<T>* res = fft_lines(a, b, py, kZB, tw, -1);
+  const long long obase = base + ((long long)c * nxh + kx) * (long long)ny * nz;
+  for (int idx = threadIdx.x; idx < kZB * ny; idx += blockDim.x) {
+    const int zl = idx % kZB, ky = idx / kZB, z = z0 + zl;
+    if (z < nz) B[obase + (long long)ky * nz + z] = res[zl * ny + ky];
+  }
+}
+
+// ------------------------------------------------ z forward (+ solve + inverse)
+// grid (ceil(ny/kyb), nxh, nload).  Dynamic LDS: tw[nz], a/b[nd*kyb*nz].
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_zpass(Grid g, AxisPlan pz, const cplx<double>* twz,
+                                                   int mode, int kyb, cplx<T>* B,
+                                                   long long sstride, const T* kplus,
+                                                   const PcgState* st, double* rz_part) {
+  const int ld = blockIdx.z;
+  __shared__ double red[16];
+  const int active = load_status(st, ld) == ST_ACTIVE;
+  if (!active) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int ny = g.ny, nz = g.nz, nxh = g.nxh, nd = g.nd;
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* a = tw + nz;
+  cplx<T>* b = a + nd * kyb * nz;
+  load_twiddles(tw, twz, nz);
+  const int ky0 = blockIdx.x * kyb, kx = blockIdx.y;
+  const long long cstride = (long long)nxh * ny * nz;
+  const long long base = (long long)ld * sstride + (long long)kx * ny * nz;
+  const int per = kyb * nz;
+  for (int idx = threadIdx.x; idx < nd * per; idx += blockDim.x) {
+    const int c = idx / per, rem = idx - c * per, kyl = rem / nz, z = rem - kyl * nz;
+    const int ky = ky0 + kyl;
+    cplx<T> v = {T(0), T(0)};
+    if (ky < ny) v = B[base + c * cstride + (long long)ky * nz + z];
+    a[idx] = v;
+  }
+  __syncthreads();
+  cplx<T>* res = fft_lines(a, b, pz, nd * kyb, tw, -1);
+  cplx<T>* other = (res == a) ? b : a;
+  double part = 0.0;
+  if (mode == Z_SOLVE) {
+    const long long nfreq = (long long)nxh * ny * nz;
+    const double wgt = (kx == 0 || (2 * kx == g.nx)) ? 1.0 : 2.0;
+    for (int idx = threadIdx.x; idx < per; idx += blockDim.x) {
+      const int kyl = idx / nz, kz = idx - kyl * nz, ky = ky0 + kyl;
+      if (ky >= ny) continue;
+      const long long f = ((long long)kx * ny + ky) * nz + kz;
+      if (nd == 3) {
+        const T k00 = kplus[f], k11 = kplus[nfreq + f], k22 = kplus[2 * nfreq + f];
+        const T k12 = kplus[3 * nfreq + f], k02 = kplus[4 * nfreq + f],
+                k01 = kplus[5 * nfreq + f];
+        const cplx<T> r0 = res[idx], r1 = res[per + idx], r2 = res[2 * per + idx];
+        cplx<T> z0v = {k00 * r0.re + k01 * r1.re + k02 * r2.re,
+                       k00 * r0.im + k01 * r1.im + k02 * r2.im};
+        cplx<T> z1v = {k01 * r0.re + k11 * r1.re + k12 * r2.re,
+                       k01 * r0.im + k11 * r1.im + k12 * r2.im};
+        cplx<T> z2v = {k02 * r0.re + k12 * r1.re + k22 * r2.re,
+                       k02 * r0.im + k12 * r1.im + k22 * r2.im};
+        part += wgt * ((double)r0.re * z0v.re + (double)r0.im * z0v.im +
+                       (double)r1.re * z1v.re + (double)r1.im * z1v.im +
+                       (double)r2.re * z2v.re + (double)r2.im * z2v.im);
+        res[idx] = z0v;
+        res[per + idx] = z1v;
+        res[2 * per + idx] = z2v;
+      } else if (nd == 2) {
+        const T k00 = kplus[f], k11 = kplus[nfreq + f], k01 = kplus[2 * nfreq + f];
+        const cplx<T> r0 = res[idx], r1 = res[per + idx];
+        cplx<T> z0v = {k00 * r0.re + k01 * r1.re, k00 * r0.im + k01 * r1.im};
+        cplx<T> z1v = {k01 * r0.re + k11 * r1.re, k01 * r0.im + k11 * r1.im};
+        part += wgt * ((double)r0.re * z0v.re + (double)r0.im * z0v.im +
+                       (double)r1.re * z1v.re + (double)r1.im * z1v.im);
+        res[idx] = z0v;
+        res[per + idx] = z1v;
+      } else {
+        const T k00 = kplus[f];
+        const cplx<T> r0 = res[idx];
+        cplx<T> z0v = {k00 * r0.re, k00 * r0.im};
+        part += wgt * ((double)r0.re * z0v.re + (double)r0.im * z0v.im);
+        res[idx] = z0v;
+      }
+    }
+    __syncthreads();
+    res = fft_lines(res, other, pz, nd * kyb, tw, +1);
+  }
+  for (int idx = threadIdx.x; idx < nd * per; idx += blockDim.x) {
+    const int c = idx / per, rem = idx - c * per, kyl = rem / nz, z = rem - kyl * nz;
+    const int ky = ky0 + kyl;
+    if (ky < ny) B[base + c * cstride + (long long)ky * nz + z] = res[idx];
+  }
+  if (mode == Z_SOLVE && rz_part) {
+    const double s = block_sum(part, red);
+    if (threadIdx.x == 0) {
+      const long long nb = (long long)gridDim.x * gridDim.y;
+      rz_part[(long long)ld * nb + (long long)blockIdx.y * gridDim.x + blockIdx.x] = s;
+    }
+  }
+}
+
+// ------------------------------------------------------------- y inverse
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_yinv(Grid g, AxisPlan py, const cplx<double>* twy,
+                                                  const cplx<T>* B, cplx<T>* A,
+                                                  long long sstride, const PcgState* st) {
+  const int ld = blockIdx.z / g.nd, c = blockIdx.z % g.nd;
+  if (load_status(st, ld) != ST_ACTIVE) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int ny = g.ny, nz = g.nz, nxh = g.nxh;
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* a = tw + ny;
+  cplx<T>* b = a + kZB * ny;
+  load_twiddles(tw, twy, ny);
+  const int z0 = blockIdx.x * kZB, kx = blockIdx.y;
+  const long long base = (long long)ld * sstride;
+  const long long ibase = base + ((long long)c * nxh + kx) * (long long)ny * nz;
+  for (int idx = threadIdx.x; idx < kZB * ny; idx += blockDim.x) {
+    const int zl = idx % kZB, ky = idx / kZB, z = z0 + zl;
+    cplx<T> v = {T(0), T(0)};
+    if (z < nz) v = B[ibase + (long long)ky * nz + z];
+    a[zl * ny + ky] = v;
+  }
+  __syncthreads();
+  cplx<T>* res = fft_lines(a, b, py, kZB, tw, +1);
+  for (int idx = threadIdx.x; idx < kZB * ny; idx += blockDim.x) {
+    const int zl = idx / ny, y = idx - zl * ny, z = z0 + zl;
+    if (z < nz) A[base + (((long long)c * nz + z) * nxh + kx) * ny + y] = res[idx];
+  }
+}
+
+// ------------------------------------------------------------- x inverse
+// grid (ceil(ny/16), nz, nload*nd).  LDS: tw[nx], a[8 nx], b[8 nx + 16]
+// (b first holds the 16 x nxh input tile).
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cplx<double>* twx,
+                                                  int mode, const cplx<T>* A, long long sstride,
+                                                  T* out, T* x, T* p, long long fstride,
+                                                  const PcgState* st) {
+  const int ld = blockIdx.z / g.nd, c = blockIdx.z % g.nd;
+  const int status = load_status(st, ld);
+  const int nx = g.nx, ny = g.ny, nxh = g.nxh;
+  const int y0 = blockIdx.x * kRows, z = blockIdx.y;
+  const long long fbase = (long long)ld * fstride + ((long long)c * g.nz + z) * ny * nx;
+  if (mode == XI_PCG && (status == ST_CONVERGED_PENDING || status == ST_MAXIT_PENDING)) {
+    const T alpha = T(st[ld].alpha);
+    for (int idx = threadIdx.x; idx < kRows * nx; idx += blockDim.x) {
+      const int row = idx / nx, xx = idx - row * nx, y = y0 + row;
+      if (y < ny) {
+        const long long o = fbase + (long long)y * nx + xx;
+        x[o] += alpha * p[o];
+      }
+    }
+    return;
+  }
+  if (status != ST_ACTIVE) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* a = tw + nx;
+  cplx<T>* b = a + (kRows / 2) * nx;
+  cplx<T>* S = b;  // 16 x nxh raw tile
+  load_twiddles(tw, twx, nx);
+  const long long abase = (long long)ld * sstride + ((long long)c * g.nz + z) * nxh * ny;
+  for (int idx = threadIdx.x; idx < kRows * nxh; idx += blockDim.x) {
+    const int yl = idx % kRows, kx = idx / kRows, y = y0 + yl;
+    cplx<T> v = {T(0), T(0)};
+    if (y < ny) v = A[abase + (long long)kx * ny + y];
+    S[yl * nxh + kx] = v;
+  }
+  __syncthreads();
+  const int half = nx / 2;
+  for (int idx = threadIdx.x; idx < (kRows / 2) * nx; idx += blockDim.x) {
+    const int j = idx / nx, k = idx - j * nx;
+    cplx<T> xa, xb;
+    if (k <= half) {
+      xa = S[(2 * j) * nxh + k];
+      xb = S[(2 * j + 1) * nxh + k];
+      if (k == 0 || k == half) {
+        xa.im = T(0);
+        xb.im = T(0);
+      }
+    } else {
+      xa = conjg(S[(2 * j) * nxh + (nx - k)]);
+      xb = conjg(S[(2 * j + 1) * nxh + (nx - k)]);
+    }
+    a[idx] = {xa.re - xb.im, xa.im + xb.re};
+  }
+  __syncthreads();
+  cplx<T>* res = fft_lines(a, b, px, kRows / 2, tw, +1);
+  const T alpha = (mode == XI_PCG) ? T(st[ld].alpha) : T(0);
+  const T beta = (mode == XI_PCG) ? T(st[ld].beta) : T(0);
+  for (int idx = threadIdx.x; idx < kRows * nx; idx += blockDim.x) {
+    const int row = idx / nx, xx = idx - row * nx, y = y0 + row;
+    if (y >= ny) continue;
+    const cplx<T> v = res[(row >> 1) * nx + xx];
+    const T zv = (row & 1) ? v.im : v.re;
+    const long long o = fbase + (long long)y * nx + xx;
+    if (mode == XI_PLAIN) {
+      out[o] = zv;
+    } else if (mode == XI_INIT_P) {
+      p[o] = zv;
+    } else {
+      const T pv = p[o];
+      x[o] += alpha * pv;
+      p[o] = zv + beta * pv;
+    }
+  }
+}
+
+// ------------------------------------------------------------- symbol
+// K^+(xi)/N from the spectra of the nd impulse responses (Alg. 2).  The
+// symbol of a centrosymmetric one-node stencil is real and symmetric: the
+// real part is taken and symmetrised.  Zero frequency: the whole block is
+// the zero matrix (rigid-body modes), its pseudo-inverse is zero.
+__global__ void k_symbol(Grid g, const cplx<double>* spec, long long sstride, double* kplus,
+                         int* bad) {
+  const long long nfreq = (long long)g.nxh * g.ny * g.nz;
+  const long long cstride = nfreq;
+  const double invN = 1.0 / (double)g.N;
+  for (long long f = blockIdx.x * (long long)blockDim.x + threadIdx.x; f < nfreq;
+       f += (long long)gridDim.x * blockDim.x) {
+    auto Kab = [&](int al, int be) -> double {
+      return spec[be * sstride + al * cstride + f].re;
+    };
+    if (g.nd == 3) {
+      double a = Kab(0, 0), bb = Kab(1, 1), c = Kab(2, 2);
+      double d = 0.5 * (Kab(1, 2) + Kab(2, 1));
+      double e = 0.5 * (Kab(0, 2) + Kab(2, 0));
+      double ff = 0.5 * (Kab(0, 1) + Kab(1, 0));
+      double out[6] = {0, 0, 0, 0, 0, 0};
+      if (f != 0) {
+        const double c00 = bb * c - d * d, c11 = a * c - e * e, c22 = a * bb - ff * ff;
+        const double c12 = e * ff - a * d, c02 = ff * d - bb * e, c01 = d * e - ff * c;
+        const double det = a * c00 + ff * c01 + e * c02;
+        if (!(a > 0.0 && c22 > 0.0 && det > 0.0)) atomicOr(bad, 1);
+        const double s = invN / det;
+        out[0] = c00 * s; out[1] = c11 * s; out[2] = c22 * s;
+        out[3] = c12 * s; out[4] = c02 * s; out[5] = c01 * s;
+      }
+      for (int k = 0; k < 6; ++k) kplus[k * nfreq + f] = out[k];
+    } else if (g.nd == 2) {
+      double a = Kab(0, 0), bb = Kab(1, 1), ff = 0.5 * (Kab(0, 1) + Kab(1, 0));
+      double out[3] = {0, 0, 0};
+      if (f != 0) {
+        const double det = a * bb - ff * ff;
+        if (!(a > 0.0 && det > 0.0)) atomicOr(bad, 1);
+        const double s = invN / det;
+        out[0] = bb * s; out[1] = a * s; out[2] = -ff * s;
+      }
+      for (int k = 0; k < 3; ++k) kplus[k * nfreq + f] = out[k];
+    } else {
+      double a = Kab(0, 0);
+      double out = 0.0;
+      if (f != 0) {
+        if (!(a > 0.0)) atomicOr(bad, 1);
+        out = invN / a;
+      }
+      kplus[f] = out;
+    }
+  }
+}
+
+__global__ void k_cast_symbol(long long n, const double* src, float* dst) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+// ------------------------------------------------------------ launchers
+template <typename T>
+hipError_t launch_xfwd(const Grid& g, const AxisPlan& px, const cplx<double>* twx, int mode,
+                       T* r, long long rstride, const T* q, long long qstride, cplx<T>* A,
+                       long long sstride, int nload, const PcgState* st, hipStream_t s) {
+  dim3 grid((g.ny + kRows - 1) / kRows, g.nz, nload * g.nd);
+  size_t lds = sizeof(cplx<T>) * (size_t)(g.nx + kRows * g.nx);
+  if (lds > 65536)
+    hipFuncSetAttribute((const void*)k_xfwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+  hipLaunchKernelGGL(k_xfwd<T>, grid, dim3(kThreads), lds, s, g, px, twx, mode, r, rstride, q,
+                     qstride, A, sstride, st);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_yfwd(const Grid& g, const AxisPlan& py, const cplx<double>* twy,
+                       const cplx<T>* A, cplx<T>* B, long long sstride, int nload,
+                       const PcgState* st, hipStream_t s) {
+  dim3 grid((g.nz + kZB - 1) / kZB, g.nxh, nload * g.nd);
+  size_t lds = sizeof(cplx<T>) * (size_t)(g.ny + 2 * kZB * g.ny);
+  if (lds > 65536)
+    hipFuncSetAttribute((const void*)k_yfwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+  hipLaunchKernelGGL(k_yfwd<T>, grid, dim3(kThreads), lds, s, g, py, twy, A, B, sstride, st);
+  return hipGetLastError();
+}
+
+template <typename T>
+static int zpass_kyb(const Grid& g) {
+  const size_t budget = 48 * 1024;
+  size_t per = 2 * (size_t)g.nd * g.nz * sizeof(cplx<T>);
+  int kyb = (int)(budget / per);
+  if (kyb < 1) kyb = 1;
+  if (kyb > 16) kyb = 16;
+  if (kyb > g.ny) kyb = g.ny;
+  return kyb;
+}
+
+template <typename T>
+int zpass_nblocks(const Grid& g) {
+  const int kyb = zpass_kyb<T>(g);
+  return ((g.ny + kyb - 1) / kyb) * g.nxh;
+}
+template int zpass_nblocks<double>(const Grid&);
+template int zpass_nblocks<float>(const Grid&);
+
+template <typename T>
+hipError_t launch_zpass(const Grid& g, const AxisPlan& pz, const cplx<double>* twz, int mode,
+                        cplx<T>* B, long long sstride, const T* kplus, int nload,
+                        const PcgState* st, double* rz_part, int* nblocks_out, hipStream_t s) {
+  const int kyb = zpass_kyb<T>(g);
+  dim3 grid((g.ny + kyb - 1) / kyb, g.nxh, nload);
+  if (nblocks_out) *nblocks_out = grid.x * grid.y;
+  size_t lds = sizeof(cplx<T>) * (size_t)(g.nz + 2 * g.nd * kyb * g.nz);
+  hipLaunchKernelGGL(k_zpass<T>, grid, dim3(kThreads), lds, s, g, pz, twz, mode, kyb, B, sstride,
+                     kplus, st, rz_part);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_yinv(const Grid& g, const AxisPlan& py, const cplx<double>* twy,
+                       const cplx<T>* B, cplx<T>* A, long long sstride, int nload,
+                       const PcgState* st, hipStream_t s) {
+  dim3 grid((g.nz + kZB - 1) / kZB, g.nxh, nload * g.nd);
+  size_t lds = sizeof(cplx<T>) * (size_t)(g.ny + 2 * kZB * g.ny);
+  if (lds > 65536)
+    hipFuncSetAttribute((const void*)k_yinv<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+  hipLaunchKernelGGL(k_yinv<T>, grid, dim3(kThreads), lds, s, g, py, twy, B, A, sstride, st);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xinv(const Grid& g, const AxisPlan& px, const cplx<double>* twx, int mode,
+                       const cplx<T>* A, long long sstride, T* out, T* x, T* p,
+                       long long fstride, int nload, const PcgState* st, hipStream_t s) {
+  dim3 grid((g.ny + kRows - 1) / kRows, g.nz, nload * g.nd);
+  size_t lds = sizeof(cplx<T>) * (size_t)(g.nx + kRows * g.nx + 16);
+  if (lds > 65536)
+    hipFuncSetAttribute((const void*)k_xinv<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+  hipLaunchKernelGGL(k_xinv<T>, grid, dim3(kThreads), lds, s, g, px, twx, mode, A, sstride, out,
+                     x, p, fstride, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_symbol(const Grid& g, const cplx<double>* spec, long long sstride,
+                         double* kplus, int* bad, hipStream_t s) {
+  long long nfreq = (long long)g.nxh * g.ny * g.nz;
+  int blocks = (int)((nfreq + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_symbol, dim3(blocks), dim3(256), 0, s, g, spec, sstride, kplus, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_symbol(long long count, const double* src, float* dst, hipStream_t s) {
+  int blocks = (int)((count + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_cast_symbol, dim3(blocks), dim3(256), 0, s, count, src, dst);
+  return hipGetLastError();
+}
+
+#define FH_INST(T)                                                                              \
+  template hipError_t launch_xfwd<T>(const Grid&, const AxisPlan&, const cplx<double>*, int,  \
+                                     T*, long long, const T*, long long, cplx<T>*, long long,  \
+                                     int, const PcgState*, hipStream_t);                       \
+  template hipError_t launch_yfwd<T>(const Grid&, const AxisPlan&, const cplx<double>*,       \
+                                     const cplx<T>*, cplx<T>*, long long, int,                 \
+                                     const PcgState*, hipStream_t);                            \
+  template hipError_t launch_zpass<T>(const Grid&, const AxisPlan&, const cplx<double>*, int, \
+                                      cplx<T>*, long long, const T*, int, const PcgState*,     \
+                                      double*, int*, hipStream_t);                             \
+  template hipError_t launch_yinv<T>(const Grid&, const AxisPlan&, const cplx<double>*,       \
+                                     const cplx<T>*, cplx<T>*, long long, int,                 \
+                                     const PcgState*, hipStream_t);                            \
+  template hipError_t launch_xinv<T>(const Grid&, const AxisPlan&, const cplx<double>*, int,  \
+                                     const cplx<T>*, long long, T*, T*, T*, long long, int,    \
+                                     const PcgState*, hipStream_t);
+FH_INST(double)
+FH_INST(float)
+
+}  // namespace fh

@@ -1,0 +1,148 @@
+// Internal declarations shared by the HIP translation units of libfh.
+// Device code targets gfx950 (CDNA4): 64-wide wavefronts, 160 KB LDS per
+// workgroup, FP64 vector ALU.  Nothing here is part of the public C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace fh {
+
+// ---------------------------------------------------------------- PCG state
+// Per load case, device resident.  Kernels read alpha/beta/status from here so
+// that no host round trip is needed inside an iteration.
+enum : int {
+  ST_ACTIVE = 0,
+  ST_CONVERGED = 1,
+  ST_MAXIT = 2,
+  ST_BREAKDOWN = 3,
+  ST_CONVERGED_PENDING = 4,  // converged this iteration, x update still due
+  ST_MAXIT_PENDING = 5,
+};
+
+struct PcgState {
+  double rho, rho0, alpha, beta, eta2, last;
+  int iter, status, itmax, pad;
+};
+
+template <typename T>
+struct cplx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.re - b.re, a.im - b.im}; }
+
+// -------------------------------------------------------------- geometry
+struct Grid {
+  int nx, ny, nz;      // nz = 1 in 2D
+  int dim;             // 2 or 3
+  int nd;              // dofs per node (d or 1)
+  int nxh;             // nx/2 + 1
+  long long N;         // nx*ny*nz
+  double h[3];         // grid spacing
+};
+
+// FFT plan for one axis length: radix of stage i (applied first to last) in
+// bits 4i..4i+3 of `code` (a packed word keeps the plan in scalar registers).
+struct AxisPlan {
+  int n;
+  int nstage;
+  unsigned code;
+};
+
+// ------------------------------------------------------ kernel launchers
+// All launchers enqueue on `s` and return hipError_t of the launch.
+
+// Operator q = K u (eq. lin_system), element-wise constant materials.
+//   elastic hex8: mat = nphase x 36 (Mandel, pre-multiplied by the voxel
+//   volume); partial energies u.Ku per block go to pq_part (may be null).
+template <typename T>
+hipError_t launch_kop_hex8_elastic(const Grid& g, const T* u, T* q, const uint8_t* phase,
+                                   const T* mat, int nload, long long ustride, long long qstride,
+                                   const PcgState* st, double* pq_part, int* nblocks_out,
+                                   hipStream_t s);
+// node-centric generic operator with per-phase element matrices (2D
+// elements, 3D scalar hex8): ke = nphase x (nc*nd)^2, or a unit element
+// matrix scaled by a per-voxel field kfield.
+template <typename T>
+hipError_t launch_kop_generic(const Grid& g, int elem, const T* u, T* q, const uint8_t* phase,
+                              const T* kfield, const T* ke, int nload, long long ustride,
+                              long long qstride, const PcgState* st, double* pq_part,
+                              int* nblocks_out, hipStream_t s);
+// b = -D^T W C e: fe = nphase x nload x (nc*nd) element forces of the
+// uniform strain, or unit forces scaled by kfield.
+hipError_t launch_rhs(const Grid& g, int elem, const uint8_t* phase, const double* kfield,
+                      const double* fe, int nphase_tables, int nload, double* b,
+                      long long bstride, hipStream_t s);
+
+// FFT passes (layouts in fft.hip).  modes below.
+enum XfwdMode { XF_PLAIN = 0, XF_UPDATE_R = 1 };
+enum XinvMode { XI_PLAIN = 0, XI_INIT_P = 1, XI_PCG = 2 };
+enum ZMode { Z_FORWARD_ONLY = 0, Z_SOLVE = 1 };
+
+template <typename T>
+hipError_t launch_xfwd(const Grid& g, const AxisPlan& px, const cplx<double>* twx, int mode,
+                       T* r, long long rstride, const T* q, long long qstride, cplx<T>* A,
+                       long long sstride, int nload, const PcgState* st, hipStream_t s);
+template <typename T>
+hipError_t launch_yfwd(const Grid& g, const AxisPlan& py, const cplx<double>* twy,
+                       const cplx<T>* A, cplx<T>* B, long long sstride, int nload,
+                       const PcgState* st, hipStream_t s);
+template <typename T>
+hipError_t launch_zpass(const Grid& g, const AxisPlan& pz, const cplx<double>* twz, int mode,
+                        cplx<T>* B, long long sstride, const T* kplus, int nload,
+                        const PcgState* st, double* rz_part, int* nblocks_out, hipStream_t s);
+template <typename T>
+hipError_t launch_yinv(const Grid& g, const AxisPlan& py, const cplx<double>* twy,
+                       const cplx<T>* B, cplx<T>* A, long long sstride, int nload,
+                       const PcgState* st, hipStream_t s);
+template <typename T>
+hipError_t launch_xinv(const Grid& g, const AxisPlan& px, const cplx<double>* twx, int mode,
+                       const cplx<T>* A, long long sstride, T* out, T* x, T* p,
+                       long long fstride, int nload, const PcgState* st, hipStream_t s);
+
+// Symbol K^+ (Alg. 2 + eq. block_inversion) from the forward spectra of the
+// impulse responses: spec[beta] = spectrum of Kref i^beta (B layout).
+hipError_t launch_symbol(const Grid& g, const cplx<double>* spec, long long sstride,
+                         double* kplus, int* bad_flag, hipStream_t s);
+hipError_t launch_cast_symbol(long long count, const double* src, float* dst, hipStream_t s);
+
+// Number of per-load partial sums the operator and z-pass launches write.
+int kop_nblocks(const Grid& g, bool hex_elastic);
+template <typename T>
+int zpass_nblocks(const Grid& g);
+
+// Reductions and PCG scalar updates.
+hipError_t launch_finalize_init(PcgState* st, const double* part, int nb, int nload,
+                                hipStream_t s);
+hipError_t launch_finalize_alpha(PcgState* st, const double* part, int nb, int nload,
+                                 hipStream_t s);
+hipError_t launch_finalize_beta(PcgState* st, const double* part, int nb, int nload,
+                                double* hist, int hist_len, hipStream_t s);
+hipError_t launch_dot_partials(const double* a, const double* b, long long n, double* part,
+                               int nb, hipStream_t s);
+hipError_t launch_sum_partials(const double* part, int nb, double* out, hipStream_t s);
+hipError_t launch_phase_count(const uint8_t* phase, long long n, int nphase,
+                              unsigned long long* counts, int* bad, hipStream_t s);
+template <typename T>
+hipError_t launch_fill(T* x, T v, long long n, hipStream_t s);
+hipError_t launch_copy(double* dst, const double* src, long long n, hipStream_t s);
+hipError_t launch_axpy(double* y, double a, const double* x, long long n, hipStream_t s);
+// y = x - mean(x) per component: not needed on the hot path.
+hipError_t launch_cast_d2f(const double* src, float* dst, long long n, hipStream_t s);
+hipError_t launch_add_f2d(double* dst, const float* src, long long n, hipStream_t s);
+hipError_t launch_residual(double* r, const double* b, const double* Kx, long long n,
+                           hipStream_t s);
+hipError_t launch_impulse(double* f, long long n, long long pos, hipStream_t s);
+hipError_t launch_field_sum(const double* x, long long n, double* out_part, int nb,
+                            hipStream_t s);
+
+}  // namespace fh

@@ -1,0 +1,417 @@
+// Matrix-free stiffness operator q = K u = D^T W C D u and the right-hand
+// side b = -D^T W C e.
+//
+// Paper Sec. 3 (eqs. Du_mat, grad_componets, W_mat, lin_system) and Sec. 5.1:
+// the gradient D is applied as a short stencil per pixel/voxel and the
+// quadrature weights are fused into the transpose ("weighted divergence").
+//
+// Elastic hex8 kernel (3D trilinear hexahedra, 2x2x2 Gauss points,
+// element-wise constant Mandel stiffness):
+//   Per voxel the 8 corner values of each displacement component are mapped
+//   to tensor-product modes (per axis: mean and difference).  In that basis
+//   the gradient at the Gauss points is a sum over products of (xi - 1/2)
+//   factors, and the 2-point Gauss rule is orthogonal on {1, xi - 1/2} with
+//   weights 1 and 1/12.  The element energy therefore splits into seven
+//   independent terms (mode sets M of size 0, 1, 2), each a 6 x 6 Mandel
+//   contraction on at most six strain coefficients.  This is exactly the
+//   2x2x2 quadrature of D^T W C D (no approximation) with about a third of
+//   the arithmetic of the per-point form.
+//   Work split: a block owns a TX x TY tile of output nodes and a chunk of z
+//   planes, computes the (TX+1) x (TY+1) voxels that touch the tile, marches
+//   in z keeping two node planes in LDS, carries the upper-face forces of the
+//   previous voxel slab in registers, and sums the four in-plane voxel
+//   contributions of every node through LDS in a fixed order (deterministic).
+//   The energy u.Ku = sum_e u_e.K_e u_e is accumulated per owned voxel, which
+//   gives the PCG inner product p.q without a second pass.
+#include "fh_internal.h"
+
+namespace fh {
+
+__device__ __forceinline__ int wrapi(int v, int n) {
+  int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ double block_sum_k(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) s += sh[w];
+  }
+  return s;
+}
+
+// One term of the modal energy for mode set M (bit 1 = x, 2 = y, 4 = z).
+// w[c][m]: mode m of displacement component c; fh: modal forces.
+template <typename T, int M>
+__device__ __forceinline__ void modal_term(const T (&w)[3][8], T (&fh)[3][8], const T* __restrict__ C,
+                                           const T ihx, const T ihy, const T ihz, double& energy) {
+  constexpr bool X = !(M & 1), Y = !(M & 2), Z = !(M & 4);
+  constexpr int nbits = ((M & 1) ? 1 : 0) + ((M & 2) ? 1 : 0) + ((M & 4) ? 1 : 0);
+  const T cM = nbits == 0 ? T(1) : (nbits == 1 ? T(1.0 / 12.0) : T(1.0 / 144.0));
+  const T s = T(0.70710678118654752440084436210485);
+  constexpr bool nz[6] = {X, Y, Z, Y || Z, X || Z, X || Y};
+  T E[6];
+  E[0] = X ? w[0][M | 1] * ihx : T(0);
+  E[1] = Y ? w[1][M | 2] * ihy : T(0);
+  E[2] = Z ? w[2][M | 4] * ihz : T(0);
+  E[3] = s * ((Z ? w[1][M | 4] * ihz : T(0)) + (Y ? w[2][M | 2] * ihy : T(0)));
+  E[4] = s * ((Z ? w[0][M | 4] * ihz : T(0)) + (X ? w[2][M | 1] * ihx : T(0)));
+  E[5] = s * ((Y ? w[0][M | 2] * ihy : T(0)) + (X ? w[1][M | 1] * ihx : T(0)));
+  T S[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    T acc = T(0);
+    if (nz[i]) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (nz[k]) acc += C[i * 6 + k] * E[k];
+    }
+    S[i] = cM * acc;
+  }
+  double e = 0.0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+    if (nz[i]) e += (double)E[i] * (double)S[i];
+  energy += e;
+  if (X) fh[0][M | 1] += S[0] * ihx;
+  if (Y) fh[1][M | 2] += S[1] * ihy;
+  if (Z) fh[2][M | 4] += S[2] * ihz;
+  if (Z) fh[1][M | 4] += s * S[3] * ihz;
+  if (Y) fh[2][M | 2] += s * S[3] * ihy;
+  if (Z) fh[0][M | 4] += s * S[4] * ihz;
+  if (X) fh[2][M | 1] += s * S[4] * ihx;
+  if (Y) fh[0][M | 2] += s * S[5] * ihy;
+  if (X) fh[1][M | 1] += s * S[5] * ihx;
+}
+
+template <typename T, int TX, int TY>
+struct HexCfg {
+  static constexpr int EX = TX + 1, EY = TY + 1, PX = TX + 2, PY = TY + 2;
+  static constexpr int NE = EX * EY, NP = PX * PY;
+  static constexpr int NT = ((NE + 63) / 64) * 64;
+};
+
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT))
+    k_kop_hex8_elastic(Grid g, int kz, const T* __restrict__ u, T* __restrict__ q,
+                       const uint8_t* __restrict__ phase, const T* __restrict__ mat,
+                       long long ustride, long long qstride, const PcgState* st, double* pq_part) {
+  using Cfg = HexCfg<T, TX, TY>;
+  constexpr int EX = Cfg::EX, PX = Cfg::PX, NE = Cfg::NE, NP = Cfg::NP;
+  __shared__ T plane[2][3][NP];
+  __shared__ T force[12][NE];
+  __shared__ double red[32];
+  const int ld = blockIdx.z;
+  if (st && st[ld].status != ST_ACTIVE) return;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const long long N = g.N;
+  const int ntx = (nx + TX - 1) / TX;
+  const int x0 = (blockIdx.x % ntx) * TX, y0 = (blockIdx.x / ntx) * TY;
+  const int z0 = blockIdx.y * kz;
+  const int z1 = min(z0 + kz, nz);
+  const T* __restrict__ ub = u + (long long)ld * ustride;
+  T* __restrict__ qb = q + (long long)ld * qstride;
+  const int tid = threadIdx.x;
+  const bool is_elem = tid < NE;
+  const int ei = tid % EX, ej = tid / EX;
+  const int ex = wrapi(x0 - 1 + ei, nx), ey = wrapi(y0 - 1 + ej, ny);
+  const bool own_xy = is_elem && ei >= 1 && ej >= 1 && (x0 + ei - 1 < nx) && (y0 + ej - 1 < ny);
+  const T ihx = T(1.0 / g.h[0]), ihy = T(1.0 / g.h[1]), ihz = T(1.0 / g.h[2]);
+
+  auto load_plane = [&](int zp, int buf) {
+    const long long zoff = (long long)wrapi(zp, nz) * ny;
+    for (int idx = tid; idx < NP; idx += blockDim.x) {
+      const int a = idx % PX, b = idx / PX;
+      const int gx = wrapi(x0 - 1 + a, nx), gy = wrapi(y0 - 1 + b, ny);
+      const long long o = (zoff + gy) * nx + gx;
+      plane[buf][0][idx] = ub[o];
+      plane[buf][1][idx] = ub[N + o];
+      plane[buf][2][idx] = ub[2 * N + o];
+    }
+  };
+
+  T carry[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) carry[k] = T(0);
+  double energy = 0.0;
+  load_plane(z0 - 1, 0);
+  const int nsteps = z1 - z0 + 1;
+  for (int s = 0; s < nsteps; ++s) {
+    const int zs = z0 - 1 + s;
+    const int lo = s & 1, hi = lo ^ 1;
+    load_plane(zs + 1, hi);
+    __syncthreads();
+    if (is_elem) {
+      T w[3][8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int idx = (ej + ((a >> 1) & 1)) * PX + (ei + (a & 1));
+        const int buf = (a >> 2) ? hi : lo;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) w[c][a] = plane[buf][c][idx];
+      }
+      // forward modal transform along x, y, z: (u0, u1) -> ((u0+u1)/2, u1-u0)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int bit = 1; bit < 8; bit <<= 1) {
+#pragma unroll
+          for (int a = 0; a < 8; ++a) {
+            if (a & bit) continue;
+            const T u0 = w[c][a], u1 = w[c][a | bit];
+            w[c][a] = T(0.5) * (u0 + u1);
+            w[c][a | bit] = u1 - u0;
+          }
+        }
+      }
+      const uint8_t ph = phase[((long long)wrapi(zs, nz) * ny + ey) * nx + ex];
+      const T* __restrict__ C = mat + (int)ph * 36;
+      T fh[3][8];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int a = 0; a < 8; ++a) fh[c][a] = T(0);
+      double e = 0.0;
+      modal_term<T, 0>(w, fh, C, ihx, ihy, ihz, e);
+      modal_term<T, 1>(w, fh, C, ihx, ihy, ihz, e);
+      modal_term<T, 2>(w, fh, C, ihx, ihy, ihz, e);
+      modal_term<T, 4>(w, fh, C, ihx, ihy, ihz, e);
+      modal_term<T, 3>(w, fh, C, ihx, ihy, ihz, e);
+      modal_term<T, 5>(w, fh, C, ihx, ihy, ihz, e);
+      modal_term<T, 6>(w, fh, C, ihx, ihy, ihz, e);
+      // transpose transform: (fm, fd) -> (fm/2 - fd, fm/2 + fd)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int bit = 1; bit < 8; bit <<= 1) {
+#pragma unroll
+          for (int a = 0; a < 8; ++a) {
+            if (a & bit) continue;
+            const T fm = fh[c][a], fd = fh[c][a | bit];
+            fh[c][a] = T(0.5) * fm - fd;
+            fh[c][a | bit] = T(0.5) * fm + fd;
+          }
+        }
+      }
+      if (s > 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) force[c * 4 + k][tid] = fh[c][k] + carry[c * 4 + k];
+        if (own_xy) energy += e;
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) carry[c * 4 + k] = fh[c][k + 4];
+    }
+    __syncthreads();
+    if (s > 0 && tid < TX * TY) {
+      const int ox = tid % TX, oy = tid / TX;
+      const int x = x0 + ox, y = y0 + oy;
+      if (x < nx && y < ny) {
+        const int e00 = oy * EX + ox;
+        const long long o = ((long long)zs * ny + y) * nx + x;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const T v = force[c * 4 + 3][e00] + force[c * 4 + 2][e00 + 1] +
+                      force[c * 4 + 1][e00 + EX] + force[c * 4 + 0][e00 + EX + 1];
+          qb[c * N + o] = v;
+        }
+      }
+    }
+  }
+  if (pq_part) {
+    const double tot = block_sum_k(energy, red);
+    if (tid == 0) {
+      const long long nb = (long long)gridDim.x * gridDim.y;
+      pq_part[(long long)ld * nb + (long long)blockIdx.y * gridDim.x + blockIdx.x] = tot;
+    }
+  }
+}
+
+constexpr int kHexTX = 32, kHexTY = 8;
+
+static int hex_kz(const Grid& g) { return g.nz >= 64 ? 16 : 8; }
+
+int kop_nblocks(const Grid& g, bool hex_elastic) {
+  if (hex_elastic) {
+    const int kz = hex_kz(g);
+    const int ntiles = ((g.nx + kHexTX - 1) / kHexTX) * ((g.ny + kHexTY - 1) / kHexTY);
+    return ntiles * ((g.nz + kz - 1) / kz);
+  }
+  long long blocks = (g.N + 255) / 256;
+  return (int)(blocks > 2048 ? 2048 : blocks);
+}
+
+template <typename T>
+hipError_t launch_kop_hex8_elastic(const Grid& g, const T* u, T* q, const uint8_t* phase,
+                                   const T* mat, int nload, long long ustride, long long qstride,
+                                   const PcgState* st, double* pq_part, int* nblocks_out,
+                                   hipStream_t s) {
+  constexpr int TX = kHexTX, TY = kHexTY;
+  using Cfg = HexCfg<T, TX, TY>;
+  const int kz = hex_kz(g);
+  const int ntiles = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
+  dim3 grid(ntiles, (g.nz + kz - 1) / kz, nload);
+  if (nblocks_out) *nblocks_out = grid.x * grid.y;
+  hipLaunchKernelGGL((k_kop_hex8_elastic<T, TX, TY>), grid, dim3(Cfg::NT), 0, s, g, kz, u, q,
+                     phase, mat, ustride, qstride, st, pq_part);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ node-centric operator
+// Used for 2D stencils (quad4, tri2) and the 3D scalar hex8: per node, sum
+// over the pixels e = I - c_a that contain it of the element-matrix rows.
+// ke holds per-phase element matrices (NC*ND)^2, row index a*ND + alpha,
+// already integrated on the host; kfield (if set) scales a unit matrix.
+template <typename T, int DIM, int ND>
+__global__ void __launch_bounds__(256)
+    k_kop_generic(Grid g, const T* __restrict__ u, T* __restrict__ q,
+                  const uint8_t* __restrict__ phase, const T* __restrict__ kfield,
+                  const T* __restrict__ ke, long long ustride, long long qstride,
+                  const PcgState* st, double* pq_part) {
+  constexpr int NC = 1 << DIM, NK = NC * ND;
+  __shared__ double red[8];
+  const int ld = blockIdx.y;
+  if (st && st[ld].status != ST_ACTIVE) return;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const long long N = g.N;
+  const T* __restrict__ ub = u + (long long)ld * ustride;
+  T* __restrict__ qb = q + (long long)ld * qstride;
+  double dot = 0.0;
+  for (long long I = blockIdx.x * (long long)blockDim.x + threadIdx.x; I < N;
+       I += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(I % nx);
+    const int y = (int)((I / nx) % ny);
+    const int z = (int)(I / ((long long)nx * ny));
+    T acc[ND];
+#pragma unroll
+    for (int al = 0; al < ND; ++al) acc[al] = T(0);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+      const int exx = wrapi(x - ax, nx), eyy = wrapi(y - ay, ny), ezz = wrapi(z - az, nz);
+      const long long e = ((long long)ezz * ny + eyy) * nx + exx;
+      const T* Ke = phase ? ke + (size_t)phase[e] * NK * NK : ke;
+      const T sc = kfield ? kfield[e] : T(1);
+#pragma unroll
+      for (int b = 0; b < NC; ++b) {
+        const int bx = b & 1, by = (b >> 1) & 1, bz = (b >> 2) & 1;
+        const long long J = ((long long)wrapi(ezz + bz, nz) * ny + wrapi(eyy + by, ny)) * nx +
+                            wrapi(exx + bx, nx);
+#pragma unroll
+        for (int be = 0; be < ND; ++be) {
+          const T uj = sc * ub[be * N + J];
+#pragma unroll
+          for (int al = 0; al < ND; ++al) acc[al] += Ke[(a * ND + al) * NK + b * ND + be] * uj;
+        }
+      }
+    }
+#pragma unroll
+    for (int al = 0; al < ND; ++al) {
+      qb[al * N + I] = acc[al];
+      dot += (double)ub[al * N + I] * (double)acc[al];
+    }
+  }
+  if (pq_part) {
+    const double tot = block_sum_k(dot, red);
+    if (threadIdx.x == 0) pq_part[(long long)ld * gridDim.x + blockIdx.x] = tot;
+  }
+}
+
+template <typename T>
+hipError_t launch_kop_generic(const Grid& g, int elem, const T* u, T* q, const uint8_t* phase,
+                              const T* kfield, const T* ke, int nload, long long ustride,
+                              long long qstride, const PcgState* st, double* pq_part,
+                              int* nblocks_out, hipStream_t s) {
+  (void)elem;
+  const int blocks = kop_nblocks(g, false);
+  dim3 grid((unsigned)blocks, nload);
+  if (nblocks_out) *nblocks_out = (int)blocks;
+  if (g.dim == 3 && g.nd == 1)
+    hipLaunchKernelGGL((k_kop_generic<T, 3, 1>), grid, dim3(256), 0, s, g, u, q, phase, kfield,
+                       ke, ustride, qstride, st, pq_part);
+  else if (g.dim == 2 && g.nd == 1)
+    hipLaunchKernelGGL((k_kop_generic<T, 2, 1>), grid, dim3(256), 0, s, g, u, q, phase, kfield,
+                       ke, ustride, qstride, st, pq_part);
+  else if (g.dim == 2 && g.nd == 2)
+    hipLaunchKernelGGL((k_kop_generic<T, 2, 2>), grid, dim3(256), 0, s, g, u, q, phase, kfield,
+                       ke, ustride, qstride, st, pq_part);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------------- RHS
+// b[alpha][I] = -sum_a fe[t(e)][load][a*nd + alpha] (* k(e)), e = I - c_a.
+// Corner contributions are added in antipodal pairs (a, NC-1-a): in a
+// homogeneous medium each pair cancels exactly, so b = 0 exactly there.
+__global__ void k_rhs(Grid g, int nc, const uint8_t* __restrict__ phase,
+                      const double* __restrict__ kfield, const double* __restrict__ fe,
+                      int nload, double* __restrict__ b, long long bstride) {
+  const int ld = blockIdx.y;
+  const int nx = g.nx, ny = g.ny, nz = g.nz, nd = g.nd;
+  const long long N = g.N;
+  const int nk = nc * nd;
+  for (long long I = blockIdx.x * (long long)blockDim.x + threadIdx.x; I < N;
+       I += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(I % nx);
+    const int y = (int)((I / nx) % ny);
+    const int z = (int)(I / ((long long)nx * ny));
+    for (int al = 0; al < nd; ++al) {
+      double acc = 0.0;
+      for (int a = 0; a < nc / 2; ++a) {
+        double pair = 0.0;
+        for (int side = 0; side < 2; ++side) {
+          const int aa = side ? nc - 1 - a : a;
+          const int ax = aa & 1, ay = (aa >> 1) & 1, az = (aa >> 2) & 1;
+          const long long e = ((long long)wrapi(z - az, nz) * ny + wrapi(y - ay, ny)) * nx +
+                              wrapi(x - ax, nx);
+          const int t = phase ? phase[e] : 0;
+          const double sc = kfield ? kfield[e] : 1.0;
+          pair += sc * fe[((size_t)t * nload + ld) * nk + aa * nd + al];
+        }
+        acc += pair;
+      }
+      b[(long long)ld * bstride + al * N + I] = -acc;
+    }
+  }
+}
+
+hipError_t launch_rhs(const Grid& g, int elem, const uint8_t* phase, const double* kfield,
+                      const double* fe, int nphase_tables, int nload, double* b,
+                      long long bstride, hipStream_t s) {
+  (void)nphase_tables;
+  (void)elem;
+  const int nc = g.dim == 3 ? 8 : 4;
+  long long blocks = (g.N + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_rhs, dim3((unsigned)blocks, nload), dim3(256), 0, s, g, nc, phase, kfield,
+                     fe, nload, b, bstride);
+  return hipGetLastError();
+}
+
+template hipError_t launch_kop_hex8_elastic<double>(const Grid&, const double*, double*,
+                                                    const uint8_t*, const double*, int,
+                                                    long long, long long, const PcgState*,
+                                                    double*, int*, hipStream_t);
+template hipError_t launch_kop_hex8_elastic<float>(const Grid&, const float*, float*,
+                                                   const uint8_t*, const float*, int, long long,
+                                                   long long, const PcgState*, double*, int*,
+                                                   hipStream_t);
+template hipError_t launch_kop_generic<double>(const Grid&, int, const double*, double*,
+                                               const uint8_t*, const double*, const double*,
+                                               int, long long, long long, const PcgState*,
+                                               double*, int*, hipStream_t);
+template hipError_t launch_kop_generic<float>(const Grid&, int, const float*, float*,
+                                              const uint8_t*, const float*, const float*, int,
+                                              long long, long long, const PcgState*, double*,
+                                              int*, hipStream_t);
+
+}  // namespace fh

@@ -1,0 +1,270 @@
+"""Thin ctypes binding of the C-ABI declared in include/fh.h.
+
+Argument marshalling only: every step of the solver runs in libfh.so.  Device
+arrays are passed as torch tensors on the context's device (their data
+pointers go to the library); host arrays as numpy arrays.  Loading fails
+loudly if libfh.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfh.so")
+
+FH_OK, FH_NOT_CONVERGED = 0, 1
+FH_EINVAL, FH_ENOMEM, FH_EDEVICE, FH_ENOTSPD, FH_ESTATE = -1, -2, -3, -4, -5
+FH_SCALAR, FH_ELASTIC = 0, 1
+FH_HEX8, FH_QUAD4, FH_TRI2 = 0, 1, 2
+FH_FP64, FH_FP32_REFINED = 0, 1
+FH_MAX_LOADS = 32
+
+ELEMENTS = {"hex8": FH_HEX8, "quad4": FH_QUAD4, "tri2": FH_TRI2}
+PROBLEMS = {"scalar": FH_SCALAR, "elastic": FH_ELASTIC}
+
+EXPORTED = [
+    "fh_create", "fh_destroy", "fh_last_error", "fh_set_stream", "fh_set_grid",
+    "fh_set_phases", "fh_set_conductivity_field", "fh_set_reference", "fh_set_load",
+    "fh_workspace_size", "fh_bind_workspace", "fh_solve", "fh_get_fluctuation",
+    "fh_get_homogenized", "fh_get_reference", "fh_get_history", "fh_apply_operator",
+    "fh_apply_preconditioner", "fh_compute_rhs", "fh_get_symbol", "fh_solve_rhs",
+]
+
+
+class fh_opts(ctypes.Structure):
+    _fields_ = [("eta", ctypes.c_double), ("itmax", ctypes.c_int),
+                ("precision", ctypes.c_int), ("poll", ctypes.c_int),
+                ("reserved_i", ctypes.c_int), ("eta_inner", ctypes.c_double)]
+
+
+class fh_stats(ctypes.Structure):
+    _fields_ = [("nload", ctypes.c_int),
+                ("iterations", ctypes.c_int * FH_MAX_LOADS),
+                ("status", ctypes.c_int * FH_MAX_LOADS),
+                ("rel_res", ctypes.c_double * FH_MAX_LOADS),
+                ("outer", ctypes.c_int * FH_MAX_LOADS),
+                ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("chom_ms", ctypes.c_double), ("dof", ctypes.c_longlong)]
+
+    def as_dict(self):
+        n = self.nload
+        return dict(nload=n, iterations=list(self.iterations[:n]), status=list(self.status[:n]),
+                    rel_res=list(self.rel_res[:n]), outer=list(self.outer[:n]),
+                    setup_ms=self.setup_ms, solve_ms=self.solve_ms, chom_ms=self.chom_ms,
+                    dof=self.dof)
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libfh.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libfh.so not found at {path}: run __graft_entry__.build() "
+                           "or python paper_2203_02962_amd/build.py")
+    lib = ctypes.CDLL(path)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    sig = {
+        "fh_create": ([ctypes.POINTER(P), I], I),
+        "fh_destroy": ([P], None),
+        "fh_last_error": ([P], ctypes.c_char_p),
+        "fh_set_stream": ([P, P], I),
+        "fh_set_grid": ([P, I, ctypes.POINTER(I), ctypes.POINTER(D), I, I], I),
+        "fh_set_phases": ([P, P, I, ctypes.POINTER(D)], I),
+        "fh_set_conductivity_field": ([P, P], I),
+        "fh_set_reference": ([P, ctypes.POINTER(D)], I),
+        "fh_set_load": ([P, I, ctypes.POINTER(D)], I),
+        "fh_workspace_size": ([P, ctypes.POINTER(ctypes.c_size_t)], I),
+        "fh_bind_workspace": ([P, P, ctypes.c_size_t], I),
+        "fh_solve": ([P, ctypes.POINTER(fh_opts), ctypes.POINTER(fh_stats)], I),
+        "fh_get_fluctuation": ([P, I, P], I),
+        "fh_get_homogenized": ([P, ctypes.POINTER(D)], I),
+        "fh_get_reference": ([P, ctypes.POINTER(D)], I),
+        "fh_get_history": ([P, I, ctypes.POINTER(D), I, ctypes.POINTER(I)], I),
+        "fh_apply_operator": ([P, P, P], I),
+        "fh_apply_preconditioner": ([P, P, P], I),
+        "fh_compute_rhs": ([P, ctypes.POINTER(D), P], I),
+        "fh_get_symbol": ([P, P], I),
+        "fh_solve_rhs": ([P, P, P, ctypes.POINTER(fh_opts), ctypes.POINTER(fh_stats)], I),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+class FHError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fh error {code}: {msg}")
+        self.code = code
+
+
+def _dptr(arr):
+    # callers convert first, so the array outlives the call
+    assert arr.dtype == np.float64 and arr.flags.c_contiguous
+    return arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _tptr(t):
+    import torch  # device memory provider only
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or not t.is_contiguous():
+        raise TypeError("expected a contiguous CUDA (HIP) tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """Owns one fh_ctx.  Method names follow the C functions (fh_ prefix
+    dropped)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        self.ptr = ctypes.c_void_p()
+        rc = self.lib.fh_create(ctypes.byref(self.ptr), device)
+        if rc != FH_OK:
+            raise FHError(rc, f"fh_create(device={device}) failed")
+        self.device = device
+        self._keep = []      # device inputs that must outlive the call
+        self._ws = None
+
+    def _check(self, rc, allow_warning=False):
+        if rc < 0 or (rc > 0 and not allow_warning):
+            raise FHError(rc, self.lib.fh_last_error(self.ptr).decode())
+        return rc
+
+    def close(self):
+        if self.ptr:
+            self.lib.fh_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --------------------------------------------------------------- setters
+    def set_stream(self, stream):
+        """stream: torch.cuda.Stream or a raw hipStream_t integer."""
+        raw = getattr(stream, "cuda_stream", stream)
+        return self._check(self.lib.fh_set_stream(self.ptr, ctypes.c_void_p(raw)))
+
+    def set_grid(self, n, problem="elastic", element="hex8", l=None):
+        n = list(n) + [1] * (3 - len(n))
+        dim = 3 if element == "hex8" else 2
+        narr = (ctypes.c_int * 3)(*[int(v) for v in n])
+        larr = None if l is None else (ctypes.c_double * 3)(*(list(l) + [1.0] * (3 - len(l))))
+        self.nd = (dim if problem == "elastic" else 1)
+        self.N = int(np.prod(n[:dim]))
+        self.n = tuple(n[:dim])
+        self.dim = dim
+        self.m = dim * (dim + 1) // 2 if problem == "elastic" else dim
+        return self._check(self.lib.fh_set_grid(self.ptr, dim, narr, larr,
+                                                PROBLEMS[problem], ELEMENTS[element]))
+
+    def set_phases(self, phase_dev, mat):
+        mat = np.ascontiguousarray(mat, dtype=np.float64)
+        self._keep = [phase_dev]
+        return self._check(self.lib.fh_set_phases(self.ptr, _tptr(phase_dev), int(mat.shape[0]),
+                                                  _dptr(mat)))
+
+    def set_conductivity_field(self, k_dev):
+        self._keep = [k_dev]
+        return self._check(self.lib.fh_set_conductivity_field(self.ptr, _tptr(k_dev)))
+
+    def set_reference(self, Cref=None):
+        if Cref is None:
+            return self._check(self.lib.fh_set_reference(self.ptr, None))
+        C = np.ascontiguousarray(Cref, dtype=np.float64)
+        return self._check(self.lib.fh_set_reference(self.ptr, _dptr(C)))
+
+    def set_load(self, E):
+        E = np.ascontiguousarray(np.atleast_2d(E), dtype=np.float64)
+        self.nload = E.shape[0]
+        return self._check(self.lib.fh_set_load(self.ptr, E.shape[0], _dptr(E)))
+
+    def workspace_size(self):
+        b = ctypes.c_size_t()
+        self._check(self.lib.fh_workspace_size(self.ptr, ctypes.byref(b)))
+        return b.value
+
+    def bind_workspace(self, buf=None):
+        """Bind a torch uint8 CUDA tensor as the workspace (None: unbind)."""
+        if buf is None:
+            self._ws = None
+            return self._check(self.lib.fh_bind_workspace(self.ptr, None, 0))
+        self._ws = buf
+        return self._check(self.lib.fh_bind_workspace(self.ptr, _tptr(buf), buf.numel()))
+
+    # ----------------------------------------------------------------- solve
+    @staticmethod
+    def opts(eta=1e-10, itmax=10000, precision=FH_FP64, poll=0, eta_inner=0.0):
+        return fh_opts(eta, itmax, precision, poll, 0, eta_inner)
+
+    def solve(self, eta=1e-10, itmax=10000, precision=FH_FP64, poll=0, eta_inner=0.0):
+        o = self.opts(eta, itmax, precision, poll, eta_inner)
+        st = fh_stats()
+        rc = self._check(self.lib.fh_solve(self.ptr, ctypes.byref(o), ctypes.byref(st)),
+                         allow_warning=True)
+        return rc, st.as_dict()
+
+    def get_fluctuation(self, load, out_dev):
+        return self._check(self.lib.fh_get_fluctuation(self.ptr, load, _tptr(out_dev)))
+
+    def get_homogenized(self):
+        H = np.zeros((self.nload, self.nload))
+        self._check(self.lib.fh_get_homogenized(self.ptr, _dptr_out(H)))
+        return H
+
+    def get_reference(self):
+        C = np.zeros((self.m, self.m))
+        self._check(self.lib.fh_get_reference(self.ptr, _dptr_out(C)))
+        return C
+
+    def get_history(self, load):
+        cnt = ctypes.c_int()
+        self._check(self.lib.fh_get_history(self.ptr, load, None, 0, ctypes.byref(cnt)))
+        h = np.zeros(max(cnt.value, 1))
+        self._check(self.lib.fh_get_history(self.ptr, load, _dptr_out(h), cnt.value,
+                                            ctypes.byref(cnt)))
+        return h[:cnt.value]
+
+    # ----------------------------------------------------------- step hooks
+    def apply_operator(self, u_dev, q_dev):
+        return self._check(self.lib.fh_apply_operator(self.ptr, _tptr(u_dev), _tptr(q_dev)))
+
+    def apply_preconditioner(self, r_dev, z_dev):
+        return self._check(self.lib.fh_apply_preconditioner(self.ptr, _tptr(r_dev),
+                                                            _tptr(z_dev)))
+
+    def compute_rhs(self, E, b_dev):
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        return self._check(self.lib.fh_compute_rhs(self.ptr, _dptr(E), _tptr(b_dev)))
+
+    def get_symbol(self, kplus_dev):
+        return self._check(self.lib.fh_get_symbol(self.ptr, _tptr(kplus_dev)))
+
+    def solve_rhs(self, b_dev, u_dev, eta=1e-10, itmax=10000, poll=0):
+        o = self.opts(eta, itmax, FH_FP64, poll)
+        st = fh_stats()
+        rc = self._check(self.lib.fh_solve_rhs(self.ptr, _tptr(b_dev), _tptr(u_dev),
+                                               ctypes.byref(o), ctypes.byref(st)),
+                         allow_warning=True)
+        return rc, st.as_dict()
+
+
+def _dptr_out(arr):
+    assert arr.dtype == np.float64 and arr.flags.c_contiguous
+    return arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# C-ABI names as module-level functions (same names as include/fh.h)
+def fh_create(device=0):
+    return Context(device)

@@ -1,0 +1,269 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU FP64 oracle.
+
+Tolerances (FP64): step-level results (operator, right-hand side, symbol,
+preconditioner) agree element by element to 1e-12 relative to the largest
+entry (round-off of sums of at most a few hundred terms); full solves agree on
+the homogenized tensor to 1e-10 relative and on the PCG iteration count to
++-max(1, 1% of the count).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.assembly import Problem, assemble_stiffness, rhs
+from oracle.precond import Preconditioner
+from synth import isotropic_conductivity, isotropic_mandel, laminate, spheres, workload
+from tests.helpers_tensor import random_spd
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fh():
+    from paper_2203_02962_amd import fh as fhmod
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    fhmod.load_library()
+    return fhmod
+
+
+def _case(elem, problem, n, nphase=3, kind="phase", seed=0, l=None):
+    rng = np.random.default_rng(seed)
+    dim = len(n)
+    m = dim * (dim + 1) // 2 if problem == "elastic" else dim
+    wl = dict(dim=dim, n=tuple(n) + (1,) * (3 - dim), problem=problem, element=elem,
+              loads=np.eye(m), l=l)
+    if kind == "phase":
+        wl["phase"] = rng.integers(0, nphase, size=n[::-1]).astype(np.uint8)
+        wl["mat"] = np.stack([random_spd(m, rng, 20.0) * (1 + 10 * p) for p in range(nphase)])
+        prob = Problem(n, problem, elem, phase=wl["phase"], mat=wl["mat"], l=l)
+    else:
+        wl["kfield"] = np.exp(rng.uniform(-2, 2, size=n[::-1]))
+        prob = Problem(n, problem, elem, kfield=wl["kfield"], l=l)
+    return wl, prob
+
+
+CASES = [
+    ("hex8", "elastic", (20, 12, 10), "phase", (1.0, 0.8, 1.2)),
+    ("hex8", "elastic", (32, 16, 16), "phase", None),
+    ("hex8", "elastic", (6, 4, 6), "phase", None),
+    ("hex8", "scalar", (12, 10, 6), "phase", None),
+    ("hex8", "scalar", (12, 10, 6), "field", (0.5, 1.0, 1.5)),
+    ("tri2", "scalar", (12, 10), "phase", None),
+    ("tri2", "elastic", (10, 6), "phase", None),
+    ("quad4", "elastic", (10, 8), "phase", (1.0, 0.7)),
+    ("quad4", "scalar", (8, 6), "phase", None),
+]
+
+
+def _ids(c):
+    return f"{c[0]}-{c[1]}-{'x'.join(map(str, c[2]))}-{c[3]}"
+
+
+def _ctx(fh, wl):
+    from paper_2203_02962_amd.runner import setup_context
+    return setup_context(wl)
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_operator_matches_oracle(fh, case):
+    elem, problem, n, kind, l = case
+    say("operator", _ids(case))
+    wl, prob = _case(elem, problem, n, kind=kind, l=l)
+    ctx = _ctx(fh, wl)
+    rng = np.random.default_rng(1)
+    u = rng.standard_normal(prob.ndof_node * prob.N)
+    ud = torch.from_numpy(u).cuda()
+    qd = torch.empty_like(ud)
+    ctx.apply_operator(ud, qd)
+    ref = assemble_stiffness(prob) @ u
+    assert _rel(qd.cpu().numpy(), ref) < 1e-12
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_rhs_matches_oracle(fh, case):
+    elem, problem, n, kind, l = case
+    say("rhs", _ids(case))
+    wl, prob = _case(elem, problem, n, kind=kind, l=l)
+    ctx = _ctx(fh, wl)
+    E = np.random.default_rng(2).standard_normal(wl["loads"].shape[1])
+    bd = torch.empty(prob.ndof_node * prob.N, dtype=torch.float64, device="cuda")
+    ctx.compute_rhs(E, bd)
+    ref = rhs(prob, E)
+    assert _rel(bd.cpu().numpy(), ref) < 1e-12
+
+
+def _half_symbol(prob, Kplus):
+    """oracle K^+ (N, nd, nd) -> [s][kx][ky][kz] half spectrum, / N."""
+    nd = prob.ndof_node
+    n = prob.n + (1,) * (3 - prob.dim)
+    K = Kplus.reshape(n[2], n[1], n[0], nd, nd)[:, :, : n[0] // 2 + 1]
+    K = np.transpose(K, (2, 1, 0, 3, 4)) / prob.N
+    pairs = {3: [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)], 2: [(0, 0), (1, 1), (0, 1)],
+             1: [(0, 0)]}[nd]
+    return np.stack([K[..., a, b] for a, b in pairs])
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_symbol_and_preconditioner_match_oracle(fh, case):
+    elem, problem, n, kind, l = case
+    say("symbol+precond", _ids(case))
+    wl, prob = _case(elem, problem, n, kind=kind, l=l)
+    ctx = _ctx(fh, wl)
+    Cref = oracle.mean_material(prob)
+    M = Preconditioner(prob, Cref)
+    nsym = prob.ndof_node * (prob.ndof_node + 1) // 2
+    nf = (wl["n"][0] // 2 + 1) * wl["n"][1] * wl["n"][2]
+    kd = torch.empty(nsym * nf, dtype=torch.float64, device="cuda")
+    ctx.get_symbol(kd)
+    ref = _half_symbol(prob, M.Kplus)
+    assert np.abs(ref.imag).max() < 1e-12 * np.abs(ref).max()
+    assert _rel(kd.cpu().numpy(), ref.real.ravel()) < 1e-12
+    assert _rel(ctx.get_reference(), Cref) < 1e-13
+    r = np.random.default_rng(3).standard_normal(prob.ndof_node * prob.N)
+    rd = torch.from_numpy(r).cuda()
+    zd = torch.empty_like(rd)
+    ctx.apply_preconditioner(rd, zd)
+    assert _rel(zd.cpu().numpy(), M.apply(r)) < 1e-12
+
+
+def _solve_both(fh, wl, prob, eta):
+    from paper_2203_02962_amd.runner import fluctuations
+    ctx = _ctx(fh, wl)
+    rc, st = ctx.solve(eta=eta)
+    H = ctx.get_homogenized()
+    us = fluctuations(ctx)
+    Ho, uo, res = oracle.homogenize(prob, wl["loads"], eta)
+    return (rc, st, H, us), (Ho, uo, res)
+
+
+SOLVE_CASES = [
+    ("elastic-spheres-24", lambda: _spheres_case(24, (2.5, 4.5), 100.0, 0)),
+    ("elastic-spheres-20x24x30", lambda: _spheres_box((20, 24, 30), 1)),
+    ("conductivity2d-tri-32", lambda: _named("conductivity2d_tri")),
+    ("scalar-hex8-field-16", lambda: _field_case(16)),
+    ("elastic-laminate-x", lambda: _laminate_case()),
+]
+
+
+def _spheres_case(n, rr, contrast, seed):
+    phase, _, _ = spheres(n, rr, 0.3, seed)
+    mat = np.stack([isotropic_mandel(1.0, 0.3), isotropic_mandel(contrast, 0.3)])
+    wl = dict(dim=3, n=(n, n, n), problem="elastic", element="hex8", phase=phase, mat=mat,
+              loads=np.eye(6))
+    return wl, Problem((n,) * 3, "elastic", "hex8", phase=phase, mat=mat)
+
+
+def _spheres_box(n, seed):
+    rng = np.random.default_rng(seed)
+    phase = (rng.random(n[::-1]) < 0.3).astype(np.uint8)
+    mat = np.stack([isotropic_mandel(1.0, 0.3), isotropic_mandel(30.0, 0.25)])
+    wl = dict(dim=3, n=n, problem="elastic", element="hex8", phase=phase, mat=mat,
+              loads=np.eye(6))
+    return wl, Problem(n, "elastic", "hex8", phase=phase, mat=mat)
+
+
+def _named(name):
+    wl = workload(name)
+    n = wl["n"][: wl["dim"]]
+    return wl, Problem(n, wl["problem"], wl["element"], phase=wl["phase"], mat=wl["mat"])
+
+
+def _field_case(n):
+    from synth import conductivity_grf
+    k = conductivity_grf(n, 2.0, 1.5, 1e3, seed=5)
+    wl = dict(dim=3, n=(n, n, n), problem="scalar", element="hex8", kfield=k, loads=np.eye(3))
+    return wl, Problem((n,) * 3, "scalar", "hex8", kfield=k)
+
+
+def _laminate_case():
+    n = (12, 6, 8)
+    phase = laminate(n, 0, [0, 1, 1, 0, 1, 0, 0, 1, 1, 1, 0, 0])
+    rng = np.random.default_rng(7)
+    mat = np.stack([random_spd(6, rng, 5.0), 50 * random_spd(6, rng, 5.0)])
+    wl = dict(dim=3, n=n, problem="elastic", element="hex8", phase=phase, mat=mat,
+              loads=np.eye(6))
+    return wl, Problem(n, "elastic", "hex8", phase=phase, mat=mat)
+
+
+@pytest.mark.parametrize("name,make", SOLVE_CASES, ids=[c[0] for c in SOLVE_CASES])
+def test_solve_matches_oracle(fh, name, make):
+    say("solve", name)
+    wl, prob = make()
+    (rc, st, H, us), (Ho, uo, res) = _solve_both(fh, wl, prob, 1e-10)
+    assert rc == 0, st
+    assert _rel(H, Ho) < 1e-10
+    for j, r in enumerate(res):
+        # the two FP64 runs sum in different orders; over long runs (high
+        # contrast, a flat residual tail) the stop can move by about 1% of
+        # the count, hence +-max(1, 1%)
+        tol = max(1, int(0.01 * r.iterations))
+        assert abs(st["iterations"][j] - r.iterations) <= tol, (st["iterations"], [x.iterations for x in res])
+        assert _rel(us[j], uo[j]) < 1e-7
+
+
+def test_homogeneous_medium_zero_iterations(fh):
+    say("homogeneous")
+    n = (8, 6, 10)
+    C0 = isotropic_mandel(3.0, 0.2)
+    wl = dict(dim=3, n=n, problem="elastic", element="hex8",
+              phase=np.zeros(n[::-1], np.uint8), mat=C0[None], loads=np.eye(6))
+    ctx = _ctx(fh, wl)
+    rc, st = ctx.solve(eta=1e-10)
+    assert rc == 0 and st["iterations"] == [0] * 6
+    assert _rel(ctx.get_homogenized(), C0) < 1e-14
+
+
+def test_reference_equal_material_one_iteration(fh):
+    say("C = Cref")
+    n = (10, 8, 6)
+    C = random_spd(6, np.random.default_rng(4))
+    wl = dict(dim=3, n=n, problem="elastic", element="hex8",
+              phase=np.zeros(n[::-1], np.uint8), mat=C[None], loads=np.eye(6))
+    ctx = _ctx(fh, wl)
+    b = np.random.default_rng(5).standard_normal((3, int(np.prod(n))))
+    b -= b.mean(axis=1, keepdims=True)
+    bd = torch.from_numpy(b.ravel()).cuda()
+    ud = torch.empty_like(bd)
+    rc, st = ctx.solve_rhs(bd, ud, eta=1e-12)
+    assert rc == 0 and st["iterations"] == [1]
+
+
+def test_solve_is_bitwise_deterministic(fh):
+    say("determinism")
+    from paper_2203_02962_amd.runner import fluctuations
+    wl, prob = _spheres_case(16, (2.0, 3.5), 100.0, 3)
+    ctx = _ctx(fh, wl)
+    ctx.solve(eta=1e-8)
+    H1, u1 = ctx.get_homogenized(), fluctuations(ctx)
+    ctx.solve(eta=1e-8)
+    H2, u2 = ctx.get_homogenized(), fluctuations(ctx)
+    assert np.array_equal(H1, H2)
+    assert all(np.array_equal(a, b) for a, b in zip(u1, u2))
+
+
+def test_breakdown_and_itmax_statuses(fh):
+    say("statuses")
+    wl, prob = _spheres_case(12, (1.5, 3.0), 100.0, 2)
+    ctx = _ctx(fh, wl)
+    rc, st = ctx.solve(eta=1e-12, itmax=3)
+    assert rc == fh.FH_NOT_CONVERGED and st["status"] == [1] * 6 and st["iterations"] == [3] * 6
+    # a negative-definite phase breaks PCG (p.q <= 0) -> FH_ENOTSPD
+    bad = dict(wl)
+    bad["mat"] = np.stack([wl["mat"][0], -wl["mat"][1]])
+    from paper_2203_02962_amd.runner import setup_context
+    with pytest.raises(fh.FHError) as e:
+        c2 = setup_context(bad, Cref=wl["mat"][0])
+        c2.solve(eta=1e-10)
+    assert e.value.code == fh.FH_ENOTSPD
