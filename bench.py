@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Whole-job throughput of the FFT-preconditioned FE homogenization solver.
+
+One step = one full solve of the 128^3 elasticity workload through the
+C-ABI: reference material, Alg. 2 symbol, the six right-hand sides, six PCG
+solves to eta = 1e-10 (all load cases advanced together on the device) and
+the 6 x 6 homogenized tensor.  Inputs (phase grid, material tables) are
+resident in HBM before the timed region.
+
+Prints one JSON line:
+  value      = sum over load cases of DOF x PCG iterations / seconds per step
+  roofline   = dominant kernel class: algorithmic bytes / event-timed duration
+               (HIP events recorded on the solve stream around every launch of
+               the timed steps) against the 8 TB/s HBM peak
+  cpu_baseline = the CPU oracle (assembled sparse K, naive-DFT
+               preconditioner) on a bounded sample of the same workload
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOF·PCG-iter/s at 128³ elasticity; time-to-1e-6 plain vs batched/warm-start"
+HBM_PEAK_GBS = 8000.0
+CLASSES = ["operator", "xfwd", "yfwd", "zsolve", "yinv", "xinv", "scalar", "other"]
+
+
+def algorithmic_bytes(n, nd=3, dtype_bytes=8):
+    """Bytes each kernel class must move per load case per PCG iteration
+    (compulsory traffic of this design: every field read or written once).
+    V = one nodal field, Sb = one half spectrum, Kb = stored K^+ / N,
+    Pb = phase grid."""
+    nx = ny = nz = n
+    N = nx * ny * nz
+    nxh = nx // 2 + 1
+    V = dtype_bytes * nd * N
+    Sb = 2 * dtype_bytes * nd * nxh * ny * nz
+    Kb = 8 * (nd * (nd + 1) // 2) * nxh * ny * nz
+    Pb = N
+    return {
+        "operator": 2 * V + Pb,          # read p, write q, read phase
+        "xfwd": 3 * V + Sb,              # read r, q; write r; write spectrum
+        "yfwd": 2 * Sb,                  # read + write spectrum
+        "zsolve": 2 * Sb + Kb,           # read + write spectrum, read K^+
+        "yinv": 2 * Sb,
+        "xinv": Sb + 4 * V,              # read spectrum, p, x; write p, x
+    }, dict(V=V, Sb=Sb, Kb=Kb, Pb=Pb)
+
+
+def cpu_baseline(wl, iters: int):
+    """Time the CPU oracle's PCG iterations (setup excluded) on load case 1."""
+    import numpy as np
+    import threadpoolctl
+
+    import oracle
+    from oracle.assembly import Problem, assemble_stiffness, rhs
+    from oracle.pcg import pcg
+    from oracle.precond import Preconditioner
+
+    n = wl["n"][0]
+    prob = Problem((n,) * 3, "elastic", "hex8", phase=wl["phase"], mat=wl["mat"])
+    t0 = time.perf_counter()
+    K = assemble_stiffness(prob)
+    M = Preconditioner(prob, oracle.mean_material(prob))
+    b = rhs(prob, wl["loads"][0])
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res = pcg(lambda v: K @ v, M.apply, b, 1e-30, itmax=iters, nd=3)
+    dt = time.perf_counter() - t0
+    dof = 3 * prob.N
+    blas = [i["num_threads"] for i in threadpoolctl.threadpool_info() if i["user_api"] == "blas"]
+    threads = max(blas) if blas else 1
+    return {
+        "value": dof * res.iterations / dt,
+        "unit": "DOF·PCG-iter/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"{n}^3 elasticity, load case 1, PCG iterations 1..{res.iterations} of the "
+                   f"CPU oracle ({dt:.1f} s timed; setup {t_setup:.1f} s not timed); CSR SpMV "
+                   f"single-threaded (scipy), naive separable DFT on OpenBLAS with {threads} "
+                   f"threads; host has {os.cpu_count()} logical CPUs"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--eta", type=float, default=1e-10)
+    ap.add_argument("--cpu-iters", type=int, default=6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-time-kernels", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(DESIGN.md describes how the solve would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2203_02962_amd.runner import setup_context
+    from synth import workload
+
+    wl = workload("elastic3d_spheres", seed=0, n=args.n)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    ctx = setup_context(wl)
+    ctx.set_stream(stream)
+    print(f"[bench] workload elastic3d_spheres n={args.n} vf={wl['vf']:.4f}; warmup {args.warmup}",
+          file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        ctx.solve(eta=args.eta, rebuild=True)
+    torch.cuda.synchronize()
+    kms = np.zeros(8)
+    kn = np.zeros(8)
+    iters_total = 0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        rc, st = ctx.solve(eta=args.eta, time_kernels=not args.no_time_kernels, rebuild=True)
+        if rc != 0:
+            raise SystemExit(f"solve returned {rc}: {st}")
+        kms += np.array(st["kernel_ms"])
+        kn += np.array(st["kernel_launches"])
+        iters_total += sum(st["iterations"])
+        print(f"[bench] step {k} done: iterations {st['iterations']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    dof = st["dof"]
+    value = dof * iters_total / (t1 - t0)
+    H = ctx.get_homogenized()
+
+    # plain-solver time to 1e-6 (same workload, separate solve)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    rc6, st6 = ctx.solve(eta=1e-6, rebuild=True)
+    torch.cuda.synchronize()
+    t_1e6 = (time.perf_counter() - ta) * 1000.0
+
+    per_iter, parts = algorithmic_bytes(args.n)
+    kernels = {}
+    for i, name in enumerate(CLASSES):
+        if kn[i] == 0:
+            continue
+        ent = {"ms_total": round(float(kms[i]), 3), "launches": int(kn[i]),
+               "avg_us": round(1000.0 * kms[i] / kn[i], 2)}
+        if name in per_iter:
+            gbs = per_iter[name] * iters_total / (kms[i] / 1000.0) / 1e9
+            ent["bytes_per_load_iter"] = per_iter[name]
+            ent["achieved_GBs"] = round(gbs, 1)
+        kernels[name] = ent
+    roof = None
+    timed = {k: v for k, v in kernels.items() if k in per_iter}
+    if timed:
+        dom = max(timed, key=lambda k: timed[k]["ms_total"])
+        e = timed[dom]
+        launches = e["launches"]
+        bytes_per_launch = per_iter[dom] * iters_total / launches
+        achieved = e["achieved_GBs"]
+        traffic = None
+        tpath = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+        if os.path.exists(tpath):
+            tr = json.load(open(tpath))
+            src = open(os.path.join(ROOT, "paper_2203_02962_amd", "csrc",
+                                    tr.get("source_file", "kop.hip")), "rb").read()
+            if (tr.get("kernel_class") == dom and tr.get("n") == args.n
+                    and tr.get("source_sha256") == hashlib.sha256(src).hexdigest()):
+                traffic = tr.get("bytes_per_launch")
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": dom, "bytes_per_launch": bytes_per_launch,
+                "avg_launch_us": e["avg_us"]}
+
+    golden = os.path.join(ROOT, "tests", "golden", f"elastic3d_spheres_{args.n}_seed0.json")
+    chom_err = None
+    if os.path.exists(golden):
+        g = json.load(open(golden))
+        Hg = np.array(g["C_hom"])
+        chom_err = float(np.abs(H - Hg).max() / np.abs(Hg).max())
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF·PCG-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"elastic3d_spheres {args.n}^3: trilinear hex, 8 Gauss points, "
+                         f"spheres r~U[6,12] vf {wl['vf']:.3f}, E ratio 100, nu 0.3, "
+                         f"6 unit Mandel loads, PCG to eta {args.eta:g}, Cref = mean"),
+            "n": args.n, "loads": 6, "dof": dof, "eta": args.eta,
+            "iterations": st["iterations"],
+            "setup_ms": round(st["setup_ms"], 2), "pcg_ms": round(st["solve_ms"], 2),
+            "chom_ms": round(st["chom_ms"], 2),
+            "time_to_1e-6_ms": {"plain_fp64": round(t_1e6, 2)},
+            "iterations_1e-6": st6["iterations"],
+            "chom_rel_err_vs_oracle": chom_err,
+        },
+        "kernels": kernels,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

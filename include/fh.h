@@ -72,6 +72,23 @@ extern "C" {
 
 #define FH_MAX_LOADS 32
 
+/* fh_opts.flags: record a HIP event pair on the solve stream around every
+ * kernel launch of the PCG loop and report per-class totals in fh_stats.   */
+#define FH_FLAG_TIME_KERNELS 1
+/* fh_opts.flags: rebuild the reference material, the Alg. 2 symbol and the
+ * right-hand sides even if the inputs have not changed since the last solve */
+#define FH_FLAG_REBUILD 2
+
+/* kernel classes of fh_stats.kernel_ms / kernel_launches                  */
+#define FH_K_OPERATOR 0   /* q = K p (+ p.q partials)                       */
+#define FH_K_XFWD 1       /* r -= alpha q, forward real FFT along x          */
+#define FH_K_YFWD 2       /* forward FFT along y                             */
+#define FH_K_ZSOLVE 3     /* FFT along z, K^+ block solve, r.z, inverse z    */
+#define FH_K_YINV 4       /* inverse FFT along y                             */
+#define FH_K_XINV 5       /* inverse real FFT along x, x += alpha p, p update */
+#define FH_K_SCALAR 6     /* single-block scalar updates (alpha, beta, stop) */
+#define FH_K_NCLASS 8
+
 typedef struct fh_ctx fh_ctx;
 
 typedef struct fh_opts {
@@ -79,7 +96,7 @@ typedef struct fh_opts {
   int itmax;        /* PCG iteration cap per load case (Alg. 1 it_max^CG)         */
   int precision;    /* FH_FP64 or FH_FP32_REFINED                                 */
   int poll;         /* iterations between host convergence polls (0 = default)   */
-  int reserved_i;   /* must be 0                                                  */
+  int flags;        /* FH_FLAG_* bits                                             */
   double eta_inner; /* inner FP32 tolerance for FH_FP32_REFINED (0 = default)    */
 } fh_opts;
 
@@ -93,6 +110,8 @@ typedef struct fh_stats {
   double solve_ms;              /* PCG loops of all load cases                    */
   double chom_ms;               /* homogenized-tensor reduction                   */
   long long dof;                /* nd * N                                         */
+  double kernel_ms[FH_K_NCLASS];      /* summed event-timed durations       */
+  long long kernel_launches[FH_K_NCLASS];
 } fh_stats;
 
 /* Context on HIP device `device`.  Returns FH_EDEVICE if it cannot be used. */

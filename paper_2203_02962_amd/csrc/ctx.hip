@@ -84,6 +84,17 @@ struct fh_ctx {
   bool layout_ok = false;
   int layout_nload = -1;
 
+  // live kernel timing (FH_FLAG_TIME_KERNELS): event pairs recorded on the
+  // solve stream around each launch, read back at every poll
+  struct KTimer {
+    bool on = false;
+    std::vector<hipEvent_t> ev;  // 2 per slot
+    std::vector<int> cls;
+    size_t used = 0;
+    double ms[FH_K_NCLASS] = {};
+    long long n[FH_K_NCLASS] = {};
+  } kt;
+
   bool symbol_ok = false;
   bool rhs_ok = false;
   bool solved = false;
@@ -582,6 +593,16 @@ int build_rhs(fh_ctx* c) {
   return FH_OK;
 }
 
+int kt_begin(fh_ctx* c, int cls);
+void kt_end(fh_ctx* c, int slot);
+void kt_collect(fh_ctx* c);
+#define KT(cls, stmt)                    \
+  do {                                   \
+    const int _slot = kt_begin(c, cls);  \
+    stmt;                                \
+    kt_end(c, _slot);                    \
+  } while (0)
+
 // ------------------------------------------------------------ FP64 PCG
 // Solves K x = b for nload right-hand sides held in L.b (or `bsrc`), result
 // in L.x.  Everything stays on the device; status polled every `poll`.
@@ -616,23 +637,30 @@ int pcg64(fh_ctx* c, int nload, double eta, int itmax, int poll, std::vector<fh:
   const int cap = itmax + 2;
   while (true) {
     for (int k = 0; k < poll && done_iters < cap; ++k, ++done_iters) {
-      int rc = apply_K(c, false, L.p, L.q, nload, F, L.st, L.pq_part);
+      int rc = 0;
+      KT(FH_K_OPERATOR, rc = apply_K(c, false, L.p, L.q, nload, F, L.st, L.pq_part));
       if (rc) return rc;
-      HIPCHK(c, fh::launch_finalize_alpha(L.st, L.pq_part, L.nb_kop, nload, c->stream));
-      HIPCHK(c, fh::launch_xfwd<double>(g, c->px, c->twx, fh::XF_UPDATE_R, L.r, F, L.q, F, L.A,
-                                        S, nload, L.st, c->stream));
-      HIPCHK(c, fh::launch_yfwd<double>(g, c->py, c->twy, L.A, L.B, S, nload, L.st, c->stream));
-      HIPCHK(c, fh::launch_zpass<double>(g, c->pz, c->twz, fh::Z_SOLVE, L.B, S, L.kplus, nload,
-                                         L.st, L.rz_part, &nbz, c->stream));
-      HIPCHK(c, fh::launch_finalize_beta(L.st, L.rz_part, nbz, nload, L.hist, L.hist_len,
-                                         c->stream));
-      HIPCHK(c, fh::launch_yinv<double>(g, c->py, c->twy, L.B, L.A, S, nload, L.st, c->stream));
-      HIPCHK(c, fh::launch_xinv<double>(g, c->px, c->twx, fh::XI_PCG, L.A, S, nullptr, L.x, L.p,
-                                        F, nload, L.st, c->stream));
+      KT(FH_K_SCALAR, HIPCHK(c, fh::launch_finalize_alpha(L.st, L.pq_part, L.nb_kop, nload,
+                                                          c->stream)));
+      KT(FH_K_XFWD, HIPCHK(c, fh::launch_xfwd<double>(g, c->px, c->twx, fh::XF_UPDATE_R, L.r, F,
+                                                      L.q, F, L.A, S, nload, L.st, c->stream)));
+      KT(FH_K_YFWD, HIPCHK(c, fh::launch_yfwd<double>(g, c->py, c->twy, L.A, L.B, S, nload, L.st,
+                                                      c->stream)));
+      KT(FH_K_ZSOLVE, HIPCHK(c, fh::launch_zpass<double>(g, c->pz, c->twz, fh::Z_SOLVE, L.B, S,
+                                                         L.kplus, nload, L.st, L.rz_part, &nbz,
+                                                         c->stream)));
+      KT(FH_K_SCALAR, HIPCHK(c, fh::launch_finalize_beta(L.st, L.rz_part, nbz, nload, L.hist,
+                                                         L.hist_len, c->stream)));
+      KT(FH_K_YINV, HIPCHK(c, fh::launch_yinv<double>(g, c->py, c->twy, L.B, L.A, S, nload, L.st,
+                                                      c->stream)));
+      KT(FH_K_XINV, HIPCHK(c, fh::launch_xinv<double>(g, c->px, c->twx, fh::XI_PCG, L.A, S,
+                                                      nullptr, L.x, L.p, F, nload, L.st,
+                                                      c->stream)));
     }
     HIPCHK(c, hipMemcpyAsync(hs.data(), L.st, sizeof(fh::PcgState) * nload,
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    kt_collect(c);
     bool any = false;
     for (auto& s : hs) any |= (s.status == fh::ST_ACTIVE);
     if (!any || done_iters >= cap) break;
@@ -683,6 +711,50 @@ int fill_stats(fh_ctx* c, const std::vector<fh::PcgState>& hs, int nload, fh_sta
   return rc;
 }
 
+int kt_begin(fh_ctx* c, int cls) {
+  fh_ctx::KTimer& t = c->kt;
+  if (!t.on) return -1;
+  if (t.used * 2 + 2 > t.ev.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return -1;
+    if (hipEventCreate(&b) != hipSuccess) {
+      hipEventDestroy(a);
+      return -1;
+    }
+    t.ev.push_back(a);
+    t.ev.push_back(b);
+    t.cls.push_back(0);
+  }
+  const int slot = (int)t.used++;
+  t.cls[slot] = cls;
+  hipEventRecord(t.ev[2 * slot], c->stream);
+  return slot;
+}
+
+void kt_end(fh_ctx* c, int slot) {
+  if (slot >= 0) hipEventRecord(c->kt.ev[2 * slot + 1], c->stream);
+}
+
+// after a stream synchronisation: fold the recorded pairs into the totals
+void kt_collect(fh_ctx* c) {
+  fh_ctx::KTimer& t = c->kt;
+  for (size_t i = 0; i < t.used; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.ev[2 * i], t.ev[2 * i + 1]) == hipSuccess) {
+      t.ms[t.cls[i]] += ms;
+      t.n[t.cls[i]] += 1;
+    }
+  }
+  t.used = 0;
+}
+
+struct KScope {
+  fh_ctx* c;
+  int slot;
+  KScope(fh_ctx* cc, int cls) : c(cc), slot(kt_begin(cc, cls)) {}
+  ~KScope() { kt_end(c, slot); }
+};
+
 double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -721,6 +793,7 @@ void fh_destroy(fh_ctx* c) {
   hipFree(c->twy);
   hipFree(c->twz);
   if (c->host_pinned) hipHostFree(c->host_pinned);
+  for (hipEvent_t e : c->kt.ev) hipEventDestroy(e);
   delete c;
 }
 
@@ -905,6 +978,13 @@ int fh_solve(fh_ctx* c, const fh_opts* opt, fh_stats* st) {
   const int poll = o.poll > 0 ? o.poll : 16;
   auto t0 = std::chrono::steady_clock::now();
   c->solved = false;
+  c->kt.on = (o.flags & FH_FLAG_TIME_KERNELS) != 0;
+  if (o.flags & FH_FLAG_REBUILD) c->symbol_ok = c->rhs_ok = false;
+  c->kt.used = 0;
+  for (int k = 0; k < FH_K_NCLASS; ++k) {
+    c->kt.ms[k] = 0.0;
+    c->kt.n[k] = 0;
+  }
   int rc = build_symbol(c);
   if (rc) return rc;
   rc = build_rhs(c);
@@ -964,11 +1044,12 @@ int fh_solve(fh_ctx* c, const fh_opts* opt, fh_stats* st) {
   c->last.setup_ms = setup_ms;
   c->last.solve_ms = solve_ms;
   c->last.chom_ms = chom_ms;
-  if (st) {
-    st->setup_ms = setup_ms;
-    st->solve_ms = solve_ms;
-    st->chom_ms = chom_ms;
+  for (int k = 0; k < FH_K_NCLASS; ++k) {
+    c->last.kernel_ms[k] = c->kt.ms[k];
+    c->last.kernel_launches[k] = c->kt.n[k];
   }
+  c->kt.on = false;
+  if (st) *st = c->last;
   return rc;
 }
 
@@ -1087,6 +1168,7 @@ int fh_solve_rhs(fh_ctx* c, const double* b_dev, double* u_dev, const fh_opts* o
     c->loads.assign(mdim(c), 0.0);
     c->rhs_ok = false;
   }
+  c->kt.on = false;
   int rc = build_symbol(c);
   if (rc) return rc;
   const long long F = (long long)c->g.nd * c->g.N;

@@ -21,6 +21,9 @@ FH_SCALAR, FH_ELASTIC = 0, 1
 FH_HEX8, FH_QUAD4, FH_TRI2 = 0, 1, 2
 FH_FP64, FH_FP32_REFINED = 0, 1
 FH_MAX_LOADS = 32
+FH_FLAG_TIME_KERNELS = 1
+FH_FLAG_REBUILD = 2
+KERNEL_CLASSES = ["operator", "xfwd", "yfwd", "zsolve", "yinv", "xinv", "scalar", "other"]
 
 ELEMENTS = {"hex8": FH_HEX8, "quad4": FH_QUAD4, "tri2": FH_TRI2}
 PROBLEMS = {"scalar": FH_SCALAR, "elastic": FH_ELASTIC}
@@ -37,7 +40,7 @@ EXPORTED = [
 class fh_opts(ctypes.Structure):
     _fields_ = [("eta", ctypes.c_double), ("itmax", ctypes.c_int),
                 ("precision", ctypes.c_int), ("poll", ctypes.c_int),
-                ("reserved_i", ctypes.c_int), ("eta_inner", ctypes.c_double)]
+                ("flags", ctypes.c_int), ("eta_inner", ctypes.c_double)]
 
 
 class fh_stats(ctypes.Structure):
@@ -47,14 +50,16 @@ class fh_stats(ctypes.Structure):
                 ("rel_res", ctypes.c_double * FH_MAX_LOADS),
                 ("outer", ctypes.c_int * FH_MAX_LOADS),
                 ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
-                ("chom_ms", ctypes.c_double), ("dof", ctypes.c_longlong)]
+                ("chom_ms", ctypes.c_double), ("dof", ctypes.c_longlong),
+                ("kernel_ms", ctypes.c_double * 8), ("kernel_launches", ctypes.c_longlong * 8)]
 
     def as_dict(self):
         n = self.nload
         return dict(nload=n, iterations=list(self.iterations[:n]), status=list(self.status[:n]),
                     rel_res=list(self.rel_res[:n]), outer=list(self.outer[:n]),
                     setup_ms=self.setup_ms, solve_ms=self.solve_ms, chom_ms=self.chom_ms,
-                    dof=self.dof)
+                    dof=self.dof, kernel_ms=list(self.kernel_ms),
+                    kernel_launches=list(self.kernel_launches))
 
 
 _lib = None
@@ -205,11 +210,13 @@ class Context:
 
     # ----------------------------------------------------------------- solve
     @staticmethod
-    def opts(eta=1e-10, itmax=10000, precision=FH_FP64, poll=0, eta_inner=0.0):
-        return fh_opts(eta, itmax, precision, poll, 0, eta_inner)
+    def opts(eta=1e-10, itmax=10000, precision=FH_FP64, poll=0, eta_inner=0.0, flags=0):
+        return fh_opts(eta, itmax, precision, poll, flags, eta_inner)
 
-    def solve(self, eta=1e-10, itmax=10000, precision=FH_FP64, poll=0, eta_inner=0.0):
-        o = self.opts(eta, itmax, precision, poll, eta_inner)
+    def solve(self, eta=1e-10, itmax=10000, precision=FH_FP64, poll=0, eta_inner=0.0,
+              time_kernels=False, rebuild=False):
+        flags = (FH_FLAG_TIME_KERNELS if time_kernels else 0) | (FH_FLAG_REBUILD if rebuild else 0)
+        o = self.opts(eta, itmax, precision, poll, eta_inner, flags)
         st = fh_stats()
         rc = self._check(self.lib.fh_solve(self.ptr, ctypes.byref(o), ctypes.byref(st)),
                          allow_warning=True)
