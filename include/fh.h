@@ -125,8 +125,8 @@ int fh_set_stream(fh_ctx *ctx, void *hip_stream);
 /* Grid and discretisation (Sec. 3).  dim = 2 or 3; n[2] ignored (taken as 1)
  * in 2D; l = cell edge lengths (NULL = all 1).  problem = FH_SCALAR or
  * FH_ELASTIC; element = FH_HEX8 (dim 3) or FH_QUAD4 / FH_TRI2 (dim 2).
- * nx and ny must be even; every n must be a product of 2, 3 and 5 and at
- * most 512.  Invalidates phases, loads and results.                          */
+ * nx and ny must be even; every n must be a product of 2 and 3 and at
+ * most 256.  Invalidates phases, loads and results.                          */
 int fh_set_grid(fh_ctx *ctx, int dim, const int n[3], const double l[3], int problem,
                 int element);
 

@@ -39,6 +39,7 @@ struct fh_ctx {
   cplx<double>* twz = nullptr;
 
   int mat_kind = 0;  // 0 none, 1 phases, 2 conductivity field
+  bool phases_checked = false;
   const uint8_t* phase_dev = nullptr;
   const double* kfield_dev = nullptr;
   int nphase = 0;
@@ -61,6 +62,12 @@ struct fh_ctx {
   double* ref_dev = nullptr;   // Kref operator tables
   double* fe_dev = nullptr;    // RHS element forces
   size_t mat_dev_n = 0, ref_dev_n = 0, fe_dev_n = 0;
+  // isotropic hex8 elasticity: {V lambda, 2 V mu} per phase (and for Cref)
+  bool iso = false, ref_iso = false;
+  double* lm_dev = nullptr;
+  float* lm_dev_f = nullptr;
+  double* ref_lm_dev = nullptr;
+  size_t lm_dev_n = 0, ref_lm_dev_n = 0;
   unsigned long long* counts_dev = nullptr;
   int* flag_dev = nullptr;
   double* host_pinned = nullptr;  // pinned staging
@@ -127,7 +134,6 @@ bool factor_ok(int n) {
   if (n < 1) return false;
   while (n % 2 == 0) n /= 2;
   while (n % 3 == 0) n /= 3;
-  while (n % 5 == 0) n /= 5;
   return n == 1;
 }
 
@@ -136,10 +142,10 @@ fh::AxisPlan make_plan(int n) {
   p.n = n;
   int m = n;
   auto push = [&](unsigned r) { p.code |= r << (4 * p.nstage); ++p.nstage; };
+  while (m % 8 == 0) { push(8); m /= 8; }
   while (m % 4 == 0) { push(4); m /= 4; }
   while (m % 2 == 0) { push(2); m /= 2; }
   while (m % 3 == 0) { push(3); m /= 3; }
-  while (m % 5 == 0) { push(5); m /= 5; }
   return p;
 }
 
@@ -308,6 +314,11 @@ bool cholesky_ok(const std::vector<double>& A, int m) {
 bool hex_elastic(const fh_ctx* c) { return c->element == FH_HEX8 && c->problem == FH_ELASTIC; }
 
 void free_tables(fh_ctx* c) {
+  hipFree(c->lm_dev); c->lm_dev = nullptr;
+  hipFree(c->lm_dev_f); c->lm_dev_f = nullptr;
+  hipFree(c->ref_lm_dev); c->ref_lm_dev = nullptr;
+  c->lm_dev_n = c->ref_lm_dev_n = 0;
+  c->iso = c->ref_iso = false;
   hipFree(c->mat_dev); c->mat_dev = nullptr;
   hipFree(c->mat_dev_f); c->mat_dev_f = nullptr;
   hipFree(c->ref_dev); c->ref_dev = nullptr;
@@ -331,6 +342,25 @@ std::vector<double> operator_tables(const fh_ctx* c, const double* mats, int cou
     out.insert(out.end(), K.begin(), K.end());
   }
   return out;
+}
+
+// Isotropic Mandel stiffness C = lambda 1(x)1 + 2 mu I?  Returns
+// {V lambda, 2 V mu} in lm when it is (to 1e-13 of the largest entry).
+bool isotropic_lm(const double* C, double Vp, double lm[2]) {
+  double mx = 0;
+  for (int i = 0; i < 36; ++i) mx = std::max(mx, std::fabs(C[i]));
+  const double lam = C[0 * 6 + 1], mu2 = C[3 * 6 + 3];
+  const double tol = 1e-13 * mx;
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) {
+      double want = 0.0;
+      if (i < 3 && j < 3) want = lam + (i == j ? mu2 : 0.0);
+      else if (i == j) want = mu2;
+      if (std::fabs(C[i * 6 + j] - want) > tol) return false;
+    }
+  lm[0] = Vp * lam;
+  lm[1] = Vp * mu2;
+  return true;
 }
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -442,12 +472,17 @@ int upload(fh_ctx* c, double** dst, size_t* dst_n, const std::vector<double>& v)
 // Apply K (or Kref when `ref`) to nload fields (double).
 int apply_K(fh_ctx* c, bool ref, const double* u, double* q, int nload, long long stride,
             const fh::PcgState* st, double* pq) {
-  const fh::Grid& g = c->g;
+  fh::Grid g = c->g;
+  g.nphase_max = (!ref && c->mat_kind == 1) ? c->nphase : 1;
   const uint8_t* ph = ref ? c->L.phase0 : (c->mat_kind == 1 ? c->phase_dev : nullptr);
   const double* kf = ref ? nullptr : (c->mat_kind == 2 ? c->kfield_dev : nullptr);
   const double* tab = ref ? c->ref_dev : c->mat_dev;
   int nb = 0;
-  if (hex_elastic(c)) {
+  if (hex_elastic(c) && (ref ? c->ref_iso : c->iso)) {
+    const double* lm = ref ? c->ref_lm_dev : c->lm_dev;
+    HIPCHK(c, fh::launch_kop_hex8_iso<double>(g, u, q, ph, lm, nload, stride, stride, st, pq,
+                                              &nb, c->stream));
+  } else if (hex_elastic(c)) {
     HIPCHK(c, fh::launch_kop_hex8_elastic<double>(g, u, q, ph, tab, nload, stride, stride, st,
                                                   pq, &nb, c->stream));
   } else {
@@ -460,10 +495,14 @@ int apply_K(fh_ctx* c, bool ref, const double* u, double* q, int nload, long lon
 
 int apply_K32(fh_ctx* c, const float* u, float* q, int nload, long long stride,
               const fh::PcgState* st, double* pq) {
-  const fh::Grid& g = c->g;
+  fh::Grid g = c->g;
+  g.nphase_max = c->mat_kind == 1 ? c->nphase : 1;
   const uint8_t* ph = c->mat_kind == 1 ? c->phase_dev : nullptr;
   int nb = 0;
-  if (hex_elastic(c)) {
+  if (hex_elastic(c) && c->iso) {
+    HIPCHK(c, fh::launch_kop_hex8_iso<float>(g, u, q, ph, c->lm_dev_f, nload, stride, stride,
+                                             st, pq, &nb, c->stream));
+  } else if (hex_elastic(c)) {
     HIPCHK(c, fh::launch_kop_hex8_elastic<float>(g, u, q, ph, c->mat_dev_f, nload, stride,
                                                  stride, st, pq, &nb, c->stream));
   } else {
@@ -493,6 +532,18 @@ int precond_fields(fh_ctx* c, double* r, double* out, int nload, long long fstri
 int check_material(fh_ctx* c) {
   if (!c->has_grid) return fail(c, FH_ESTATE, "fh_set_grid not called");
   if (c->mat_kind == 0) return fail(c, FH_ESTATE, "no material set");
+  if (c->mat_kind == 1 && !c->phases_checked) {
+    // every phase id must index a table before any kernel reads the tables
+    HIPCHK(c, hipMemsetAsync(c->flag_dev, 0, sizeof(int), c->stream));
+    HIPCHK(c, hipMemsetAsync(c->counts_dev, 0, 256 * sizeof(unsigned long long), c->stream));
+    HIPCHK(c, fh::launch_phase_count(c->phase_dev, c->g.N, c->nphase, c->counts_dev, c->flag_dev,
+                                     c->stream));
+    int bad = 0;
+    HIPCHK(c, hipMemcpyAsync(&bad, c->flag_dev, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (bad) return fail(c, FH_EINVAL, "phase id >= nphase in phase field");
+    c->phases_checked = true;
+  }
   return FH_OK;
 }
 
@@ -537,6 +588,15 @@ int build_symbol(fh_ctx* c) {
   if (!cholesky_ok(c->cref, m)) return fail(c, FH_ENOTSPD, "reference material is not SPD");
   rc = upload(c, &c->ref_dev, &c->ref_dev_n, operator_tables(c, c->cref.data(), 1));
   if (rc) return rc;
+  c->ref_iso = false;
+  if (hex_elastic(c)) {
+    std::vector<double> lm(2);
+    if (isotropic_lm(c->cref.data(), voxel_volume(c), lm.data())) {
+      rc = upload(c, &c->ref_lm_dev, &c->ref_lm_dev_n, lm);
+      if (rc) return rc;
+      c->ref_iso = true;
+    }
+  }
   // Alg. 2: impulse responses of Kref, forward FFT, per-frequency inverse
   const long long F = (long long)g.nd * g.N;
   const long long S = (long long)g.nd * g.nxh * g.ny * g.nz;
@@ -816,8 +876,8 @@ int fh_set_grid(fh_ctx* c, int dim, const int n[3], const double l[3], int probl
     return fail(c, FH_EINVAL, "element does not match dim");
   int nn[3] = {n[0], n[1], dim == 3 ? n[2] : 1};
   for (int k = 0; k < 3; ++k)
-    if (nn[k] < 1 || nn[k] > 512 || !factor_ok(nn[k]))
-      return fail(c, FH_EINVAL, "grid sizes must be products of 2, 3, 5 and at most 512");
+    if (nn[k] < 1 || nn[k] > 256 || !factor_ok(nn[k]))
+      return fail(c, FH_EINVAL, "grid sizes must be products of 2 and 3 and at most 256");
   if (nn[0] % 2 || nn[1] % 2) return fail(c, FH_EINVAL, "nx and ny must be even");
   if (dim == 3 && nn[2] < 2) return fail(c, FH_EINVAL, "nz must be >= 2 in 3D");
   for (int k = 0; k < dim; ++k)
@@ -830,6 +890,7 @@ int fh_set_grid(fh_ctx* c, int dim, const int n[3], const double l[3], int probl
   c->g.nd = problem == FH_ELASTIC ? dim : 1;
   c->g.nxh = nn[0] / 2 + 1;
   c->g.N = (long long)nn[0] * nn[1] * nn[2];
+  c->g.nphase_max = 1;
   for (int k = 0; k < 3; ++k) {
     c->l[k] = (l && k < dim) ? l[k] : 1.0;
     c->g.h[k] = c->l[k] / nn[k];
@@ -875,13 +936,31 @@ int fh_set_phases(fh_ctx* c, const uint8_t* phase_dev, int nphase, const double*
       }
   c->phase_dev = phase_dev;
   c->nphase = nphase;
+  c->g.nphase_max = nphase;
+  c->phases_checked = false;
   c->mat.assign(mat, mat + (size_t)nphase * m * m);
   c->kfield_dev = nullptr;
   c->mat_kind = 1;
   std::vector<double> tab = operator_tables(c, c->mat.data(), nphase);
   int rc = upload(c, &c->mat_dev, &c->mat_dev_n, tab);
   if (rc) return rc;
+  c->iso = false;
   if (hex_elastic(c)) {
+    std::vector<double> lm(2 * (size_t)nphase);
+    bool all = true;
+    for (int p = 0; p < nphase && all; ++p)
+      all = isotropic_lm(c->mat.data() + (size_t)p * 36, voxel_volume(c), lm.data() + 2 * p);
+    if (all) {
+      rc = upload(c, &c->lm_dev, &c->lm_dev_n, lm);
+      if (rc) return rc;
+      hipFree(c->lm_dev_f);
+      c->lm_dev_f = nullptr;
+      std::vector<float> lf(lm.begin(), lm.end());
+      HIPCHK(c, hipMalloc((void**)&c->lm_dev_f, lf.size() * sizeof(float)));
+      HIPCHK(c, hipMemcpy(c->lm_dev_f, lf.data(), lf.size() * sizeof(float),
+                          hipMemcpyHostToDevice));
+      c->iso = true;
+    }
     hipFree(c->mat_dev_f);
     c->mat_dev_f = nullptr;
     std::vector<float> tf(tab.begin(), tab.end());

@@ -28,7 +28,6 @@
 namespace fh {
 
 constexpr int kRows = 16;   // rows per block in x passes (8 complex lines)
-constexpr int kZB = 16;     // lines per block in y passes
 constexpr int kThreads = 256;
 
 template <typename T>
@@ -52,6 +51,25 @@ __device__ __forceinline__ void dft_small(cplx<T>* x, int s) {
     x[2] = csub(a0, b0);
     x[1] = cadd(a1, b1);
     x[3] = csub(a1, b1);
+  } else if constexpr (R == 8) {
+    // 8 = 2 x 4: two radix-4 on even/odd samples, twiddles w8^k, radix-2
+    const T h = T(0.70710678118654752440084436210485);
+    cplx<T> e[4] = {x[0], x[2], x[4], x[6]};
+    cplx<T> o[4] = {x[1], x[3], x[5], x[7]};
+    dft_small<T, 4>(e, s);
+    dft_small<T, 4>(o, s);
+    // o[k] *= exp(s 2 pi i k / 8)
+    cplx<T> o1 = {h * (o[1].re - s * o[1].im), h * (o[1].im + s * o[1].re)};
+    cplx<T> o2 = muli(o[2], s);
+    cplx<T> o3 = {h * (-o[3].re - s * o[3].im), h * (-o[3].im + s * o[3].re)};
+    x[0] = cadd(e[0], o[0]);
+    x[4] = csub(e[0], o[0]);
+    x[1] = cadd(e[1], o1);
+    x[5] = csub(e[1], o1);
+    x[2] = cadd(e[2], o2);
+    x[6] = csub(e[2], o2);
+    x[3] = cadd(e[3], o3);
+    x[7] = csub(e[3], o3);
   } else if constexpr (R == 3) {
     const T h = T(0.86602540378443864676372317075294);  // sqrt(3)/2
     cplx<T> t1 = cadd(x[1], x[2]), t2 = csub(x[1], x[2]);
@@ -79,59 +97,73 @@ __device__ __forceinline__ void dft_small(cplx<T>* x, int s) {
   }
 }
 
-// One Stockham stage on `nlines` lines of length n (line stride n) from `in`
-// to `out`; L = product of the radices of the earlier stages.
+// One in-place Stockham stage on `nlines` lines of length n (line stride n):
+// every thread first reads its butterflies' inputs into registers, the
+// block synchronises, then the results are written back.  L = product of the
+// radices of the earlier stages.  A block holds at most kMaxPts points, so a
+// thread owns at most kMaxPts / (R * 256) butterflies.
+constexpr int kMaxPts = 2048;
+
 template <typename T, int R>
-__device__ __forceinline__ void stockham_stage(const cplx<T>* in, cplx<T>* out, int n,
-                                               int nlines, int L, const cplx<T>* tw,
-                                               int sign) {
+__device__ __forceinline__ void stockham_stage(cplx<T>* buf, int n, int nlines, int L,
+                                               const cplx<T>* tw, int sign) {
+  constexpr int MAXIT = (kMaxPts / R + kThreads - 1) / kThreads;
   const int m = n / R;
   const int items = nlines * m;
   const int twstep = n / (L * R);
-  for (int it = threadIdx.x; it < items; it += blockDim.x) {
-    const int line = it / m;
-    const int j = it - line * m;
-    const int k = j % L;
-    const cplx<T>* src = in + (size_t)line * n;
-    cplx<T> v[R];
+  cplx<T> v[MAXIT][R];
+  int dst[MAXIT];
 #pragma unroll
-    for (int t = 0; t < R; ++t) {
-      cplx<T> a = src[j + t * m];
-      if (t > 0) {
-        // t*k < R*L, so the index stays below n
-        cplx<T> w = tw[t * k * twstep];
-        if (sign > 0) w.im = -w.im;
-        a = cmul(a, w);
+  for (int k = 0; k < MAXIT; ++k) {
+    const int it = threadIdx.x + k * kThreads;
+    dst[k] = -1;
+    if (it < items) {
+      const int line = it / m;
+      const int j = it - line * m;
+      const int kk = j % L;
+      const cplx<T>* src = buf + line * n;
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        cplx<T> a = src[j + t * m];
+        if (t > 0) {
+          // t*kk < R*L, so the index stays below n
+          cplx<T> w = tw[t * kk * twstep];
+          if (sign > 0) w.im = -w.im;
+          a = cmul(a, w);
+        }
+        v[k][t] = a;
       }
-      v[t] = a;
+      dst[k] = line * n + (j / L) * L * R + kk;
     }
-    dft_small<T, R>(v, sign);
-    cplx<T>* dst = out + (size_t)line * n + (j / L) * L * R + k;
-#pragma unroll
-    for (int t = 0; t < R; ++t) dst[t * L] = v[t];
   }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < MAXIT; ++k) {
+    if (dst[k] >= 0) {
+      dft_small<T, R>(v[k], sign);
+#pragma unroll
+      for (int t = 0; t < R; ++t) buf[dst[k] + t * L] = v[k][t];
+    }
+  }
+  __syncthreads();
 }
 
-// Runs all stages; returns the buffer holding the result.  Caller must have
-// synchronised after filling `a`; returns after a final barrier.
-template <typename T>
-__device__ cplx<T>* fft_lines(cplx<T>* a, cplx<T>* b, const AxisPlan& plan, int nlines,
-                              const cplx<T>* tw, int sign) {
+// Runs all stages in place on `a` (caller synchronised after filling it);
+// returns `a` after a final barrier.
+// P3: the length has a factor 3 (radix-3 stages compiled in).  Lengths are
+// products of 2 and 3 only.
+template <typename T, bool P3>
+__device__ cplx<T>* fft_lines(cplx<T>* a, const AxisPlan& plan, int nlines, const cplx<T>* tw,
+                              int sign) {
   int L = 1;
   const int n = plan.n;
   for (int st = 0; st < plan.nstage; ++st) {
     const int R = (plan.code >> (4 * st)) & 15u;
-    switch (R) {
-      case 4: stockham_stage<T, 4>(a, b, n, nlines, L, tw, sign); break;
-      case 2: stockham_stage<T, 2>(a, b, n, nlines, L, tw, sign); break;
-      case 3: stockham_stage<T, 3>(a, b, n, nlines, L, tw, sign); break;
-      default: stockham_stage<T, 5>(a, b, n, nlines, L, tw, sign); break;
-    }
+    if (R == 8) stockham_stage<T, 8>(a, n, nlines, L, tw, sign);
+    else if (R == 4) stockham_stage<T, 4>(a, n, nlines, L, tw, sign);
+    else if (R == 2) stockham_stage<T, 2>(a, n, nlines, L, tw, sign);
+    else if constexpr (P3) stockham_stage<T, 3>(a, n, nlines, L, tw, sign);
     L *= R;
-    __syncthreads();
-    cplx<T>* t = a;
-    a = b;
-    b = t;
   }
   return a;
 }
@@ -161,7 +193,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // ------------------------------------------------------------- x forward
 // grid (ceil(ny/16), nz, nload*nd).  Optionally r -= alpha q first.
-template <typename T>
+template <typename T, bool P3>
 __global__ void __launch_bounds__(kThreads) k_xfwd(Grid g, AxisPlan px, const cplx<double>* twx,
                                                   int mode, T* r, long long rstride, const T* q,
                                                   long long qstride, cplx<T>* A,
@@ -172,7 +204,6 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(Grid g, AxisPlan px, const cp
   const int nx = g.nx, ny = g.ny, nxh = g.nxh;
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* a = tw + nx;
-  cplx<T>* b = a + (kRows / 2) * nx;
   load_twiddles(tw, twx, nx);
   const int y0 = blockIdx.x * kRows, z = blockIdx.y;
   const long long rbase = (long long)ld * rstride + ((long long)c * g.nz + z) * ny * nx;
@@ -193,7 +224,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(Grid g, AxisPlan px, const cp
     if (row & 1) d.im = v; else d.re = v;
   }
   __syncthreads();
-  cplx<T>* res = fft_lines(a, b, px, kRows / 2, tw, -1);
+  cplx<T>* res = fft_lines<T, P3>(a, px, kRows / 2, tw, -1);
   const long long abase = (long long)ld * sstride + ((long long)c * g.nz + z) * nxh * ny;
   for (int idx = threadIdx.x; idx < kRows * nxh; idx += blockDim.x) {
     const int yl = idx % kRows, kx = idx / kRows, y = y0 + yl;
@@ -214,10 +245,10 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(Grid g, AxisPlan px, const cp
 }
 
 // ------------------------------------------------------------- y forward
-// grid (ceil(nz/16), nxh, nload*nd)
-template <typename T>
+// grid (ceil(nz/zb), nxh, nload*nd); zb lines per block, zb*ny <= kMaxPts
+template <typename T, bool P3>
 __global__ void __launch_bounds__(kThreads) k_yfwd(Grid g, AxisPlan py, const cplx<double>* twy,
-                                                  const cplx<T>* A, cplx<T>* B,
+                                                  int zb, const cplx<T>* A, cplx<T>* B,
                                                   long long sstride, const PcgState* st) {
   const int ld = blockIdx.z / g.nd, c = blockIdx.z % g.nd;
   if (load_status(st, ld) != ST_ACTIVE) return;
@@ -225,28 +256,27 @@ __global__ void __launch_bounds__(kThreads) k_yfwd(Grid g, AxisPlan py, const cp
   const int ny = g.ny, nz = g.nz, nxh = g.nxh;
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* a = tw + ny;
-  cplx<T>* b = a + kZB * ny;
   load_twiddles(tw, twy, ny);
-  const int z0 = blockIdx.x * kZB, kx = blockIdx.y;
+  const int z0 = blockIdx.x * zb, kx = blockIdx.y;
   const long long base = (long long)ld * sstride;
-  for (int idx = threadIdx.x; idx < kZB * ny; idx += blockDim.x) {
+  for (int idx = threadIdx.x; idx < zb * ny; idx += blockDim.x) {
     const int zl = idx / ny, y = idx - zl * ny, z = z0 + zl;
     cplx<T> v = {T(0), T(0)};
     if (z < nz) v = A[base + (((long long)c * nz + z) * nxh + kx) * ny + y];
     a[idx] = v;
   }
   __syncthreads();
-  cplx<T>* res = fft_lines(a, b, py, kZB, tw, -1);
+  cplx<T>* res = fft_lines<T, P3>(a, py, zb, tw, -1);
   const long long obase = base + ((long long)c * nxh + kx) * (long long)ny * nz;
-  for (int idx = threadIdx.x; idx < kZB * ny; idx += blockDim.x) {
-    const int zl = idx % kZB, ky = idx / kZB, z = z0 + zl;
+  for (int idx = threadIdx.x; idx < zb * ny; idx += blockDim.x) {
+    const int zl = idx % zb, ky = idx / zb, z = z0 + zl;
     if (z < nz) B[obase + (long long)ky * nz + z] = res[zl * ny + ky];
   }
 }
 
 // ------------------------------------------------ z forward (+ solve + inverse)
 // grid (ceil(ny/kyb), nxh, nload).  Dynamic LDS: tw[nz], a/b[nd*kyb*nz].
-template <typename T>
+template <typename T, bool P3>
 __global__ void __launch_bounds__(kThreads) k_zpass(Grid g, AxisPlan pz, const cplx<double>* twz,
                                                    int mode, int kyb, cplx<T>* B,
                                                    long long sstride, const T* kplus,
@@ -259,7 +289,6 @@ __global__ void __launch_bounds__(kThreads) k_zpass(Grid g, AxisPlan pz, const c
   const int ny = g.ny, nz = g.nz, nxh = g.nxh, nd = g.nd;
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* a = tw + nz;
-  cplx<T>* b = a + nd * kyb * nz;
   load_twiddles(tw, twz, nz);
   const int ky0 = blockIdx.x * kyb, kx = blockIdx.y;
   const long long cstride = (long long)nxh * ny * nz;
@@ -273,8 +302,7 @@ __global__ void __launch_bounds__(kThreads) k_zpass(Grid g, AxisPlan pz, const c
     a[idx] = v;
   }
   __syncthreads();
-  cplx<T>* res = fft_lines(a, b, pz, nd * kyb, tw, -1);
-  cplx<T>* other = (res == a) ? b : a;
+  cplx<T>* res = fft_lines<T, P3>(a, pz, nd * kyb, tw, -1);
   double part = 0.0;
   if (mode == Z_SOLVE) {
     const long long nfreq = (long long)nxh * ny * nz;
@@ -318,7 +346,7 @@ __global__ void __launch_bounds__(kThreads) k_zpass(Grid g, AxisPlan pz, const c
       }
     }
     __syncthreads();
-    res = fft_lines(res, other, pz, nd * kyb, tw, +1);
+    res = fft_lines<T, P3>(res, pz, nd * kyb, tw, +1);
   }
   for (int idx = threadIdx.x; idx < nd * per; idx += blockDim.x) {
     const int c = idx / per, rem = idx - c * per, kyl = rem / nz, z = rem - kyl * nz;
@@ -335,9 +363,9 @@ __global__ void __launch_bounds__(kThreads) k_zpass(Grid g, AxisPlan pz, const c
 }
 
 // ------------------------------------------------------------- y inverse
-template <typename T>
+template <typename T, bool P3>
 __global__ void __launch_bounds__(kThreads) k_yinv(Grid g, AxisPlan py, const cplx<double>* twy,
-                                                  const cplx<T>* B, cplx<T>* A,
+                                                  int zb, const cplx<T>* B, cplx<T>* A,
                                                   long long sstride, const PcgState* st) {
   const int ld = blockIdx.z / g.nd, c = blockIdx.z % g.nd;
   if (load_status(st, ld) != ST_ACTIVE) return;
@@ -345,29 +373,27 @@ __global__ void __launch_bounds__(kThreads) k_yinv(Grid g, AxisPlan py, const cp
   const int ny = g.ny, nz = g.nz, nxh = g.nxh;
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* a = tw + ny;
-  cplx<T>* b = a + kZB * ny;
   load_twiddles(tw, twy, ny);
-  const int z0 = blockIdx.x * kZB, kx = blockIdx.y;
+  const int z0 = blockIdx.x * zb, kx = blockIdx.y;
   const long long base = (long long)ld * sstride;
   const long long ibase = base + ((long long)c * nxh + kx) * (long long)ny * nz;
-  for (int idx = threadIdx.x; idx < kZB * ny; idx += blockDim.x) {
-    const int zl = idx % kZB, ky = idx / kZB, z = z0 + zl;
+  for (int idx = threadIdx.x; idx < zb * ny; idx += blockDim.x) {
+    const int zl = idx % zb, ky = idx / zb, z = z0 + zl;
     cplx<T> v = {T(0), T(0)};
     if (z < nz) v = B[ibase + (long long)ky * nz + z];
     a[zl * ny + ky] = v;
   }
   __syncthreads();
-  cplx<T>* res = fft_lines(a, b, py, kZB, tw, +1);
-  for (int idx = threadIdx.x; idx < kZB * ny; idx += blockDim.x) {
+  cplx<T>* res = fft_lines<T, P3>(a, py, zb, tw, +1);
+  for (int idx = threadIdx.x; idx < zb * ny; idx += blockDim.x) {
     const int zl = idx / ny, y = idx - zl * ny, z = z0 + zl;
     if (z < nz) A[base + (((long long)c * nz + z) * nxh + kx) * ny + y] = res[idx];
   }
 }
 
 // ------------------------------------------------------------- x inverse
-// grid (ceil(ny/16), nz, nload*nd).  LDS: tw[nx], a[8 nx], b[8 nx + 16]
-// (b first holds the 16 x nxh input tile).
-template <typename T>
+// grid (ceil(ny/16), nz, nload*nd).  LDS: tw[nx], a[8 nx], S[16 nxh].
+template <typename T, bool P3>
 __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cplx<double>* twx,
                                                   int mode, const cplx<T>* A, long long sstride,
                                                   T* out, T* x, T* p, long long fstride,
@@ -392,8 +418,7 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* a = tw + nx;
-  cplx<T>* b = a + (kRows / 2) * nx;
-  cplx<T>* S = b;  // 16 x nxh raw tile
+  cplx<T>* S = a + (kRows / 2) * nx;  // 16 x nxh raw tile
   load_twiddles(tw, twx, nx);
   const long long abase = (long long)ld * sstride + ((long long)c * g.nz + z) * nxh * ny;
   for (int idx = threadIdx.x; idx < kRows * nxh; idx += blockDim.x) {
@@ -421,7 +446,7 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
     a[idx] = {xa.re - xb.im, xa.im + xb.re};
   }
   __syncthreads();
-  cplx<T>* res = fft_lines(a, b, px, kRows / 2, tw, +1);
+  cplx<T>* res = fft_lines<T, P3>(a, px, kRows / 2, tw, +1);
   const T alpha = (mode == XI_PCG) ? T(st[ld].alpha) : T(0);
   const T beta = (mode == XI_PCG) ? T(st[ld].beta) : T(0);
   for (int idx = threadIdx.x; idx < kRows * nx; idx += blockDim.x) {
@@ -506,36 +531,51 @@ template <typename T>
 hipError_t launch_xfwd(const Grid& g, const AxisPlan& px, const cplx<double>* twx, int mode,
                        T* r, long long rstride, const T* q, long long qstride, cplx<T>* A,
                        long long sstride, int nload, const PcgState* st, hipStream_t s) {
+  const bool P3K = px.n % 3 == 0;
   dim3 grid((g.ny + kRows - 1) / kRows, g.nz, nload * g.nd);
-  size_t lds = sizeof(cplx<T>) * (size_t)(g.nx + kRows * g.nx);
+  size_t lds = sizeof(cplx<T>) * (size_t)(g.nx + (kRows / 2) * g.nx);
   if (lds > 65536)
-    hipFuncSetAttribute((const void*)k_xfwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipFuncSetAttribute(P3K ? (const void*)k_xfwd<T, true> : (const void*)k_xfwd<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
-  hipLaunchKernelGGL(k_xfwd<T>, grid, dim3(kThreads), lds, s, g, px, twx, mode, r, rstride, q,
+  if (P3K)
+    hipLaunchKernelGGL((k_xfwd<T, true>), grid, dim3(kThreads), lds, s, g, px, twx, mode, r, rstride, q,
+                     qstride, A, sstride, st);
+  else
+    hipLaunchKernelGGL((k_xfwd<T, false>), grid, dim3(kThreads), lds, s, g, px, twx, mode, r, rstride, q,
                      qstride, A, sstride, st);
   return hipGetLastError();
+}
+
+static int ypass_zb(const Grid& g) {
+  int zb = kMaxPts / g.ny;
+  if (zb > 16) zb = 16;
+  if (zb < 1) zb = 1;
+  return zb;
 }
 
 template <typename T>
 hipError_t launch_yfwd(const Grid& g, const AxisPlan& py, const cplx<double>* twy,
                        const cplx<T>* A, cplx<T>* B, long long sstride, int nload,
                        const PcgState* st, hipStream_t s) {
-  dim3 grid((g.nz + kZB - 1) / kZB, g.nxh, nload * g.nd);
-  size_t lds = sizeof(cplx<T>) * (size_t)(g.ny + 2 * kZB * g.ny);
+  const bool P3K = py.n % 3 == 0;
+  const int zb = ypass_zb(g);
+  dim3 grid((g.nz + zb - 1) / zb, g.nxh, nload * g.nd);
+  size_t lds = sizeof(cplx<T>) * (size_t)(g.ny + zb * g.ny);
   if (lds > 65536)
-    hipFuncSetAttribute((const void*)k_yfwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipFuncSetAttribute(P3K ? (const void*)k_yfwd<T, true> : (const void*)k_yfwd<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
-  hipLaunchKernelGGL(k_yfwd<T>, grid, dim3(kThreads), lds, s, g, py, twy, A, B, sstride, st);
+  if (P3K)
+    hipLaunchKernelGGL((k_yfwd<T, true>), grid, dim3(kThreads), lds, s, g, py, twy, zb, A, B, sstride, st);
+  else
+    hipLaunchKernelGGL((k_yfwd<T, false>), grid, dim3(kThreads), lds, s, g, py, twy, zb, A, B, sstride, st);
   return hipGetLastError();
 }
 
 template <typename T>
 static int zpass_kyb(const Grid& g) {
-  const size_t budget = 48 * 1024;
-  size_t per = 2 * (size_t)g.nd * g.nz * sizeof(cplx<T>);
-  int kyb = (int)(budget / per);
-  if (kyb < 1) kyb = 1;
+  int kyb = kMaxPts / (g.nd * g.nz);
   if (kyb > 16) kyb = 16;
+  if (kyb < 1) kyb = 1;
   if (kyb > g.ny) kyb = g.ny;
   return kyb;
 }
@@ -552,11 +592,19 @@ template <typename T>
 hipError_t launch_zpass(const Grid& g, const AxisPlan& pz, const cplx<double>* twz, int mode,
                         cplx<T>* B, long long sstride, const T* kplus, int nload,
                         const PcgState* st, double* rz_part, int* nblocks_out, hipStream_t s) {
+  const bool P3K = pz.n % 3 == 0;
   const int kyb = zpass_kyb<T>(g);
   dim3 grid((g.ny + kyb - 1) / kyb, g.nxh, nload);
   if (nblocks_out) *nblocks_out = grid.x * grid.y;
-  size_t lds = sizeof(cplx<T>) * (size_t)(g.nz + 2 * g.nd * kyb * g.nz);
-  hipLaunchKernelGGL(k_zpass<T>, grid, dim3(kThreads), lds, s, g, pz, twz, mode, kyb, B, sstride,
+  size_t lds = sizeof(cplx<T>) * (size_t)(g.nz + g.nd * kyb * g.nz);
+  if (lds > 65536)
+    hipFuncSetAttribute(P3K ? (const void*)k_zpass<T, true> : (const void*)k_zpass<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+  if (P3K)
+    hipLaunchKernelGGL((k_zpass<T, true>), grid, dim3(kThreads), lds, s, g, pz, twz, mode, kyb, B, sstride,
+                     kplus, st, rz_part);
+  else
+    hipLaunchKernelGGL((k_zpass<T, false>), grid, dim3(kThreads), lds, s, g, pz, twz, mode, kyb, B, sstride,
                      kplus, st, rz_part);
   return hipGetLastError();
 }
@@ -565,12 +613,17 @@ template <typename T>
 hipError_t launch_yinv(const Grid& g, const AxisPlan& py, const cplx<double>* twy,
                        const cplx<T>* B, cplx<T>* A, long long sstride, int nload,
                        const PcgState* st, hipStream_t s) {
-  dim3 grid((g.nz + kZB - 1) / kZB, g.nxh, nload * g.nd);
-  size_t lds = sizeof(cplx<T>) * (size_t)(g.ny + 2 * kZB * g.ny);
+  const bool P3K = py.n % 3 == 0;
+  const int zb = ypass_zb(g);
+  dim3 grid((g.nz + zb - 1) / zb, g.nxh, nload * g.nd);
+  size_t lds = sizeof(cplx<T>) * (size_t)(g.ny + zb * g.ny);
   if (lds > 65536)
-    hipFuncSetAttribute((const void*)k_yinv<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipFuncSetAttribute(P3K ? (const void*)k_yinv<T, true> : (const void*)k_yinv<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
-  hipLaunchKernelGGL(k_yinv<T>, grid, dim3(kThreads), lds, s, g, py, twy, B, A, sstride, st);
+  if (P3K)
+    hipLaunchKernelGGL((k_yinv<T, true>), grid, dim3(kThreads), lds, s, g, py, twy, zb, B, A, sstride, st);
+  else
+    hipLaunchKernelGGL((k_yinv<T, false>), grid, dim3(kThreads), lds, s, g, py, twy, zb, B, A, sstride, st);
   return hipGetLastError();
 }
 
@@ -578,12 +631,17 @@ template <typename T>
 hipError_t launch_xinv(const Grid& g, const AxisPlan& px, const cplx<double>* twx, int mode,
                        const cplx<T>* A, long long sstride, T* out, T* x, T* p,
                        long long fstride, int nload, const PcgState* st, hipStream_t s) {
+  const bool P3K = px.n % 3 == 0;
   dim3 grid((g.ny + kRows - 1) / kRows, g.nz, nload * g.nd);
-  size_t lds = sizeof(cplx<T>) * (size_t)(g.nx + kRows * g.nx + 16);
+  size_t lds = sizeof(cplx<T>) * (size_t)(g.nx + (kRows / 2) * g.nx + kRows * g.nxh);
   if (lds > 65536)
-    hipFuncSetAttribute((const void*)k_xinv<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipFuncSetAttribute(P3K ? (const void*)k_xinv<T, true> : (const void*)k_xinv<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
-  hipLaunchKernelGGL(k_xinv<T>, grid, dim3(kThreads), lds, s, g, px, twx, mode, A, sstride, out,
+  if (P3K)
+    hipLaunchKernelGGL((k_xinv<T, true>), grid, dim3(kThreads), lds, s, g, px, twx, mode, A, sstride, out,
+                     x, p, fstride, st);
+  else
+    hipLaunchKernelGGL((k_xinv<T, false>), grid, dim3(kThreads), lds, s, g, px, twx, mode, A, sstride, out,
                      x, p, fstride, st);
   return hipGetLastError();
 }

@@ -48,6 +48,7 @@ struct Grid {
   int nxh;             // nx/2 + 1
   long long N;         // nx*ny*nz
   double h[3];         // grid spacing
+  int nphase_max;      // number of material tables the operator may index
 };
 
 // FFT plan for one axis length: radix of stage i (applied first to last) in
@@ -69,6 +70,12 @@ hipError_t launch_kop_hex8_elastic(const Grid& g, const T* u, T* q, const uint8_
                                    const T* mat, int nload, long long ustride, long long qstride,
                                    const PcgState* st, double* pq_part, int* nblocks_out,
                                    hipStream_t s);
+// isotropic phases: lm = nphase x {V lambda, 2 V mu}.
+template <typename T>
+hipError_t launch_kop_hex8_iso(const Grid& g, const T* u, T* q, const uint8_t* phase,
+                               const T* lm, int nload, long long ustride, long long qstride,
+                               const PcgState* st, double* pq_part, int* nblocks_out,
+                               hipStream_t s);
 // node-centric generic operator with per-phase element matrices (2D
 // elements, 3D scalar hex8): ke = nphase x (nc*nd)^2, or a unit element
 // matrix scaled by a per-voxel field kfield.

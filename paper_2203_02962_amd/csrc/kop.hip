@@ -235,6 +235,215 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT))
   }
 }
 
+// ------------------------------------------------ isotropic hex8 kernel
+// Same operator for isotropic phases, C = lambda 1(x)1 + 2 mu I (Mandel).
+// Both modal transforms are pure sum/difference butterflies: the factors
+// 1/2 of the mean modes are folded into per-term constants a_beta(M) =
+// 2^-(2-|M|) / h_beta, which scale the gradient coefficients on the way in
+// and the modal forces on the way out.  The PCG product p.q is taken at the
+// output nodes (p is still in the LDS plane), so no per-voxel energy is
+// formed.  Node planes are triple-buffered in LDS and the plane after next is
+// prefetched into registers while the current slab is computed.
+template <typename T, int M>
+__device__ __forceinline__ void iso_term(const T (&w)[3][8], T (&f)[3][8], const T lam,
+                                         const T mu2, const T ax, const T ay, const T az) {
+  constexpr bool X = !(M & 1), Y = !(M & 2), Z = !(M & 4);
+  const T s = T(0.70710678118654752440084436210485);
+  const T sax = s * ax, say = s * ay, saz = s * az;
+  const T E0 = X ? w[0][M | 1] * ax : T(0);
+  const T E1 = Y ? w[1][M | 2] * ay : T(0);
+  const T E2 = Z ? w[2][M | 4] * az : T(0);
+  const T E3 = (Z ? w[1][M | 4] * saz : T(0)) + (Y ? w[2][M | 2] * say : T(0));
+  const T E4 = (Z ? w[0][M | 4] * saz : T(0)) + (X ? w[2][M | 1] * sax : T(0));
+  const T E5 = (Y ? w[0][M | 2] * say : T(0)) + (X ? w[1][M | 1] * sax : T(0));
+  const T lt = lam * (E0 + E1 + E2);
+  if (X) f[0][M | 1] += (lt + mu2 * E0) * ax;
+  if (Y) f[1][M | 2] += (lt + mu2 * E1) * ay;
+  if (Z) f[2][M | 4] += (lt + mu2 * E2) * az;
+  const T S3 = mu2 * E3, S4 = mu2 * E4, S5 = mu2 * E5;
+  if (Z) f[1][M | 4] += S3 * saz;
+  if (Y) f[2][M | 2] += S3 * say;
+  if (Z) f[0][M | 4] += S4 * saz;
+  if (X) f[2][M | 1] += S4 * sax;
+  if (Y) f[0][M | 2] += S5 * say;
+  if (X) f[1][M | 1] += S5 * sax;
+}
+
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
+    k_kop_hex8_iso(Grid g, int kz, const T* __restrict__ u, T* __restrict__ q,
+                   const uint8_t* __restrict__ phase, const T* __restrict__ lm,
+                   long long ustride, long long qstride, const PcgState* st, double* pq_part) {
+  using Cfg = HexCfg<T, TX, TY>;
+  constexpr int EX = Cfg::EX, PX = Cfg::PX, NE = Cfg::NE, NP = Cfg::NP, NT = Cfg::NT;
+  constexpr int NPF = (NP + NT - 1) / NT;  // plane nodes per thread
+  __shared__ T plane[2][3][NP];
+  __shared__ T force[12][NE];   // lower-face totals of the current slab
+  __shared__ T carry[12][NE];   // upper-face forces of the previous slab (own slot)
+  __shared__ double red[32];
+  __shared__ T lmt[2 * 256];
+  const int ld = blockIdx.z;
+  if (st && st[ld].status != ST_ACTIVE) return;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const long long N = g.N;
+  const int ntx = (nx + TX - 1) / TX;
+  const int x0 = (blockIdx.x % ntx) * TX, y0 = (blockIdx.x / ntx) * TY;
+  const int z0 = blockIdx.y * kz;
+  const int z1 = min(z0 + kz, nz);
+  const T* __restrict__ ub = u + (long long)ld * ustride;
+  T* __restrict__ qb = q + (long long)ld * qstride;
+  const int tid = threadIdx.x;
+  const bool is_elem = tid < NE;
+  const int ei = tid % EX, ej = tid / EX;
+  const int ex = wrapi(x0 - 1 + ei, nx), ey = wrapi(y0 - 1 + ej, ny);
+  const T ihx = T(1.0 / g.h[0]), ihy = T(1.0 / g.h[1]), ihz = T(1.0 / g.h[2]);
+
+  int poff[NPF];
+#pragma unroll
+  for (int k = 0; k < NPF; ++k) {
+    const int idx = tid + k * NT;
+    const int a = idx % PX, b = idx / PX;
+    poff[k] = idx < NP ? wrapi(y0 - 1 + b, ny) * nx + wrapi(x0 - 1 + a, nx) : -1;
+  }
+  T pf[NPF][3];
+  auto fetch = [&](int zp) {
+    const long long zb = (long long)wrapi(zp, nz) * ny * nx;
+#pragma unroll
+    for (int k = 0; k < NPF; ++k)
+      if (poff[k] >= 0) {
+        pf[k][0] = ub[zb + poff[k]];
+        pf[k][1] = ub[N + zb + poff[k]];
+        pf[k][2] = ub[2 * N + zb + poff[k]];
+      }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int k = 0; k < NPF; ++k)
+      if (poff[k] >= 0) {
+        const int idx = tid + k * NT;
+        plane[buf][0][idx] = pf[k][0];
+        plane[buf][1][idx] = pf[k][1];
+        plane[buf][2][idx] = pf[k][2];
+      }
+  };
+
+  for (int i = tid; i < 2 * g.nphase_max; i += NT) lmt[i] = lm[i];
+  // phase of this thread's voxel column, one slab ahead
+  const long long ecol = (long long)ey * nx + ex;
+  int ph_next = is_elem ? phase[(long long)wrapi(z0 - 1, nz) * ny * nx + ecol] : 0;
+  double dot = 0.0;
+  fetch(z0 - 1);
+  store(0);
+  fetch(z0);
+  store(1);
+  if (z0 + 1 <= z1) fetch(z0 + 1);
+  const int nsteps = z1 - z0 + 1;
+  for (int s = 0; s < nsteps; ++s) {
+    const int zs = z0 - 1 + s;
+    const int blo = s & 1, bhi = blo ^ 1;
+    const int ph = ph_next;
+    if (is_elem && s + 1 < nsteps) ph_next = phase[(long long)wrapi(zs + 1, nz) * ny * nx + ecol];
+    // p at this step's output node, for p.q (loaded early, used after B2)
+    const int ox = tid % TX, oy = tid / TX;
+    const bool out_ok = s > 0 && tid < TX * TY && x0 + ox < nx && y0 + oy < ny;
+    const long long o = ((long long)zs * ny + (y0 + oy)) * nx + (x0 + ox);
+    T pd0 = T(0), pd1 = T(0), pd2 = T(0);
+    if (out_ok) {
+      pd0 = ub[o];
+      pd1 = ub[N + o];
+      pd2 = ub[2 * N + o];
+    }
+    __syncthreads();
+    if (is_elem) {
+      T w[3][8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int idx = (ej + ((a >> 1) & 1)) * PX + (ei + (a & 1));
+        const int buf = (a >> 2) ? bhi : blo;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) w[c][a] = plane[buf][c][idx];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+          for (int a = 0; a < 8; ++a) {
+            if (a & bit) continue;
+            const T u0 = w[c][a], u1 = w[c][a | bit];
+            w[c][a] = u0 + u1;
+            w[c][a | bit] = u1 - u0;
+          }
+      const T lam = lmt[2 * ph], mu2 = lmt[2 * ph + 1];
+      T f[3][8];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int a = 0; a < 8; ++a) f[c][a] = T(0);
+      {  // |M| = 0: c_M = 1, a = h^-1 / 4
+        const T qx = T(0.25) * ihx, qy = T(0.25) * ihy, qz = T(0.25) * ihz;
+        iso_term<T, 0>(w, f, lam, mu2, qx, qy, qz);
+      }
+      {  // |M| = 1: c_M = 1/12, a = h^-1 / 2
+        const T l1 = lam * T(1.0 / 12.0), m1 = mu2 * T(1.0 / 12.0);
+        const T hx = T(0.5) * ihx, hy = T(0.5) * ihy, hz = T(0.5) * ihz;
+        iso_term<T, 1>(w, f, l1, m1, hx, hy, hz);
+        iso_term<T, 2>(w, f, l1, m1, hx, hy, hz);
+        iso_term<T, 4>(w, f, l1, m1, hx, hy, hz);
+      }
+      {  // |M| = 2: c_M = 1/144, a = h^-1
+        const T l2 = lam * T(1.0 / 144.0), m2 = mu2 * T(1.0 / 144.0);
+        iso_term<T, 3>(w, f, l2, m2, ihx, ihy, ihz);
+        iso_term<T, 5>(w, f, l2, m2, ihx, ihy, ihz);
+        iso_term<T, 6>(w, f, l2, m2, ihx, ihy, ihz);
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+          for (int a = 0; a < 8; ++a) {
+            if (a & bit) continue;
+            const T fm = f[c][a], fd = f[c][a | bit];
+            f[c][a] = fm - fd;
+            f[c][a | bit] = fm + fd;
+          }
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int r = c * 4 + k;
+          if (s > 0) force[r][tid] = f[c][k] + carry[r][tid];
+          carry[r][tid] = f[c][k + 4];
+        }
+    }
+    __syncthreads();
+    // the lower plane is no longer read: refill it with plane zs+2, prefetch zs+3
+    if (zs + 2 <= z1) {
+      store(blo);
+      if (zs + 3 <= z1) fetch(zs + 3);
+    }
+    if (out_ok) {
+      const int e00 = oy * EX + ox;
+      const T pd[3] = {pd0, pd1, pd2};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T v = force[c * 4 + 3][e00] + force[c * 4 + 2][e00 + 1] +
+                    force[c * 4 + 1][e00 + EX] + force[c * 4 + 0][e00 + EX + 1];
+        qb[c * N + o] = v;
+        dot += (double)pd[c] * (double)v;
+      }
+    }
+  }
+  if (pq_part) {
+    const double tot = block_sum_k(dot, red);
+    if (tid == 0) {
+      const long long nb = (long long)gridDim.x * gridDim.y;
+      pq_part[(long long)ld * nb + (long long)blockIdx.y * gridDim.x + blockIdx.x] = tot;
+    }
+  }
+}
+
 constexpr int kHexTX = 32, kHexTY = 8;
 
 static int hex_kz(const Grid& g) { return g.nz >= 64 ? 16 : 8; }
@@ -396,6 +605,29 @@ hipError_t launch_rhs(const Grid& g, int elem, const uint8_t* phase, const doubl
                      fe, nload, b, bstride);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_kop_hex8_iso(const Grid& g, const T* u, T* q, const uint8_t* phase,
+                               const T* lm, int nload, long long ustride, long long qstride,
+                               const PcgState* st, double* pq_part, int* nblocks_out,
+                               hipStream_t s) {
+  constexpr int TX = kHexTX, TY = kHexTY;
+  using Cfg = HexCfg<T, TX, TY>;
+  const int kz = hex_kz(g);
+  const int ntiles = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
+  dim3 grid(ntiles, (g.nz + kz - 1) / kz, nload);
+  if (nblocks_out) *nblocks_out = grid.x * grid.y;
+  hipLaunchKernelGGL((k_kop_hex8_iso<T, TX, TY>), grid, dim3(Cfg::NT), 0, s, g, kz, u, q, phase,
+                     lm, ustride, qstride, st, pq_part);
+  return hipGetLastError();
+}
+template hipError_t launch_kop_hex8_iso<double>(const Grid&, const double*, double*,
+                                                const uint8_t*, const double*, int, long long,
+                                                long long, const PcgState*, double*, int*,
+                                                hipStream_t);
+template hipError_t launch_kop_hex8_iso<float>(const Grid&, const float*, float*, const uint8_t*,
+                                               const float*, int, long long, long long,
+                                               const PcgState*, double*, int*, hipStream_t);
 
 template hipError_t launch_kop_hex8_elastic<double>(const Grid&, const double*, double*,
                                                     const uint8_t*, const double*, int,
