@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-kernels", action="store_true")
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="also run a plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -113,6 +115,13 @@ def main():
 
     wl = workload("elastic3d_spheres", seed=0, n=args.n)
     torch.cuda.set_device(0)
+    if args.probe_copy:
+        a = torch.ones(64 * 2 ** 20, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     stream = torch.cuda.current_stream()
     ctx = setup_context(wl)
     ctx.set_stream(stream)

@@ -105,7 +105,7 @@ __device__ __forceinline__ void dft_small(cplx<T>* x, int s) {
 constexpr int kMaxPts = 2048;
 
 template <typename T, int R>
-__device__ __forceinline__ void stockham_stage(cplx<T>* buf, int n, int nlines, int L,
+__device__ __forceinline__ void stockham_stage(cplx<T>* buf, int n, int ls, int nlines, int L,
                                                const cplx<T>* tw, int sign) {
   constexpr int MAXIT = (kMaxPts / R + kThreads - 1) / kThreads;
   const int m = n / R;
@@ -121,7 +121,7 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int n, int nlines, 
       const int line = it / m;
       const int j = it - line * m;
       const int kk = j % L;
-      const cplx<T>* src = buf + line * n;
+      const cplx<T>* src = buf + line * ls;
 #pragma unroll
       for (int t = 0; t < R; ++t) {
         cplx<T> a = src[j + t * m];
@@ -133,7 +133,7 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int n, int nlines, 
         }
         v[k][t] = a;
       }
-      dst[k] = line * n + (j / L) * L * R + kk;
+      dst[k] = line * ls + (j / L) * L * R + kk;
     }
   }
   __syncthreads();
@@ -152,17 +152,22 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int n, int nlines, 
 // returns `a` after a final barrier.
 // P3: the length has a factor 3 (radix-3 stages compiled in).  Lengths are
 // products of 2 and 3 only.
+// Lines are stored with stride ls = n + 1 complex values in LDS, so that
+// accesses to the same index of consecutive lines (the transposed loads and
+// stores of the passes) fall into different banks.
+__host__ __device__ __forceinline__ int lds_stride(int n) { return n + 1; }
+
 template <typename T, bool P3>
 __device__ cplx<T>* fft_lines(cplx<T>* a, const AxisPlan& plan, int nlines, const cplx<T>* tw,
                               int sign) {
   int L = 1;
-  const int n = plan.n;
+  const int n = plan.n, ls = lds_stride(n);
   for (int st = 0; st < plan.nstage; ++st) {
     const int R = (plan.code >> (4 * st)) & 15u;
-    if (R == 8) stockham_stage<T, 8>(a, n, nlines, L, tw, sign);
-    else if (R == 4) stockham_stage<T, 4>(a, n, nlines, L, tw, sign);
-    else if (R == 2) stockham_stage<T, 2>(a, n, nlines, L, tw, sign);
-    else if constexpr (P3) stockham_stage<T, 3>(a, n, nlines, L, tw, sign);
+    if (R == 8) stockham_stage<T, 8>(a, n, ls, nlines, L, tw, sign);
+    else if (R == 4) stockham_stage<T, 4>(a, n, ls, nlines, L, tw, sign);
+    else if (R == 2) stockham_stage<T, 2>(a, n, ls, nlines, L, tw, sign);
+    else if constexpr (P3) stockham_stage<T, 3>(a, n, ls, nlines, L, tw, sign);
     L *= R;
   }
   return a;
@@ -208,6 +213,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(Grid g, AxisPlan px, const cp
   const int y0 = blockIdx.x * kRows, z = blockIdx.y;
   const long long rbase = (long long)ld * rstride + ((long long)c * g.nz + z) * ny * nx;
   const T alpha = (mode == XF_UPDATE_R) ? T(st[ld].alpha) : T(0);
+  const int lsx = lds_stride(nx);
   for (int idx = threadIdx.x; idx < kRows * nx; idx += blockDim.x) {
     const int row = idx / nx, x = idx - row * nx, y = y0 + row;
     T v = T(0);
@@ -220,7 +226,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(Grid g, AxisPlan px, const cp
         r[o] = v;
       }
     }
-    cplx<T>& d = a[(row >> 1) * nx + x];
+    cplx<T>& d = a[(row >> 1) * lsx + x];
     if (row & 1) d.im = v; else d.re = v;
   }
   __syncthreads();
@@ -229,7 +235,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(Grid g, AxisPlan px, const cp
   for (int idx = threadIdx.x; idx < kRows * nxh; idx += blockDim.x) {
     const int yl = idx % kRows, kx = idx / kRows, y = y0 + yl;
     if (y >= ny) continue;
-    const cplx<T>* line = res + (yl >> 1) * nx;
+    const cplx<T>* line = res + (yl >> 1) * lsx;
     const cplx<T> ck = line[kx];
     const cplx<T> cn = line[(nx - kx) % nx];
     cplx<T> X;
@@ -259,18 +265,19 @@ __global__ void __launch_bounds__(kThreads) k_yfwd(Grid g, AxisPlan py, const cp
   load_twiddles(tw, twy, ny);
   const int z0 = blockIdx.x * zb, kx = blockIdx.y;
   const long long base = (long long)ld * sstride;
+  const int ls = lds_stride(ny);
   for (int idx = threadIdx.x; idx < zb * ny; idx += blockDim.x) {
     const int zl = idx / ny, y = idx - zl * ny, z = z0 + zl;
     cplx<T> v = {T(0), T(0)};
     if (z < nz) v = A[base + (((long long)c * nz + z) * nxh + kx) * ny + y];
-    a[idx] = v;
+    a[zl * ls + y] = v;
   }
   __syncthreads();
   cplx<T>* res = fft_lines<T, P3>(a, py, zb, tw, -1);
   const long long obase = base + ((long long)c * nxh + kx) * (long long)ny * nz;
   for (int idx = threadIdx.x; idx < zb * ny; idx += blockDim.x) {
     const int zl = idx % zb, ky = idx / zb, z = z0 + zl;
-    if (z < nz) B[obase + (long long)ky * nz + z] = res[zl * ny + ky];
+    if (z < nz) B[obase + (long long)ky * nz + z] = res[zl * ls + ky];
   }
 }
 
@@ -294,12 +301,14 @@ __global__ void __launch_bounds__(kThreads) k_zpass(Grid g, AxisPlan pz, const c
   const long long cstride = (long long)nxh * ny * nz;
   const long long base = (long long)ld * sstride + (long long)kx * ny * nz;
   const int per = kyb * nz;
+  const int ls = lds_stride(nz);
+  const int cls = kyb * ls;  // LDS stride between components
   for (int idx = threadIdx.x; idx < nd * per; idx += blockDim.x) {
     const int c = idx / per, rem = idx - c * per, kyl = rem / nz, z = rem - kyl * nz;
     const int ky = ky0 + kyl;
     cplx<T> v = {T(0), T(0)};
     if (ky < ny) v = B[base + c * cstride + (long long)ky * nz + z];
-    a[idx] = v;
+    a[c * cls + kyl * ls + z] = v;
   }
   __syncthreads();
   cplx<T>* res = fft_lines<T, P3>(a, pz, nd * kyb, tw, -1);
@@ -307,15 +316,16 @@ __global__ void __launch_bounds__(kThreads) k_zpass(Grid g, AxisPlan pz, const c
   if (mode == Z_SOLVE) {
     const long long nfreq = (long long)nxh * ny * nz;
     const double wgt = (kx == 0 || (2 * kx == g.nx)) ? 1.0 : 2.0;
-    for (int idx = threadIdx.x; idx < per; idx += blockDim.x) {
-      const int kyl = idx / nz, kz = idx - kyl * nz, ky = ky0 + kyl;
+    for (int idx0 = threadIdx.x; idx0 < per; idx0 += blockDim.x) {
+      const int kyl = idx0 / nz, kz = idx0 - kyl * nz, ky = ky0 + kyl;
       if (ky >= ny) continue;
+      const int idx = kyl * ls + kz;
       const long long f = ((long long)kx * ny + ky) * nz + kz;
       if (nd == 3) {
         const T k00 = kplus[f], k11 = kplus[nfreq + f], k22 = kplus[2 * nfreq + f];
         const T k12 = kplus[3 * nfreq + f], k02 = kplus[4 * nfreq + f],
                 k01 = kplus[5 * nfreq + f];
-        const cplx<T> r0 = res[idx], r1 = res[per + idx], r2 = res[2 * per + idx];
+        const cplx<T> r0 = res[idx], r1 = res[cls + idx], r2 = res[2 * cls + idx];
         cplx<T> z0v = {k00 * r0.re + k01 * r1.re + k02 * r2.re,
                        k00 * r0.im + k01 * r1.im + k02 * r2.im};
         cplx<T> z1v = {k01 * r0.re + k11 * r1.re + k12 * r2.re,
@@ -326,17 +336,17 @@ __global__ void __launch_bounds__(kThreads) k_zpass(Grid g, AxisPlan pz, const c
                        (double)r1.re * z1v.re + (double)r1.im * z1v.im +
                        (double)r2.re * z2v.re + (double)r2.im * z2v.im);
         res[idx] = z0v;
-        res[per + idx] = z1v;
-        res[2 * per + idx] = z2v;
+        res[cls + idx] = z1v;
+        res[2 * cls + idx] = z2v;
       } else if (nd == 2) {
         const T k00 = kplus[f], k11 = kplus[nfreq + f], k01 = kplus[2 * nfreq + f];
-        const cplx<T> r0 = res[idx], r1 = res[per + idx];
+        const cplx<T> r0 = res[idx], r1 = res[cls + idx];
         cplx<T> z0v = {k00 * r0.re + k01 * r1.re, k00 * r0.im + k01 * r1.im};
         cplx<T> z1v = {k01 * r0.re + k11 * r1.re, k01 * r0.im + k11 * r1.im};
         part += wgt * ((double)r0.re * z0v.re + (double)r0.im * z0v.im +
                        (double)r1.re * z1v.re + (double)r1.im * z1v.im);
         res[idx] = z0v;
-        res[per + idx] = z1v;
+        res[cls + idx] = z1v;
       } else {
         const T k00 = kplus[f];
         const cplx<T> r0 = res[idx];
@@ -351,7 +361,7 @@ __global__ void __launch_bounds__(kThreads) k_zpass(Grid g, AxisPlan pz, const c
   for (int idx = threadIdx.x; idx < nd * per; idx += blockDim.x) {
     const int c = idx / per, rem = idx - c * per, kyl = rem / nz, z = rem - kyl * nz;
     const int ky = ky0 + kyl;
-    if (ky < ny) B[base + c * cstride + (long long)ky * nz + z] = res[idx];
+    if (ky < ny) B[base + c * cstride + (long long)ky * nz + z] = res[c * cls + kyl * ls + z];
   }
   if (mode == Z_SOLVE && rz_part) {
     const double s = block_sum(part, red);
@@ -377,17 +387,18 @@ __global__ void __launch_bounds__(kThreads) k_yinv(Grid g, AxisPlan py, const cp
   const int z0 = blockIdx.x * zb, kx = blockIdx.y;
   const long long base = (long long)ld * sstride;
   const long long ibase = base + ((long long)c * nxh + kx) * (long long)ny * nz;
+  const int ls = lds_stride(ny);
   for (int idx = threadIdx.x; idx < zb * ny; idx += blockDim.x) {
     const int zl = idx % zb, ky = idx / zb, z = z0 + zl;
     cplx<T> v = {T(0), T(0)};
     if (z < nz) v = B[ibase + (long long)ky * nz + z];
-    a[zl * ny + ky] = v;
+    a[zl * ls + ky] = v;
   }
   __syncthreads();
   cplx<T>* res = fft_lines<T, P3>(a, py, zb, tw, +1);
   for (int idx = threadIdx.x; idx < zb * ny; idx += blockDim.x) {
     const int zl = idx / ny, y = idx - zl * ny, z = z0 + zl;
-    if (z < nz) A[base + (((long long)c * nz + z) * nxh + kx) * ny + y] = res[idx];
+    if (z < nz) A[base + (((long long)c * nz + z) * nxh + kx) * ny + y] = res[zl * ls + y];
   }
 }
 
@@ -417,15 +428,16 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
   if (status != ST_ACTIVE) return;
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
+  const int lsx = lds_stride(nx);
   cplx<T>* a = tw + nx;
-  cplx<T>* S = a + (kRows / 2) * nx;  // 16 x nxh raw tile
+  cplx<T>* S = a + (kRows / 2) * lsx;  // 16 x nxh raw tile, row stride nxh + 1
   load_twiddles(tw, twx, nx);
   const long long abase = (long long)ld * sstride + ((long long)c * g.nz + z) * nxh * ny;
   for (int idx = threadIdx.x; idx < kRows * nxh; idx += blockDim.x) {
     const int yl = idx % kRows, kx = idx / kRows, y = y0 + yl;
     cplx<T> v = {T(0), T(0)};
     if (y < ny) v = A[abase + (long long)kx * ny + y];
-    S[yl * nxh + kx] = v;
+    S[yl * (nxh + 1) + kx] = v;
   }
   __syncthreads();
   const int half = nx / 2;
@@ -433,17 +445,17 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
     const int j = idx / nx, k = idx - j * nx;
     cplx<T> xa, xb;
     if (k <= half) {
-      xa = S[(2 * j) * nxh + k];
-      xb = S[(2 * j + 1) * nxh + k];
+      xa = S[(2 * j) * (nxh + 1) + k];
+      xb = S[(2 * j + 1) * (nxh + 1) + k];
       if (k == 0 || k == half) {
         xa.im = T(0);
         xb.im = T(0);
       }
     } else {
-      xa = conjg(S[(2 * j) * nxh + (nx - k)]);
-      xb = conjg(S[(2 * j + 1) * nxh + (nx - k)]);
+      xa = conjg(S[(2 * j) * (nxh + 1) + (nx - k)]);
+      xb = conjg(S[(2 * j + 1) * (nxh + 1) + (nx - k)]);
     }
-    a[idx] = {xa.re - xb.im, xa.im + xb.re};
+    a[j * lsx + k] = {xa.re - xb.im, xa.im + xb.re};
   }
   __syncthreads();
   cplx<T>* res = fft_lines<T, P3>(a, px, kRows / 2, tw, +1);
@@ -452,7 +464,7 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
   for (int idx = threadIdx.x; idx < kRows * nx; idx += blockDim.x) {
     const int row = idx / nx, xx = idx - row * nx, y = y0 + row;
     if (y >= ny) continue;
-    const cplx<T> v = res[(row >> 1) * nx + xx];
+    const cplx<T> v = res[(row >> 1) * lsx + xx];
     const T zv = (row & 1) ? v.im : v.re;
     const long long o = fbase + (long long)y * nx + xx;
     if (mode == XI_PLAIN) {
@@ -533,7 +545,7 @@ hipError_t launch_xfwd(const Grid& g, const AxisPlan& px, const cplx<double>* tw
                        long long sstride, int nload, const PcgState* st, hipStream_t s) {
   const bool P3K = px.n % 3 == 0;
   dim3 grid((g.ny + kRows - 1) / kRows, g.nz, nload * g.nd);
-  size_t lds = sizeof(cplx<T>) * (size_t)(g.nx + (kRows / 2) * g.nx);
+  size_t lds = sizeof(cplx<T>) * (size_t)(g.nx + (kRows / 2) * lds_stride(g.nx));
   if (lds > 65536)
     hipFuncSetAttribute(P3K ? (const void*)k_xfwd<T, true> : (const void*)k_xfwd<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
@@ -560,7 +572,7 @@ hipError_t launch_yfwd(const Grid& g, const AxisPlan& py, const cplx<double>* tw
   const bool P3K = py.n % 3 == 0;
   const int zb = ypass_zb(g);
   dim3 grid((g.nz + zb - 1) / zb, g.nxh, nload * g.nd);
-  size_t lds = sizeof(cplx<T>) * (size_t)(g.ny + zb * g.ny);
+  size_t lds = sizeof(cplx<T>) * (size_t)(g.ny + zb * lds_stride(g.ny));
   if (lds > 65536)
     hipFuncSetAttribute(P3K ? (const void*)k_yfwd<T, true> : (const void*)k_yfwd<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
@@ -596,7 +608,7 @@ hipError_t launch_zpass(const Grid& g, const AxisPlan& pz, const cplx<double>* t
   const int kyb = zpass_kyb<T>(g);
   dim3 grid((g.ny + kyb - 1) / kyb, g.nxh, nload);
   if (nblocks_out) *nblocks_out = grid.x * grid.y;
-  size_t lds = sizeof(cplx<T>) * (size_t)(g.nz + g.nd * kyb * g.nz);
+  size_t lds = sizeof(cplx<T>) * (size_t)(g.nz + g.nd * kyb * lds_stride(g.nz));
   if (lds > 65536)
     hipFuncSetAttribute(P3K ? (const void*)k_zpass<T, true> : (const void*)k_zpass<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
@@ -616,7 +628,7 @@ hipError_t launch_yinv(const Grid& g, const AxisPlan& py, const cplx<double>* tw
   const bool P3K = py.n % 3 == 0;
   const int zb = ypass_zb(g);
   dim3 grid((g.nz + zb - 1) / zb, g.nxh, nload * g.nd);
-  size_t lds = sizeof(cplx<T>) * (size_t)(g.ny + zb * g.ny);
+  size_t lds = sizeof(cplx<T>) * (size_t)(g.ny + zb * lds_stride(g.ny));
   if (lds > 65536)
     hipFuncSetAttribute(P3K ? (const void*)k_yinv<T, true> : (const void*)k_yinv<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
@@ -633,7 +645,8 @@ hipError_t launch_xinv(const Grid& g, const AxisPlan& px, const cplx<double>* tw
                        long long fstride, int nload, const PcgState* st, hipStream_t s) {
   const bool P3K = px.n % 3 == 0;
   dim3 grid((g.ny + kRows - 1) / kRows, g.nz, nload * g.nd);
-  size_t lds = sizeof(cplx<T>) * (size_t)(g.nx + (kRows / 2) * g.nx + kRows * g.nxh);
+  size_t lds = sizeof(cplx<T>) * (size_t)(g.nx + (kRows / 2) * lds_stride(g.nx) +
+                                          kRows * (g.nxh + 1));
   if (lds > 65536)
     hipFuncSetAttribute(P3K ? (const void*)k_xinv<T, true> : (const void*)k_xinv<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);

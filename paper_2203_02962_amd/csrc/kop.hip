@@ -282,13 +282,26 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
   __shared__ T carry[12][NE];   // upper-face forces of the previous slab (own slot)
   __shared__ double red[32];
   __shared__ T lmt[2 * 256];
-  const int ld = blockIdx.z;
+  // Workgroups are dispatched round-robin over the 8 XCDs; renumber them so
+  // that each XCD receives a contiguous range of tiles, whose halos then
+  // meet in the same L2.
+  int bt = blockIdx.x, bz = blockIdx.y, ld = blockIdx.z;
+  {
+    const int nb = gridDim.x * gridDim.y * gridDim.z;
+    if ((nb & 7) == 0) {
+      const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+      const int l = (b & 7) * (nb >> 3) + (b >> 3);
+      bt = l % gridDim.x;
+      bz = (l / gridDim.x) % gridDim.y;
+      ld = l / (gridDim.x * gridDim.y);
+    }
+  }
   if (st && st[ld].status != ST_ACTIVE) return;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const long long N = g.N;
   const int ntx = (nx + TX - 1) / TX;
-  const int x0 = (blockIdx.x % ntx) * TX, y0 = (blockIdx.x / ntx) * TY;
-  const int z0 = blockIdx.y * kz;
+  const int x0 = (bt % ntx) * TX, y0 = (bt / ntx) * TY;
+  const int z0 = bz * kz;
   const int z1 = min(z0 + kz, nz);
   const T* __restrict__ ub = u + (long long)ld * ustride;
   T* __restrict__ qb = q + (long long)ld * qstride;
@@ -343,16 +356,9 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
     const int blo = s & 1, bhi = blo ^ 1;
     const int ph = ph_next;
     if (is_elem && s + 1 < nsteps) ph_next = phase[(long long)wrapi(zs + 1, nz) * ny * nx + ecol];
-    // p at this step's output node, for p.q (loaded early, used after B2)
     const int ox = tid % TX, oy = tid / TX;
     const bool out_ok = s > 0 && tid < TX * TY && x0 + ox < nx && y0 + oy < ny;
     const long long o = ((long long)zs * ny + (y0 + oy)) * nx + (x0 + ox);
-    T pd0 = T(0), pd1 = T(0), pd2 = T(0);
-    if (out_ok) {
-      pd0 = ub[o];
-      pd1 = ub[N + o];
-      pd2 = ub[2 * N + o];
-    }
     __syncthreads();
     if (is_elem) {
       T w[3][8];
@@ -417,6 +423,14 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
           carry[r][tid] = f[c][k + 4];
         }
     }
+    // p at this step's output node (plane zs, still in LDS) for p.q
+    T pd0 = T(0), pd1 = T(0), pd2 = T(0);
+    if (out_ok) {
+      const int pidx = (oy + 1) * PX + (ox + 1);
+      pd0 = plane[blo][0][pidx];
+      pd1 = plane[blo][1][pidx];
+      pd2 = plane[blo][2][pidx];
+    }
     __syncthreads();
     // the lower plane is no longer read: refill it with plane zs+2, prefetch zs+3
     if (zs + 2 <= z1) {
@@ -439,7 +453,7 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
     const double tot = block_sum_k(dot, red);
     if (tid == 0) {
       const long long nb = (long long)gridDim.x * gridDim.y;
-      pq_part[(long long)ld * nb + (long long)blockIdx.y * gridDim.x + blockIdx.x] = tot;
+      pq_part[(long long)ld * nb + (long long)bz * gridDim.x + bt] = tot;
     }
   }
 }
