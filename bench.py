@@ -149,12 +149,19 @@ def main():
     value = dof * iters_total / (t1 - t0)
     H = ctx.get_homogenized()
 
-    # plain-solver time to 1e-6 (same workload, separate solve)
-    torch.cuda.synchronize()
-    ta = time.perf_counter()
-    rc6, st6 = ctx.solve(eta=1e-6, rebuild=True)
-    torch.cuda.synchronize()
-    t_1e6 = (time.perf_counter() - ta) * 1000.0
+    # time to 1e-6 (same workload, separate solves, setup included)
+    def timed_solve(**kw):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        rcx, stx = ctx.solve(rebuild=True, **kw)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - ta) * 1000.0, rcx, stx
+    t_1e6, rc6, st6 = timed_solve(eta=1e-6)
+    from paper_2203_02962_amd.fh import FH_FP32_REFINED
+    t_1e6_r, rc6r, st6r = timed_solve(eta=1e-6, precision=FH_FP32_REFINED, eta_inner=1e-4)
+    H6r = ctx.get_homogenized()
+    t_1e10_r, rc10r, st10r = timed_solve(eta=args.eta, precision=FH_FP32_REFINED, eta_inner=1e-4)
+    H10r = ctx.get_homogenized()
 
     per_iter, parts = algorithmic_bytes(args.n)
     kernels = {}
@@ -218,8 +225,16 @@ def main():
             "iterations": st["iterations"],
             "setup_ms": round(st["setup_ms"], 2), "pcg_ms": round(st["solve_ms"], 2),
             "chom_ms": round(st["chom_ms"], 2),
-            "time_to_1e-6_ms": {"plain_fp64": round(t_1e6, 2)},
-            "iterations_1e-6": st6["iterations"],
+            "time_to_1e-6_ms": {"plain_fp64": round(t_1e6, 2),
+                                "fp32_refined": round(t_1e6_r, 2)},
+            "iterations_1e-6": {"plain_fp64": st6["iterations"],
+                                "fp32_refined_inner": st6r["iterations"],
+                                "fp32_refined_sweeps": st6r["outer"]},
+            "fp32_refined_to_eta": {
+                "ms": round(t_1e10_r, 2), "inner_iterations": st10r["iterations"],
+                "sweeps": st10r["outer"],
+                "chom_rel_err_vs_fp64": float(np.abs(H10r - H).max() / np.abs(H).max()),
+                "chom_1e-6_rel_err_vs_fp64_1e-10": float(np.abs(H6r - H).max() / np.abs(H).max())},
             "chom_rel_err_vs_oracle": chom_err,
         },
         "kernels": kernels,

@@ -81,6 +81,7 @@ struct fh_ctx {
     double* kplus;
     float* kplus_f;
     float *x32, *r32, *p32, *q32;
+    float* kf32;  // float copy of a per-voxel conductivity
     cplx<float> *A32, *B32;
     double *d64;  // refinement: correction accumulator
     fh::PcgState* st;
@@ -398,6 +399,7 @@ size_t layout(fh_ctx* c, char* base, fh_ctx::Layout* Lout) {
   L.A32 = (cplx<float>*)take(sizeof(cplx<float>) * S * nl);
   L.B32 = (cplx<float>*)take(sizeof(cplx<float>) * S * nl);
   L.d64 = (double*)take(sizeof(double) * F * nl);
+  L.kf32 = (float*)take(sizeof(float) * (size_t)g.N);
   L.st = (fh::PcgState*)take(sizeof(fh::PcgState) * nl);
   L.nb_kop = fh::kop_nblocks(g, hex_elastic(c));
   L.nb_z = fh::zpass_nblocks<double>(g);
@@ -455,6 +457,15 @@ int ensure_pinned(fh_ctx* c, size_t n) {
   return FH_OK;
 }
 
+int upload_f(fh_ctx* c, float** dst, const std::vector<double>& v) {
+  hipFree(*dst);
+  *dst = nullptr;
+  std::vector<float> f(v.begin(), v.end());
+  HIPCHK(c, hipMalloc((void**)dst, f.size() * sizeof(float)));
+  HIPCHK(c, hipMemcpy(*dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+  return FH_OK;
+}
+
 int upload(fh_ctx* c, double** dst, size_t* dst_n, const std::vector<double>& v) {
   if (*dst_n < v.size()) {
     hipFree(*dst);
@@ -506,7 +517,9 @@ int apply_K32(fh_ctx* c, const float* u, float* q, int nload, long long stride,
     HIPCHK(c, fh::launch_kop_hex8_elastic<float>(g, u, q, ph, c->mat_dev_f, nload, stride,
                                                  stride, st, pq, &nb, c->stream));
   } else {
-    return fail(c, FH_EINVAL, "FP32 operator only for hex8 elasticity in this build");
+    const float* kf = c->mat_kind == 2 ? c->L.kf32 : nullptr;
+    HIPCHK(c, fh::launch_kop_generic<float>(g, c->element, u, q, ph, kf, c->mat_dev_f, nload,
+                                            stride, stride, st, pq, &nb, c->stream));
   }
   return FH_OK;
 }
@@ -616,6 +629,7 @@ int build_symbol(fh_ctx* c) {
   HIPCHK(c, fh::launch_symbol(g, c->L.spec, S, c->L.kplus, c->flag_dev, c->stream));
   const long long nsym_n = (long long)g.nxh * g.ny * g.nz * (g.nd * (g.nd + 1) / 2);
   HIPCHK(c, fh::launch_cast_symbol(nsym_n, c->L.kplus, c->L.kplus_f, c->stream));
+  if (c->mat_kind == 2) HIPCHK(c, fh::launch_cast_d2f(c->kfield_dev, c->L.kf32, g.N, c->stream));
   int bad = 0;
   HIPCHK(c, hipMemcpyAsync(&bad, c->flag_dev, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -663,69 +677,192 @@ void kt_collect(fh_ctx* c);
     kt_end(c, _slot);                    \
   } while (0)
 
-// ------------------------------------------------------------ FP64 PCG
-// Solves K x = b for nload right-hand sides held in L.b (or `bsrc`), result
-// in L.x.  Everything stays on the device; status polled every `poll`.
-int pcg64(fh_ctx* c, int nload, double eta, int itmax, int poll, std::vector<fh::PcgState>& out) {
+// ------------------------------------------------------------------ PCG
+// One PCG solve per load case on buffers of type T (double, or float for the
+// inner solves of the refinement).  The right-hand side must already be in
+// `r`; x is zeroed here.  Load cases whose initial state is not ACTIVE are
+// skipped by every kernel.  Scalars, reductions and the stopping test are
+// FP64 in both cases.  The host only polls the per-load status every `poll`
+// iterations.
+template <typename T>
+struct PcgBufs {
+  T *x, *r, *p, *q;
+  cplx<T> *A, *B;
+  const T* kplus;
+};
+
+int apply_KT(fh_ctx* c, const double* u, double* q, int nload, long long F,
+             const fh::PcgState* st, double* pq) {
+  return apply_K(c, false, u, q, nload, F, st, pq);
+}
+int apply_KT(fh_ctx* c, const float* u, float* q, int nload, long long F,
+             const fh::PcgState* st, double* pq) {
+  return apply_K32(c, u, q, nload, F, st, pq);
+}
+
+template <typename T>
+int pcg_run(fh_ctx* c, int nload, const PcgBufs<T>& bf, double eta, int itmax, int poll,
+            const std::vector<int>& active, std::vector<fh::PcgState>& out) {
   const fh::Grid& g = c->g;
   const long long F = (long long)g.nd * g.N;
   const long long S = (long long)g.nd * g.nxh * g.ny * g.nz;
   fh_ctx::Layout& L = c->L;
   std::vector<fh::PcgState> hs(nload);
-  for (auto& s : hs) {
-    s = fh::PcgState{};
-    s.status = fh::ST_ACTIVE;
-    s.eta2 = eta * eta;
-    s.itmax = itmax;
+  for (int j = 0; j < nload; ++j) {
+    hs[j] = fh::PcgState{};
+    hs[j].status = active[j] ? fh::ST_ACTIVE : fh::ST_CONVERGED;
+    hs[j].eta2 = eta * eta;
+    hs[j].itmax = itmax;
   }
   HIPCHK(c, hipMemcpyAsync(L.st, hs.data(), sizeof(fh::PcgState) * nload, hipMemcpyHostToDevice,
                            c->stream));
-  HIPCHK(c, fh::launch_fill<double>(L.x, 0.0, F * nload, c->stream));
-  HIPCHK(c, fh::launch_copy(L.r, L.b, F * nload, c->stream));
+  HIPCHK(c, fh::launch_fill<T>(bf.x, T(0), F * nload, c->stream));
   // z0 = M r0, p0 = z0, rho0 = r0.z0
   int nbz = 0;
-  HIPCHK(c, fh::launch_xfwd<double>(g, c->px, c->twx, fh::XF_PLAIN, L.r, F, nullptr, 0, L.A, S,
-                                    nload, L.st, c->stream));
-  HIPCHK(c, fh::launch_yfwd<double>(g, c->py, c->twy, L.A, L.B, S, nload, L.st, c->stream));
-  HIPCHK(c, fh::launch_zpass<double>(g, c->pz, c->twz, fh::Z_SOLVE, L.B, S, L.kplus, nload, L.st,
-                                     L.rz_part, &nbz, c->stream));
-  HIPCHK(c, fh::launch_yinv<double>(g, c->py, c->twy, L.B, L.A, S, nload, L.st, c->stream));
-  HIPCHK(c, fh::launch_xinv<double>(g, c->px, c->twx, fh::XI_INIT_P, L.A, S, nullptr, nullptr,
-                                    L.p, F, nload, L.st, c->stream));
+  HIPCHK(c, fh::launch_xfwd<T>(g, c->px, c->twx, fh::XF_PLAIN, bf.r, F, nullptr, 0, bf.A, S,
+                               nload, L.st, c->stream));
+  HIPCHK(c, fh::launch_yfwd<T>(g, c->py, c->twy, bf.A, bf.B, S, nload, L.st, c->stream));
+  HIPCHK(c, fh::launch_zpass<T>(g, c->pz, c->twz, fh::Z_SOLVE, bf.B, S, bf.kplus, nload, L.st,
+                                L.rz_part, &nbz, c->stream));
+  HIPCHK(c, fh::launch_yinv<T>(g, c->py, c->twy, bf.B, bf.A, S, nload, L.st, c->stream));
+  HIPCHK(c, fh::launch_xinv<T>(g, c->px, c->twx, fh::XI_INIT_P, bf.A, S, nullptr, nullptr, bf.p,
+                               F, nload, L.st, c->stream));
   HIPCHK(c, fh::launch_finalize_init(L.st, L.rz_part, nbz, nload, c->stream));
   int done_iters = 0;
   const int cap = itmax + 2;
   while (true) {
     for (int k = 0; k < poll && done_iters < cap; ++k, ++done_iters) {
       int rc = 0;
-      KT(FH_K_OPERATOR, rc = apply_K(c, false, L.p, L.q, nload, F, L.st, L.pq_part));
+      KT(FH_K_OPERATOR, rc = apply_KT(c, bf.p, bf.q, nload, F, L.st, L.pq_part));
       if (rc) return rc;
       KT(FH_K_SCALAR, HIPCHK(c, fh::launch_finalize_alpha(L.st, L.pq_part, L.nb_kop, nload,
                                                           c->stream)));
-      KT(FH_K_XFWD, HIPCHK(c, fh::launch_xfwd<double>(g, c->px, c->twx, fh::XF_UPDATE_R, L.r, F,
-                                                      L.q, F, L.A, S, nload, L.st, c->stream)));
-      KT(FH_K_YFWD, HIPCHK(c, fh::launch_yfwd<double>(g, c->py, c->twy, L.A, L.B, S, nload, L.st,
-                                                      c->stream)));
-      KT(FH_K_ZSOLVE, HIPCHK(c, fh::launch_zpass<double>(g, c->pz, c->twz, fh::Z_SOLVE, L.B, S,
-                                                         L.kplus, nload, L.st, L.rz_part, &nbz,
-                                                         c->stream)));
+      KT(FH_K_XFWD, HIPCHK(c, fh::launch_xfwd<T>(g, c->px, c->twx, fh::XF_UPDATE_R, bf.r, F,
+                                                 bf.q, F, bf.A, S, nload, L.st, c->stream)));
+      KT(FH_K_YFWD, HIPCHK(c, fh::launch_yfwd<T>(g, c->py, c->twy, bf.A, bf.B, S, nload, L.st,
+                                                 c->stream)));
+      KT(FH_K_ZSOLVE, HIPCHK(c, fh::launch_zpass<T>(g, c->pz, c->twz, fh::Z_SOLVE, bf.B, S,
+                                                    bf.kplus, nload, L.st, L.rz_part, &nbz,
+                                                    c->stream)));
       KT(FH_K_SCALAR, HIPCHK(c, fh::launch_finalize_beta(L.st, L.rz_part, nbz, nload, L.hist,
                                                          L.hist_len, c->stream)));
-      KT(FH_K_YINV, HIPCHK(c, fh::launch_yinv<double>(g, c->py, c->twy, L.B, L.A, S, nload, L.st,
-                                                      c->stream)));
-      KT(FH_K_XINV, HIPCHK(c, fh::launch_xinv<double>(g, c->px, c->twx, fh::XI_PCG, L.A, S,
-                                                      nullptr, L.x, L.p, F, nload, L.st,
-                                                      c->stream)));
+      KT(FH_K_YINV, HIPCHK(c, fh::launch_yinv<T>(g, c->py, c->twy, bf.B, bf.A, S, nload, L.st,
+                                                 c->stream)));
+      KT(FH_K_XINV, HIPCHK(c, fh::launch_xinv<T>(g, c->px, c->twx, fh::XI_PCG, bf.A, S, nullptr,
+                                                 bf.x, bf.p, F, nload, L.st, c->stream)));
     }
     HIPCHK(c, hipMemcpyAsync(hs.data(), L.st, sizeof(fh::PcgState) * nload,
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     kt_collect(c);
     bool any = false;
-    for (auto& s : hs) any |= (s.status == fh::ST_ACTIVE);
+    for (auto& st : hs) any |= (st.status == fh::ST_ACTIVE);
     if (!any || done_iters >= cap) break;
   }
   out = hs;
+  return FH_OK;
+}
+
+// Plain FP64 solve of K x = b for the right-hand sides in L.b.
+int pcg64(fh_ctx* c, int nload, double eta, int itmax, int poll, std::vector<fh::PcgState>& out) {
+  const long long F = (long long)c->g.nd * c->g.N;
+  fh_ctx::Layout& L = c->L;
+  HIPCHK(c, fh::launch_copy(L.r, L.b, F * nload, c->stream));
+  PcgBufs<double> bf{L.x, L.r, L.p, L.q, L.A, L.B, L.kplus};
+  return pcg_run<double>(c, nload, bf, eta, itmax, poll, std::vector<int>(nload, 1), out);
+}
+
+// FP32-in-FP64 iterative refinement (FH_FP32_REFINED).  Outer loop in FP64:
+// residual r = b - K x with the FP64 operator, its Kref^-1-norm sqrt(r.M r)
+// with the FP64 preconditioner (the same stopping rule as the plain solve,
+// relative to the norm of b), then an inner PCG in FP32 for K d = r to the
+// relative tolerance eta_inner and x += d in FP64.  out[j].iter holds the
+// summed inner iterations, outer[j] the number of sweeps.
+int pcg_refined(fh_ctx* c, int nload, double eta, double eta_in, int itmax, int poll,
+                std::vector<fh::PcgState>& out, std::vector<int>& outer) {
+  const fh::Grid& g = c->g;
+  const long long F = (long long)g.nd * g.N;
+  fh_ctx::Layout& L = c->L;
+  std::vector<double> rho0(nload, 0.0), rho(nload, 0.0);
+  std::vector<int> active(nload, 1), total(nload, 0), status(nload, fh::ST_ACTIVE);
+  std::vector<double> last(nload, 1.0);
+  outer.assign(nload, 0);
+  int* mask_dev = reinterpret_cast<int*>(L.scal + 32);
+  HIPCHK(c, fh::launch_fill<double>(L.x, 0.0, F * nload, c->stream));
+  HIPCHK(c, fh::launch_copy(L.r, L.b, F * nload, c->stream));
+  const int max_outer = 64;
+  for (int sweep = 0; sweep <= max_outer; ++sweep) {
+    // Kref^-1-norm of the FP64 residual
+    int rc = precond_fields(c, L.r, L.q, nload, F);
+    if (rc) return rc;
+    const int nb = 1024;
+    for (int j = 0; j < nload; ++j) {
+      if (!active[j]) continue;
+      HIPCHK(c, fh::launch_dot_partials(L.r + j * F, L.q + j * F, F, L.dot_part, nb, c->stream));
+      HIPCHK(c, fh::launch_sum_partials(L.dot_part, nb, L.scal + j, c->stream));
+    }
+    std::vector<double> dots(nload, 0.0);
+    HIPCHK(c, hipMemcpyAsync(dots.data(), L.scal, sizeof(double) * nload, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    bool any = false;
+    for (int j = 0; j < nload; ++j) {
+      if (!active[j]) continue;
+      rho[j] = dots[j];
+      if (sweep == 0) rho0[j] = rho[j];
+      if (!(rho0[j] > 0.0)) {
+        active[j] = 0;
+        status[j] = rho0[j] == 0.0 ? fh::ST_CONVERGED : fh::ST_BREAKDOWN;
+        last[j] = 0.0;
+        continue;
+      }
+      last[j] = rho[j] > 0.0 ? std::sqrt(rho[j] / rho0[j]) : 0.0;
+      if (rho[j] <= eta * eta * rho0[j]) {
+        active[j] = 0;
+        status[j] = fh::ST_CONVERGED;
+      } else if (sweep == max_outer || total[j] >= itmax) {
+        active[j] = 0;
+        status[j] = fh::ST_MAXIT;
+      }
+      any |= active[j] != 0;
+    }
+    if (!any) break;
+    // inner FP32 solve K d = r (cast per active load), d in x32
+    std::vector<fh::PcgState> ist(nload);
+    for (int j = 0; j < nload; ++j) {
+      ist[j] = fh::PcgState{};
+      ist[j].status = active[j] ? fh::ST_ACTIVE : fh::ST_CONVERGED;
+    }
+    HIPCHK(c, hipMemcpyAsync(L.st, ist.data(), sizeof(fh::PcgState) * nload,
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, fh::launch_cast_masked(L.r, L.r32, F, nload, L.st, c->stream));
+    PcgBufs<float> bf{L.x32, L.r32, L.p32, L.q32, L.A32, L.B32, L.kplus_f};
+    std::vector<fh::PcgState> hs;
+    rc = pcg_run<float>(c, nload, bf, eta_in, std::max(1, itmax), poll, active, hs);
+    if (rc) return rc;
+    for (int j = 0; j < nload; ++j)
+      if (active[j]) {
+        total[j] += hs[j].iter;
+        outer[j] += 1;
+        if (hs[j].status == fh::ST_BREAKDOWN) {
+          active[j] = 0;
+          status[j] = fh::ST_BREAKDOWN;
+        }
+      }
+    HIPCHK(c, hipMemcpyAsync(mask_dev, active.data(), sizeof(int) * nload, hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, fh::launch_add_masked(L.x, L.x32, F, nload, mask_dev, c->stream));
+    // r = b - K x in FP64
+    rc = apply_K(c, false, L.x, L.q, nload, F, nullptr, nullptr);
+    if (rc) return rc;
+    HIPCHK(c, fh::launch_residual(L.r, L.b, L.q, F * nload, c->stream));
+  }
+  out.assign(nload, fh::PcgState{});
+  for (int j = 0; j < nload; ++j) {
+    out[j].iter = total[j];
+    out[j].status = status[j] == fh::ST_ACTIVE ? fh::ST_MAXIT : status[j];
+    out[j].last = last[j];
+  }
   return FH_OK;
 }
 
@@ -953,21 +1090,13 @@ int fh_set_phases(fh_ctx* c, const uint8_t* phase_dev, int nphase, const double*
     if (all) {
       rc = upload(c, &c->lm_dev, &c->lm_dev_n, lm);
       if (rc) return rc;
-      hipFree(c->lm_dev_f);
-      c->lm_dev_f = nullptr;
-      std::vector<float> lf(lm.begin(), lm.end());
-      HIPCHK(c, hipMalloc((void**)&c->lm_dev_f, lf.size() * sizeof(float)));
-      HIPCHK(c, hipMemcpy(c->lm_dev_f, lf.data(), lf.size() * sizeof(float),
-                          hipMemcpyHostToDevice));
+      rc = upload_f(c, &c->lm_dev_f, lm);
+      if (rc) return rc;
       c->iso = true;
     }
-    hipFree(c->mat_dev_f);
-    c->mat_dev_f = nullptr;
-    std::vector<float> tf(tab.begin(), tab.end());
-    HIPCHK(c, hipMalloc((void**)&c->mat_dev_f, tf.size() * sizeof(float)));
-    HIPCHK(c, hipMemcpy(c->mat_dev_f, tf.data(), tf.size() * sizeof(float),
-                        hipMemcpyHostToDevice));
   }
+  rc = upload_f(c, &c->mat_dev_f, tab);
+  if (rc) return rc;
   c->symbol_ok = c->rhs_ok = c->solved = false;
   return FH_OK;
 }
@@ -985,7 +1114,10 @@ int fh_set_conductivity_field(fh_ctx* c, const double* k_dev) {
   std::vector<double> I((size_t)c->g.dim * c->g.dim, 0.0);
   for (int i = 0; i < c->g.dim; ++i) I[i * c->g.dim + i] = 1.0;
   c->mat = I;
-  int rc = upload(c, &c->mat_dev, &c->mat_dev_n, operator_tables(c, I.data(), 1));
+  std::vector<double> tab = operator_tables(c, I.data(), 1);
+  int rc = upload(c, &c->mat_dev, &c->mat_dev_n, tab);
+  if (rc) return rc;
+  rc = upload_f(c, &c->mat_dev_f, tab);
   if (rc) return rc;
   c->symbol_ok = c->rhs_ok = c->solved = false;
   return FH_OK;
@@ -1051,8 +1183,7 @@ int fh_solve(fh_ctx* c, const fh_opts* opt, fh_stats* st) {
   if (!(o.eta > 0.0) || o.itmax < 1) return fail(c, FH_EINVAL, "bad eta/itmax");
   if (o.precision != FH_FP64 && o.precision != FH_FP32_REFINED)
     return fail(c, FH_EINVAL, "bad precision");
-  if (o.precision == FH_FP32_REFINED)
-    return fail(c, FH_EINVAL, "FP32 refinement not available in this build");
+
   if (c->nload < 1) return fail(c, FH_ESTATE, "fh_set_load not called");
   const int poll = o.poll > 0 ? o.poll : 16;
   auto t0 = std::chrono::steady_clock::now();
@@ -1072,7 +1203,13 @@ int fh_solve(fh_ctx* c, const fh_opts* opt, fh_stats* st) {
   const double setup_ms = ms_since(t0);
   auto t1 = std::chrono::steady_clock::now();
   std::vector<fh::PcgState> hs;
-  rc = pcg64(c, c->nload, o.eta, o.itmax, poll, hs);
+  std::vector<int> outer;
+  if (o.precision == FH_FP32_REFINED) {
+    const double eta_in = o.eta_inner > 0.0 ? o.eta_inner : 1e-4;
+    rc = pcg_refined(c, c->nload, o.eta, eta_in, o.itmax, o.poll > 0 ? o.poll : 8, hs, outer);
+  } else {
+    rc = pcg64(c, c->nload, o.eta, o.itmax, poll, hs);
+  }
   if (rc) return rc;
   const double solve_ms = ms_since(t1);
   auto t2 = std::chrono::steady_clock::now();
@@ -1117,9 +1254,12 @@ int fh_solve(fh_ctx* c, const fh_opts* opt, fh_stats* st) {
           e + (-bu[(size_t)i * nl + j] - bu[(size_t)j * nl + i] + uKu[(size_t)i * nl + j]) / vol;
     }
   const double chom_ms = ms_since(t2);
-  record_history(c, hs, nl);
+  if (o.precision == FH_FP32_REFINED) c->history.assign(nl, {});
+  else record_history(c, hs, nl);
   c->solved = true;
   rc = fill_stats(c, hs, nl, st);
+  for (int j = 0; j < nl && j < FH_MAX_LOADS && j < (int)outer.size(); ++j)
+    c->last.outer[j] = outer[j];
   c->last.setup_ms = setup_ms;
   c->last.solve_ms = solve_ms;
   c->last.chom_ms = chom_ms;

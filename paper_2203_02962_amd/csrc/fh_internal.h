@@ -148,6 +148,12 @@ hipError_t launch_cast_d2f(const double* src, float* dst, long long n, hipStream
 hipError_t launch_add_f2d(double* dst, const float* src, long long n, hipStream_t s);
 hipError_t launch_residual(double* r, const double* b, const double* Kx, long long n,
                            hipStream_t s);
+// per load case (blockIdx.y): dst = (float) src where the load is active;
+// dst += src where mask[load] != 0
+hipError_t launch_cast_masked(const double* src, float* dst, long long F, int nload,
+                              const PcgState* st, hipStream_t s);
+hipError_t launch_add_masked(double* dst, const float* src, long long F, int nload,
+                             const int* mask, hipStream_t s);
 hipError_t launch_impulse(double* f, long long n, long long pos, hipStream_t s);
 hipError_t launch_field_sum(const double* x, long long n, double* out_part, int nb,
                             hipStream_t s);

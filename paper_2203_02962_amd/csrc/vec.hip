@@ -31,6 +31,7 @@ __device__ double sum_parts(const double* part, int nb, double* sh) {
 __global__ void k_finalize_init(PcgState* st, const double* part, int nb) {
   __shared__ double sh[256];
   const int ld = blockIdx.x;
+  if (st[ld].status != ST_ACTIVE) return;  // load case masked out by the caller
   const double rho = sum_parts(part + (long long)ld * nb, nb, sh);
   if (threadIdx.x == 0) {
     st[ld].rho = rho;
@@ -201,6 +202,23 @@ __global__ void k_add_f2d(double* d, const float* s, long long n) {
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
     d[i] += (double)s[i];
 }
+__global__ void k_cast_masked(const double* src, float* dst, long long F, const PcgState* st) {
+  // one load case per blockIdx.y; skipped when its state is not active
+  const int ld = blockIdx.y;
+  if (st && st[ld].status != ST_ACTIVE) return;
+  const double* s = src + (long long)ld * F;
+  float* d = dst + (long long)ld * F;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < F; i += (long long)gridDim.x * 256)
+    d[i] = (float)s[i];
+}
+__global__ void k_add_masked(double* dst, const float* src, long long F, const int* mask) {
+  const int ld = blockIdx.y;
+  if (!mask[ld]) return;
+  double* d = dst + (long long)ld * F;
+  const float* s = src + (long long)ld * F;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < F; i += (long long)gridDim.x * 256)
+    d[i] += (double)s[i];
+}
 __global__ void k_residual(double* r, const double* b, const double* Kx, long long n) {
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
     r[i] = b[i] - Kx[i];
@@ -239,6 +257,20 @@ hipError_t launch_cast_d2f(const double* src, float* dst, long long n, hipStream
 }
 hipError_t launch_add_f2d(double* dst, const float* src, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_add_f2d, ew_grid(n), dim3(256), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+hipError_t launch_cast_masked(const double* src, float* dst, long long F, int nload,
+                              const PcgState* st, hipStream_t s) {
+  dim3 g = ew_grid(F);
+  g.y = nload;
+  hipLaunchKernelGGL(k_cast_masked, g, dim3(256), 0, s, src, dst, F, st);
+  return hipGetLastError();
+}
+hipError_t launch_add_masked(double* dst, const float* src, long long F, int nload,
+                             const int* mask, hipStream_t s) {
+  dim3 g = ew_grid(F);
+  g.y = nload;
+  hipLaunchKernelGGL(k_add_masked, g, dim3(256), 0, s, dst, src, F, mask);
   return hipGetLastError();
 }
 hipError_t launch_residual(double* r, const double* b, const double* Kx, long long n,

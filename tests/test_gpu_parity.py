@@ -300,3 +300,30 @@ def test_full_size_128_matches_stored_oracle(fh):
     assert _rel(ctx.get_reference(), np.array(g["Cref"])) < 4 * 128 ** 3 * 2.2e-16
     for a, b in zip(st["iterations"], g["iterations"]):
         assert abs(a - b) <= max(1, int(0.01 * b))
+
+
+REFINED_CASES = [
+    ("elastic-spheres-24", lambda: _spheres_case(24, (2.5, 4.5), 100.0, 0)),
+    ("scalar-hex8-field-16", lambda: _field_case(16)),
+    ("elastic-aniso-random-12x18x24", lambda: _case("hex8", "elastic", (12, 18, 24))),
+]
+
+
+@pytest.mark.parametrize("name,make", REFINED_CASES, ids=[c[0] for c in REFINED_CASES])
+def test_fp32_refined_solve_reaches_fp64_accuracy(fh, name, make):
+    """FP32 operator/FFT/solve inside FP64 refinement: the outer residual and
+    its Kref^-1-norm are FP64, so the refined result meets the same stopping
+    rule as the plain solve and C_hom agrees with the oracle to 1e-10."""
+    say("fp32 refined", name)
+    wl, prob = make()
+    ctx = _ctx(fh, wl)
+    rc, st = ctx.solve(eta=1e-10, precision=fh.FH_FP32_REFINED, eta_inner=1e-4)
+    assert rc == 0, st
+    H = ctx.get_homogenized()
+    Ho, _, res = oracle.homogenize(prob, wl["loads"], 1e-10)
+    assert _rel(H, Ho) < 1e-10
+    assert all(o >= 2 for o in st["outer"])            # more than one sweep to 1e-10
+    assert all(r <= 1e-10 for r in st["rel_res"])
+    # plain FP64 to the same tolerance for reference: same answer
+    rc2, st2 = ctx.solve(eta=1e-10)
+    assert _rel(ctx.get_homogenized(), H) < 1e-10
