@@ -89,6 +89,57 @@ def cpu_baseline(wl, iters: int):
     }
 
 
+def batch_comparison(count: int):
+    """`count` seeded microstructures (n ~ U{32,48,64,96}, vf ~ U[0.1,0.4],
+    contrast ~ U[10,1000]) x 6 unit loads to eta = 1e-6: one batched
+    FP32-refined call vs the plain FP64 solver called system by system."""
+    import numpy as np
+    import torch
+
+    from paper_2203_02962_amd import fh
+    from paper_2203_02962_amd.runner import setup_context
+    from synth import batch_workload
+
+    print(f"[bench] batch: generating {count} microstructures", file=sys.stderr, flush=True)
+    wls = batch_workload(count=count)
+    devs = [(torch.from_numpy(w["phase"]).cuda(), w["n"], w["mat"]) for w in wls]
+    ctx = fh.Context(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, Hb, sts, rep = ctx.solve_batch(devs, np.eye(6), eta=1e-6, precision=fh.FH_FP32_REFINED)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) * 1000.0
+    print(f"[bench] batch solved in {t_batch:.0f} ms (rc {rc})", file=sys.stderr, flush=True)
+    inner = sum(sum(s["iterations"]) for s in sts)
+    dof_iters = sum(s["dof"] * sum(s["iterations"]) for s in sts)
+    t_plain = 0.0
+    diffs = []
+    plain_iters = 0
+    for w, Hi in zip(wls, Hb):
+        c1 = setup_context(w)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        rc1, st1 = c1.solve(eta=1e-6)
+        torch.cuda.synchronize()
+        t_plain += (time.perf_counter() - ta) * 1000.0
+        plain_iters += sum(st1["iterations"])
+        Hp = c1.get_homogenized()
+        diffs.append(float(np.abs(Hi - Hp).max() / np.abs(Hp).max()))
+        c1.close()
+    return {
+        "systems": count, "solves": 6 * count,
+        "voxels_total": int(sum(np.prod(w["n"]) for w in wls)),
+        "batched_fp32_refined_ms": round(t_batch, 1),
+        "plain_fp64_sequential_ms": round(t_plain, 1),
+        "speedup": round(t_plain / t_batch, 3),
+        "batched_inner_iterations_total": int(inner),
+        "plain_iterations_total": int(plain_iters),
+        "batched_dof_iter_per_s": dof_iters / (t_batch / 1000.0),
+        "max_chom_rel_diff_batched_vs_plain": max(diffs),
+        "groups": rep,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +150,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-kernels", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 96-microstructure batched comparison")
+    ap.add_argument("--batch-count", type=int, default=96)
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run a plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -158,7 +212,7 @@ def main():
         return (time.perf_counter() - ta) * 1000.0, rcx, stx
     t_1e6, rc6, st6 = timed_solve(eta=1e-6)
     from paper_2203_02962_amd.fh import FH_FP32_REFINED
-    t_1e6_r, rc6r, st6r = timed_solve(eta=1e-6, precision=FH_FP32_REFINED, eta_inner=1e-4)
+    t_1e6_r, rc6r, st6r = timed_solve(eta=1e-6, precision=FH_FP32_REFINED)
     H6r = ctx.get_homogenized()
     t_1e10_r, rc10r, st10r = timed_solve(eta=args.eta, precision=FH_FP32_REFINED, eta_inner=1e-4)
     H10r = ctx.get_homogenized()
@@ -240,6 +294,8 @@ def main():
         "kernels": kernels,
         "roofline": roof,
     }
+    if not args.no_batch:
+        out["config"]["batched_vs_plain_1e-6"] = batch_comparison(args.batch_count)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_iters)

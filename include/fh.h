@@ -97,7 +97,8 @@ typedef struct fh_opts {
   int precision;    /* FH_FP64 or FH_FP32_REFINED                                 */
   int poll;         /* iterations between host convergence polls (0 = default)   */
   int flags;        /* FH_FLAG_* bits                                             */
-  double eta_inner; /* inner FP32 tolerance for FH_FP32_REFINED (0 = default)    */
+  double eta_inner; /* inner FP32 tolerance for FH_FP32_REFINED (0 = eta/2 when
+                       eta >= 1e-6, else 1e-4)                                    */
 } fh_opts;
 
 typedef struct fh_stats {
@@ -185,6 +186,40 @@ int fh_compute_rhs(fh_ctx *ctx, const double *E, double *b_dev);
 int fh_get_symbol(fh_ctx *ctx, double *kplus_dev);
 int fh_solve_rhs(fh_ctx *ctx, const double *b_dev, double *u_dev, const fh_opts *opt,
                  fh_stats *st);
+
+/* ------------------------------------------------------------ batches
+ * Many independent microstructures (possibly of different grid sizes), each
+ * solved for the same nload macroscopic strains.  Systems are grouped by grid
+ * size; within a group every stage of an iteration is one launch over all
+ * microstructures x load cases, one PCG iteration is captured in a hipGraph
+ * and replayed, and the launch shapes (operator z-chunk, FFT lines per block)
+ * are chosen per grid size by timing candidates on the group's own data.
+ * Every microstructure gets its own mean reference material and Alg. 2
+ * symbol.  Phases must be isotropic (C = lambda 1(x)1 + 2 mu I, Mandel).  */
+typedef struct fh_system {
+  const uint8_t *phase_dev; /* n0*n1*n2 bytes on the device                  */
+  int n[3];                 /* 3D grid, sizes as for fh_set_grid             */
+  int nphase;               /* 1..16                                         */
+  const double *mat;        /* nphase x 6 x 6 Mandel stiffness tables (host)  */
+} fh_system;
+
+#define FH_MAX_GROUPS 16
+typedef struct fh_batch_report {
+  int ngroups;
+  int n[FH_MAX_GROUPS][3];
+  int nsys[FH_MAX_GROUPS];
+  int kz[FH_MAX_GROUPS], zb[FH_MAX_GROUPS], kyb[FH_MAX_GROUPS]; /* tuned shapes */
+  double tune_ms[FH_MAX_GROUPS], setup_ms[FH_MAX_GROUPS], solve_ms[FH_MAX_GROUPS];
+} fh_batch_report;
+
+/* Solve nsys systems (elasticity, FH_HEX8) for the nload strains E (host,
+ * nload x 6 Mandel, nload <= 8).  chom (host, nsys x nload x nload) receives
+ * each system's homogenized tensor in energy form; st (may be NULL) one
+ * fh_stats per system; rep (may be NULL) the per-group tuning and timings.
+ * opt as for fh_solve (FH_FP32_REFINED recommended).  At most FH_MAX_GROUPS
+ * distinct grid sizes.  Device scratch is allocated inside the call.       */
+int fh_solve_batch(fh_ctx *ctx, int nsys, const fh_system *sys, int nload, const double *E,
+                   const fh_opts *opt, double *chom, fh_stats *st, fh_batch_report *rep);
 
 #ifdef __cplusplus
 }

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <functional>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -86,6 +88,8 @@ struct fh_ctx {
     double *d64;  // refinement: correction accumulator
     fh::PcgState* st;
     double *pq_part, *rz_part, *hist, *dot_part, *scal;
+    double *sysdot, *sysdot_part;  // one dot per system (refinement norms)
+    int* mask;                     // per-system flags
     uint8_t* phase0;
     int nb_kop, nb_z, nb_z32, hist_len;
   } L{};
@@ -102,6 +106,13 @@ struct fh_ctx {
     double ms[FH_K_NCLASS] = {};
     long long n[FH_K_NCLASS] = {};
   } kt;
+
+  // batched solves: nms microstructures of this grid, G = loads each
+  int nms = 1;
+  bool use_graph = false;
+  bool own_stream = false;
+  uint8_t* phase_pack = nullptr;
+  std::vector<std::vector<double>> cmean_ms;
 
   bool symbol_ok = false;
   bool rhs_ok = false;
@@ -390,8 +401,8 @@ size_t layout(fh_ctx* c, char* base, fh_ctx::Layout* Lout) {
   L.A = (cplx<double>*)take(sizeof(cplx<double>) * S * nl);
   L.B = (cplx<double>*)take(sizeof(cplx<double>) * S * nl);
   L.spec = (cplx<double>*)take(sizeof(cplx<double>) * S * g.nd);
-  L.kplus = (double*)take(sizeof(double) * nfreq * nsym);
-  L.kplus_f = (float*)take(sizeof(float) * nfreq * nsym);
+  L.kplus = (double*)take(sizeof(double) * nfreq * nsym * c->nms);
+  L.kplus_f = (float*)take(sizeof(float) * nfreq * nsym * c->nms);
   L.x32 = (float*)take(sizeof(float) * F * nl);
   L.r32 = (float*)take(sizeof(float) * F * nl);
   L.p32 = (float*)take(sizeof(float) * F * nl);
@@ -401,9 +412,15 @@ size_t layout(fh_ctx* c, char* base, fh_ctx::Layout* Lout) {
   L.d64 = (double*)take(sizeof(double) * F * nl);
   L.kf32 = (float*)take(sizeof(float) * (size_t)g.N);
   L.st = (fh::PcgState*)take(sizeof(fh::PcgState) * nl);
-  L.nb_kop = fh::kop_nblocks(g, hex_elastic(c));
-  L.nb_z = fh::zpass_nblocks<double>(g);
-  L.nb_z32 = fh::zpass_nblocks<float>(g);
+  {
+    // partial sums sized for the smallest launch shapes the tuner may pick
+    fh::Grid gw = g;
+    gw.kz = 4;
+    gw.kyb = 1;
+    L.nb_kop = fh::kop_nblocks(gw, hex_elastic(c));
+    L.nb_z = fh::zpass_nblocks<double>(gw);
+    L.nb_z32 = fh::zpass_nblocks<float>(gw);
+  }
   const int nbz = std::max(L.nb_z, L.nb_z32);
   L.pq_part = (double*)take(sizeof(double) * (size_t)L.nb_kop * nl);
   L.rz_part = (double*)take(sizeof(double) * (size_t)nbz * nl);
@@ -411,6 +428,9 @@ size_t layout(fh_ctx* c, char* base, fh_ctx::Layout* Lout) {
   L.hist = (double*)take(sizeof(double) * (size_t)L.hist_len * nl);
   L.dot_part = (double*)take(sizeof(double) * 1024);
   L.scal = (double*)take(sizeof(double) * 64);
+  L.sysdot = (double*)take(sizeof(double) * nl);
+  L.sysdot_part = (double*)take(sizeof(double) * nl * 64);
+  L.mask = (int*)take(sizeof(int) * nl);
   L.phase0 = (uint8_t*)take((size_t)g.N);
   L.bytes = off;
   if (Lout) *Lout = L;
@@ -728,14 +748,12 @@ int pcg_run(fh_ctx* c, int nload, const PcgBufs<T>& bf, double eta, int itmax, i
   HIPCHK(c, fh::launch_xinv<T>(g, c->px, c->twx, fh::XI_INIT_P, bf.A, S, nullptr, nullptr, bf.p,
                                F, nload, L.st, c->stream));
   HIPCHK(c, fh::launch_finalize_init(L.st, L.rz_part, nbz, nload, c->stream));
-  int done_iters = 0;
-  const int cap = itmax + 2;
-  while (true) {
-    for (int k = 0; k < poll && done_iters < cap; ++k, ++done_iters) {
+  const int nbk = fh::kop_nblocks(g, hex_elastic(c));
+  auto one_iteration = [&]() -> int {
       int rc = 0;
       KT(FH_K_OPERATOR, rc = apply_KT(c, bf.p, bf.q, nload, F, L.st, L.pq_part));
       if (rc) return rc;
-      KT(FH_K_SCALAR, HIPCHK(c, fh::launch_finalize_alpha(L.st, L.pq_part, L.nb_kop, nload,
+      KT(FH_K_SCALAR, HIPCHK(c, fh::launch_finalize_alpha(L.st, L.pq_part, nbk, nload,
                                                           c->stream)));
       KT(FH_K_XFWD, HIPCHK(c, fh::launch_xfwd<T>(g, c->px, c->twx, fh::XF_UPDATE_R, bf.r, F,
                                                  bf.q, F, bf.A, S, nload, L.st, c->stream)));
@@ -750,6 +768,43 @@ int pcg_run(fh_ctx* c, int nload, const PcgBufs<T>& bf, double eta, int itmax, i
                                                  c->stream)));
       KT(FH_K_XINV, HIPCHK(c, fh::launch_xinv<T>(g, c->px, c->twx, fh::XI_PCG, bf.A, S, nullptr,
                                                  bf.x, bf.p, F, nload, L.st, c->stream)));
+      return FH_OK;
+  };
+  // Batched solves capture one iteration (all kernels, all systems) in a
+  // hipGraph and replay it; kernels read everything that changes from the
+  // device-resident PCG state, so the same graph serves every iteration.
+  hipGraphExec_t exec = nullptr;
+  if (c->use_graph) {
+    hipGraph_t graph = nullptr;
+    const bool kt_was = c->kt.on;
+    c->kt.on = false;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    const int rc = one_iteration();
+    const hipError_t e = hipStreamEndCapture(c->stream, &graph);
+    c->kt.on = kt_was;
+    if (rc) {
+      if (graph) hipGraphDestroy(graph);
+      return rc;
+    }
+    HIPCHK(c, e);
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    HIPCHK(c, ei);
+  }
+  struct ExecGuard {
+    hipGraphExec_t e;
+    ~ExecGuard() { if (e) hipGraphExecDestroy(e); }
+  } guard{exec};
+  int done_iters = 0;
+  const int cap = itmax + 2;
+  while (true) {
+    for (int k = 0; k < poll && done_iters < cap; ++k, ++done_iters) {
+      if (exec) {
+        HIPCHK(c, hipGraphLaunch(exec, c->stream));
+      } else {
+        const int rc = one_iteration();
+        if (rc) return rc;
+      }
     }
     HIPCHK(c, hipMemcpyAsync(hs.data(), L.st, sizeof(fh::PcgState) * nload,
                              hipMemcpyDeviceToHost, c->stream));
@@ -772,6 +827,14 @@ int pcg64(fh_ctx* c, int nload, double eta, int itmax, int poll, std::vector<fh:
   return pcg_run<double>(c, nload, bf, eta, itmax, poll, std::vector<int>(nload, 1), out);
 }
 
+// Inner FP32 tolerance when the caller gives none: a loose outer target is
+// met in about one sweep (eta/2); tight targets use 1e-4 per sweep, well
+// above the level where FP32 PCG stagnates.
+double default_eta_inner(const fh_opts& o) {
+  if (o.eta_inner > 0.0) return o.eta_inner;
+  return o.eta >= 1e-6 ? 0.5 * o.eta : 1e-4;
+}
+
 // FP32-in-FP64 iterative refinement (FH_FP32_REFINED).  Outer loop in FP64:
 // residual r = b - K x with the FP64 operator, its Kref^-1-norm sqrt(r.M r)
 // with the FP64 preconditioner (the same stopping rule as the plain solve,
@@ -787,7 +850,7 @@ int pcg_refined(fh_ctx* c, int nload, double eta, double eta_in, int itmax, int 
   std::vector<int> active(nload, 1), total(nload, 0), status(nload, fh::ST_ACTIVE);
   std::vector<double> last(nload, 1.0);
   outer.assign(nload, 0);
-  int* mask_dev = reinterpret_cast<int*>(L.scal + 32);
+  int* mask_dev = L.mask;
   HIPCHK(c, fh::launch_fill<double>(L.x, 0.0, F * nload, c->stream));
   HIPCHK(c, fh::launch_copy(L.r, L.b, F * nload, c->stream));
   const int max_outer = 64;
@@ -795,15 +858,12 @@ int pcg_refined(fh_ctx* c, int nload, double eta, double eta_in, int itmax, int 
     // Kref^-1-norm of the FP64 residual
     int rc = precond_fields(c, L.r, L.q, nload, F);
     if (rc) return rc;
-    const int nb = 1024;
-    for (int j = 0; j < nload; ++j) {
-      if (!active[j]) continue;
-      HIPCHK(c, fh::launch_dot_partials(L.r + j * F, L.q + j * F, F, L.dot_part, nb, c->stream));
-      HIPCHK(c, fh::launch_sum_partials(L.dot_part, nb, L.scal + j, c->stream));
-    }
+    // r_j . z_j for every system in one launch (fixed-order sums)
+    HIPCHK(c, fh::launch_pair_dots(L.r, L.q, F, 1, nload, 64, L.sysdot_part, L.sysdot,
+                                   c->stream));
     std::vector<double> dots(nload, 0.0);
-    HIPCHK(c, hipMemcpyAsync(dots.data(), L.scal, sizeof(double) * nload, hipMemcpyDeviceToHost,
-                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(dots.data(), L.sysdot, sizeof(double) * nload,
+                             hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     bool any = false;
     for (int j = 0; j < nload; ++j) {
@@ -958,6 +1018,325 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 
 }  // namespace
 
+
+// ================================================================ batches
+namespace {
+
+double time_launches(fh_ctx* c, const std::function<int()>& launch, int reps) {
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return 1e30;
+  if (hipEventCreate(&b) != hipSuccess) {
+    hipEventDestroy(a);
+    return 1e30;
+  }
+  double ms = 1e30;
+  if (launch() == FH_OK) {  // warm-up
+    hipEventRecord(a, c->stream);
+    bool ok = true;
+    for (int r = 0; r < reps && ok; ++r) ok = launch() == FH_OK;
+    hipEventRecord(b, c->stream);
+    float t = 0.f;
+    if (ok && hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&t, a, b) == hipSuccess)
+      ms = t / reps;
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return ms;
+}
+
+// Choose the operator z-chunk and the FFT lines per block for this grid by
+// timing the FP32 kernels (the refinement's inner loop) on the group's own
+// buffers.
+int autotune(fh_ctx* c, int nload_total, double* tune_ms) {
+  auto t0 = std::chrono::steady_clock::now();
+  fh::Grid& g = c->g;
+  const long long F = (long long)g.nd * g.N;
+  const long long S = (long long)g.nd * g.nxh * g.ny * g.nz;
+  fh_ctx::Layout& L = c->L;
+  HIPCHK(c, fh::launch_fill<float>(L.p32, 0.f, F * nload_total, c->stream));
+  HIPCHK(c, fh::launch_fill<float>(L.q32, 0.f, F * nload_total, c->stream));
+  const int reps = 3;
+  int best = g.kz;
+  double bt = 1e30;
+  for (int kz : {4, 8, 16, 32}) {
+    if (kz > g.nz) continue;
+    g.kz = kz;
+    const double t = time_launches(c, [&] {
+      return apply_K32(c, L.p32, L.q32, nload_total, F, nullptr, nullptr);
+    }, reps);
+    if (t < bt) { bt = t; best = kz; }
+  }
+  g.kz = best;
+  best = 0;
+  bt = 1e30;
+  for (int zb : {2, 4, 8, 16}) {
+    if (zb * g.ny > 2048 || zb > g.nz) continue;
+    g.zb = zb;
+    const double t = time_launches(c, [&] {
+      return fh::launch_yfwd<float>(g, c->py, c->twy, L.A32, L.B32, S, nload_total, nullptr,
+                                    c->stream) == hipSuccess ? FH_OK : FH_EDEVICE;
+    }, reps);
+    if (t < bt) { bt = t; best = zb; }
+  }
+  g.zb = best;
+  best = 0;
+  bt = 1e30;
+  for (int kyb : {1, 2, 4, 8, 16}) {
+    if (kyb * g.nd * g.nz > 2048 || kyb > g.ny) continue;
+    g.kyb = kyb;
+    int nb = 0;
+    const double t = time_launches(c, [&] {
+      return fh::launch_zpass<float>(g, c->pz, c->twz, fh::Z_FORWARD_ONLY, L.B32, S, nullptr,
+                                     nload_total, nullptr, nullptr, &nb,
+                                     c->stream) == hipSuccess ? FH_OK : FH_EDEVICE;
+    }, reps);
+    if (t < bt) { bt = t; best = kyb; }
+  }
+  g.kyb = best;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *tune_ms = ms_since(t0);
+  return FH_OK;
+}
+
+int batch_group(fh_ctx* parent, const std::vector<int>& idx, const fh_system* sys, int nload,
+                const double* E, const fh_opts& o, double* chom, fh_stats* st,
+                fh_batch_report* rep, int gi) {
+  fh_ctx* c = nullptr;
+  if (fh_create(&c, parent->device) != FH_OK) return fail(parent, FH_EDEVICE, "fh_create");
+  struct Owner {
+    fh_ctx* c;
+    ~Owner() { fh_destroy(c); }
+  } owner{c};
+  auto pfail = [&](int rc) { return fail(parent, rc, c->err); };
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
+    return fail(parent, FH_EDEVICE, "stream creation failed");
+  c->own_stream = true;
+  const fh_system& s0 = sys[idx[0]];
+  int rc = fh_set_grid(c, 3, s0.n, nullptr, FH_ELASTIC, FH_HEX8);
+  if (rc) return pfail(rc);
+  auto t0 = std::chrono::steady_clock::now();
+  const fh::Grid g0 = c->g;
+  const int nms = (int)idx.size();
+  const long long N = g0.N, F = 3 * N;
+  const long long nfreq = (long long)g0.nxh * g0.ny * g0.nz;
+  const long long S = 3 * nfreq;
+  const double Vp = voxel_volume(c);
+  int np = 1;
+  for (int i : idx) np = std::max(np, sys[i].nphase);
+  // packed phases and per-microstructure {V lambda, 2 V mu} tables
+  if (hipMalloc((void**)&c->phase_pack, (size_t)nms * N) != hipSuccess)
+    return fail(parent, FH_ENOMEM, "phase pack allocation failed");
+  std::vector<double> lm((size_t)nms * 2 * np, 0.0);
+  for (int ms = 0; ms < nms; ++ms) {
+    const fh_system& sy = sys[idx[ms]];
+    HIPCHK(parent, hipMemcpyAsync(c->phase_pack + (size_t)ms * N, sy.phase_dev, (size_t)N,
+                                  hipMemcpyDeviceToDevice, c->stream));
+    for (int p = 0; p < sy.nphase; ++p)
+      if (!isotropic_lm(sy.mat + (size_t)p * 36, Vp, lm.data() + ((size_t)ms * np + p) * 2))
+        return fail(parent, FH_EINVAL, "batched solves need isotropic phases");
+  }
+  if ((rc = upload(c, &c->lm_dev, &c->lm_dev_n, lm)) || (rc = upload_f(c, &c->lm_dev_f, lm)))
+    return pfail(rc);
+  c->iso = true;
+  c->mat_kind = 1;
+  c->phase_dev = c->phase_pack;
+  c->nphase = np;
+  c->g.nphase_max = np;
+  c->phases_checked = true;
+  c->nms = nms;
+  c->nload = nms * nload;
+  c->loads.clear();
+  for (int ms = 0; ms < nms; ++ms) c->loads.insert(c->loads.end(), E, E + (size_t)nload * 6);
+  if ((rc = ensure_layout(c))) return pfail(rc);
+  fh_ctx::Layout& L = c->L;
+  // per microstructure: Cref = mean (Sec. 6.2), Alg. 2 symbol, right-hand sides
+  c->cmean_ms.assign(nms, std::vector<double>(36, 0.0));
+  for (int ms = 0; ms < nms; ++ms) {
+    const fh_system& sy = sys[idx[ms]];
+    HIPCHK(parent, hipMemsetAsync(c->flag_dev, 0, sizeof(int), c->stream));
+    HIPCHK(parent, hipMemsetAsync(c->counts_dev, 0, 256 * sizeof(unsigned long long), c->stream));
+    HIPCHK(parent, fh::launch_phase_count(c->phase_pack + (size_t)ms * N, N, sy.nphase,
+                                          c->counts_dev, c->flag_dev, c->stream));
+    unsigned long long counts[256];
+    int bad = 0;
+    HIPCHK(parent, hipMemcpyAsync(counts, c->counts_dev, sizeof(counts), hipMemcpyDeviceToHost,
+                                  c->stream));
+    HIPCHK(parent, hipMemcpyAsync(&bad, c->flag_dev, sizeof(int), hipMemcpyDeviceToHost,
+                                  c->stream));
+    HIPCHK(parent, hipStreamSynchronize(c->stream));
+    if (bad) return fail(parent, FH_EINVAL, "phase id >= nphase in a batched system");
+    std::vector<double>& cm = c->cmean_ms[ms];
+    for (int p = 0; p < sy.nphase; ++p)
+      for (int i = 0; i < 36; ++i) cm[i] += (double)counts[p] * sy.mat[(size_t)p * 36 + i];
+    for (double& v : cm) v /= (double)N;
+    std::vector<double> rlm(2);
+    if (!cholesky_ok(cm, 6) || !isotropic_lm(cm.data(), Vp, rlm.data()))
+      return fail(parent, FH_ENOTSPD, "mean reference material not SPD/isotropic");
+    if ((rc = upload(c, &c->ref_lm_dev, &c->ref_lm_dev_n, rlm))) return pfail(rc);
+    c->ref_iso = true;
+    c->cref = cm;
+    for (int be = 0; be < 3; ++be) {
+      HIPCHK(parent, fh::launch_impulse(L.x, F, (long long)be * N, c->stream));
+      if ((rc = apply_K(c, true, L.x, L.q, 1, F, nullptr, nullptr))) return pfail(rc);
+      HIPCHK(parent, fh::launch_xfwd<double>(c->g, c->px, c->twx, fh::XF_PLAIN, L.q, F, nullptr,
+                                             0, L.A, S, 1, nullptr, c->stream));
+      HIPCHK(parent, fh::launch_yfwd<double>(c->g, c->py, c->twy, L.A, L.spec + be * S, S, 1,
+                                             nullptr, c->stream));
+      int nb = 0;
+      HIPCHK(parent, fh::launch_zpass<double>(c->g, c->pz, c->twz, fh::Z_FORWARD_ONLY,
+                                              L.spec + be * S, S, nullptr, 1, nullptr, nullptr,
+                                              &nb, c->stream));
+    }
+    HIPCHK(parent, hipMemsetAsync(c->flag_dev, 0, sizeof(int), c->stream));
+    HIPCHK(parent, fh::launch_symbol(c->g, L.spec, S, L.kplus + (size_t)ms * 6 * nfreq,
+                                     c->flag_dev, c->stream));
+    std::vector<double> fe;
+    for (int p = 0; p < np; ++p)
+      for (int j = 0; j < nload; ++j) {
+        std::vector<double> f(24, 0.0);
+        if (p < sy.nphase) f = uniform_strain_force(c, sy.mat + (size_t)p * 36, E + (size_t)j * 6);
+        fe.insert(fe.end(), f.begin(), f.end());
+      }
+    if ((rc = upload(c, &c->fe_dev, &c->fe_dev_n, fe))) return pfail(rc);
+    HIPCHK(parent, fh::launch_rhs(c->g, c->element, c->phase_pack + (size_t)ms * N, nullptr,
+                                  c->fe_dev, np, nload, L.b + (size_t)ms * nload * F, F,
+                                  c->stream));
+    HIPCHK(parent, hipMemcpyAsync(&bad, c->flag_dev, sizeof(int), hipMemcpyDeviceToHost,
+                                  c->stream));
+    HIPCHK(parent, hipStreamSynchronize(c->stream));
+    if (bad) return fail(parent, FH_ENOTSPD, "reference symbol has a non-SPD block");
+  }
+  HIPCHK(parent, fh::launch_cast_symbol((long long)nms * 6 * nfreq, L.kplus, L.kplus_f,
+                                        c->stream));
+  c->symbol_ok = c->rhs_ok = true;
+  // batched addressing: system ld -> microstructure ld / nload
+  c->g.G = nload;
+  c->g.phase_stride = N;
+  c->g.kplus_stride = 6 * nfreq;
+  c->g.lm_stride = 2 * np;
+  HIPCHK(parent, hipStreamSynchronize(c->stream));
+  const double setup_ms = ms_since(t0);
+  double tune_ms = 0.0;
+  if ((rc = autotune(c, c->nload, &tune_ms))) return pfail(rc);
+  // solve all microstructures x loads together
+  auto t1 = std::chrono::steady_clock::now();
+  c->use_graph = true;
+  std::vector<fh::PcgState> hs;
+  std::vector<int> outer;
+  if (o.precision == FH_FP32_REFINED)
+    rc = pcg_refined(c, c->nload, o.eta, default_eta_inner(o), o.itmax,
+                     o.poll > 0 ? o.poll : 8, hs, outer);
+  else
+    rc = pcg64(c, c->nload, o.eta, o.itmax, o.poll > 0 ? o.poll : 16, hs);
+  if (rc) return pfail(rc);
+  // homogenized tensors (energy form, as fh_solve)
+  if ((rc = apply_K(c, false, L.x, L.q, c->nload, F, nullptr, nullptr))) return pfail(rc);
+  const int nchunk = 64;
+  double* part = nullptr;
+  double* dots = nullptr;
+  HIPCHK(parent, hipMalloc((void**)&part, sizeof(double) * (size_t)nms * nchunk * nload * nload));
+  HIPCHK(parent, hipMalloc((void**)&dots, sizeof(double) * (size_t)2 * nms * nload * nload));
+  hipError_t e1 = fh::launch_pair_dots(L.b, L.x, F, nload, nms, nchunk, part, dots, c->stream);
+  hipError_t e2 = fh::launch_pair_dots(L.x, L.q, F, nload, nms, nchunk, part,
+                                       dots + (size_t)nms * nload * nload, c->stream);
+  std::vector<double> hd((size_t)2 * nms * nload * nload);
+  hipError_t e3 = hipMemcpyAsync(hd.data(), dots, hd.size() * sizeof(double),
+                                 hipMemcpyDeviceToHost, c->stream);
+  hipError_t e4 = hipStreamSynchronize(c->stream);
+  hipFree(part);
+  hipFree(dots);
+  if (e1 || e2 || e3 || e4) return fail(parent, FH_EDEVICE, "batched C_hom reduction failed");
+  const double solve_ms = ms_since(t1);
+  const double vol = c->l[0] * c->l[1] * c->l[2];
+  for (int ms = 0; ms < nms; ++ms) {
+    const int sid = idx[ms];
+    const double* bu = hd.data() + (size_t)ms * nload * nload;
+    const double* uk = hd.data() + ((size_t)nms + ms) * nload * nload;
+    double* H = chom + (size_t)sid * nload * nload;
+    for (int i = 0; i < nload; ++i)
+      for (int j = 0; j < nload; ++j) {
+        double e = 0;
+        for (int a = 0; a < 6; ++a)
+          for (int b = 0; b < 6; ++b)
+            e += E[(size_t)i * 6 + a] * c->cmean_ms[ms][a * 6 + b] * E[(size_t)j * 6 + b];
+        H[i * nload + j] = e + (-bu[i * nload + j] - bu[j * nload + i] + uk[i * nload + j]) / vol;
+      }
+    if (st) {
+      fh_stats s{};
+      s.nload = nload;
+      s.dof = F;
+      for (int j = 0; j < nload; ++j) {
+        const fh::PcgState& p = hs[(size_t)ms * nload + j];
+        s.iterations[j] = p.iter;
+        s.status[j] = status_code(p.status);
+        s.rel_res[j] = p.last;
+        s.outer[j] = outer.empty() ? 0 : outer[(size_t)ms * nload + j];
+      }
+      s.setup_ms = setup_ms;
+      s.solve_ms = solve_ms;
+      st[sid] = s;
+    }
+  }
+  if (rep && gi < FH_MAX_GROUPS) {
+    for (int k = 0; k < 3; ++k) rep->n[gi][k] = (&g0.nx)[k];
+    rep->nsys[gi] = nms;
+    rep->kz[gi] = c->g.kz;
+    rep->zb[gi] = c->g.zb;
+    rep->kyb[gi] = c->g.kyb;
+    rep->tune_ms[gi] = tune_ms;
+    rep->setup_ms[gi] = setup_ms;
+    rep->solve_ms[gi] = solve_ms;
+  }
+  for (const fh::PcgState& p : hs)
+    if (status_code(p.status) < 0) return fail(parent, FH_ENOTSPD, "PCG breakdown in a batch");
+  for (const fh::PcgState& p : hs)
+    if (status_code(p.status) > 0) return FH_NOT_CONVERGED;
+  return FH_OK;
+}
+
+}  // namespace
+
+extern "C" int fh_solve_batch(fh_ctx* c, int nsys, const fh_system* sys, int nload,
+                              const double* E, const fh_opts* opt, double* chom, fh_stats* st,
+                              fh_batch_report* rep) {
+  if (!c || nsys < 1 || !sys || nload < 1 || nload > 8 || !E || !chom) return FH_EINVAL;
+  hipSetDevice(c->device);
+  fh_opts o{1e-10, 10000, FH_FP64, 0, 0, 0.0};
+  if (opt) o = *opt;
+  if (!(o.eta > 0.0) || o.itmax < 1) return fail(c, FH_EINVAL, "bad eta/itmax");
+  // group by grid size, keeping first-appearance order
+  std::vector<std::array<int, 3>> sizes;
+  std::vector<std::vector<int>> groups;
+  for (int i = 0; i < nsys; ++i) {
+    const fh_system& s = sys[i];
+    if (!s.phase_dev || !s.mat || s.nphase < 1 || s.nphase > 16)
+      return fail(c, FH_EINVAL, "bad system " + std::to_string(i));
+    std::array<int, 3> key{s.n[0], s.n[1], s.n[2]};
+    auto it = std::find(sizes.begin(), sizes.end(), key);
+    if (it == sizes.end()) {
+      sizes.push_back(key);
+      groups.push_back({i});
+    } else {
+      groups[it - sizes.begin()].push_back(i);
+    }
+  }
+  if ((int)groups.size() > FH_MAX_GROUPS) return fail(c, FH_EINVAL, "too many grid sizes");
+  if (rep) *rep = fh_batch_report{};
+  if (rep) rep->ngroups = (int)groups.size();
+  if (c->stream) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  } else {
+    HIPCHK(c, hipDeviceSynchronize());
+  }
+  int worst = FH_OK;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const int rc = batch_group(c, groups[gi], sys, nload, E, o, chom, st, rep, (int)gi);
+    if (rc < 0) return rc;
+    if (rc > 0) worst = rc;
+  }
+  return worst;
+}
+
 // ================================================================ C-ABI
 extern "C" {
 
@@ -991,6 +1370,8 @@ void fh_destroy(fh_ctx* c) {
   hipFree(c->twz);
   if (c->host_pinned) hipHostFree(c->host_pinned);
   for (hipEvent_t e : c->kt.ev) hipEventDestroy(e);
+  hipFree(c->phase_pack);
+  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
 }
 
@@ -1028,6 +1409,7 @@ int fh_set_grid(fh_ctx* c, int dim, const int n[3], const double l[3], int probl
   c->g.nxh = nn[0] / 2 + 1;
   c->g.N = (long long)nn[0] * nn[1] * nn[2];
   c->g.nphase_max = 1;
+  c->g.G = 1 << 30;
   for (int k = 0; k < 3; ++k) {
     c->l[k] = (l && k < dim) ? l[k] : 1.0;
     c->g.h[k] = c->l[k] / nn[k];
@@ -1205,8 +1587,8 @@ int fh_solve(fh_ctx* c, const fh_opts* opt, fh_stats* st) {
   std::vector<fh::PcgState> hs;
   std::vector<int> outer;
   if (o.precision == FH_FP32_REFINED) {
-    const double eta_in = o.eta_inner > 0.0 ? o.eta_inner : 1e-4;
-    rc = pcg_refined(c, c->nload, o.eta, eta_in, o.itmax, o.poll > 0 ? o.poll : 8, hs, outer);
+    rc = pcg_refined(c, c->nload, o.eta, default_eta_inner(o), o.itmax, o.poll > 0 ? o.poll : 8,
+                     hs, outer);
   } else {
     rc = pcg64(c, c->nload, o.eta, o.itmax, poll, hs);
   }

@@ -298,6 +298,7 @@ __global__ void __launch_bounds__(kThreads) k_zpass(Grid g, AxisPlan pz, const c
   cplx<T>* a = tw + nz;
   load_twiddles(tw, twz, nz);
   const int ky0 = blockIdx.x * kyb, kx = blockIdx.y;
+  if (kplus) kplus += (ld / g.G) * g.kplus_stride;
   const long long cstride = (long long)nxh * ny * nz;
   const long long base = (long long)ld * sstride + (long long)kx * ny * nz;
   const int per = kyb * nz;
@@ -559,7 +560,8 @@ hipError_t launch_xfwd(const Grid& g, const AxisPlan& px, const cplx<double>* tw
 }
 
 static int ypass_zb(const Grid& g) {
-  int zb = kMaxPts / g.ny;
+  int zb = g.zb > 0 ? g.zb : kMaxPts / g.ny;
+  if (zb * g.ny > kMaxPts) zb = kMaxPts / g.ny;
   if (zb > 16) zb = 16;
   if (zb < 1) zb = 1;
   return zb;
@@ -585,7 +587,8 @@ hipError_t launch_yfwd(const Grid& g, const AxisPlan& py, const cplx<double>* tw
 
 template <typename T>
 static int zpass_kyb(const Grid& g) {
-  int kyb = kMaxPts / (g.nd * g.nz);
+  int kyb = g.kyb > 0 ? g.kyb : kMaxPts / (g.nd * g.nz);
+  if (kyb * g.nd * g.nz > kMaxPts) kyb = kMaxPts / (g.nd * g.nz);
   if (kyb > 16) kyb = 16;
   if (kyb < 1) kyb = 1;
   if (kyb > g.ny) kyb = g.ny;

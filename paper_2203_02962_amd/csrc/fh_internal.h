@@ -49,6 +49,15 @@ struct Grid {
   long long N;         // nx*ny*nz
   double h[3];         // grid spacing
   int nphase_max;      // number of material tables the operator may index
+  // Batched solves: load index ld belongs to microstructure ld / G, whose
+  // phase grid, material table and K^+ sit at these strides (G large and
+  // strides 0 for a single microstructure).
+  int G;
+  long long phase_stride, kplus_stride;
+  int lm_stride;
+  // launch shapes (0 = default): operator z-chunk, y-pass lines per block,
+  // z-pass ky lines per block -- set by the autotuner for batched solves
+  int kz, zb, kyb;
 };
 
 // FFT plan for one axis length: radix of stage i (applied first to last) in
@@ -137,6 +146,8 @@ hipError_t launch_finalize_beta(PcgState* st, const double* part, int nb, int nl
 hipError_t launch_dot_partials(const double* a, const double* b, long long n, double* part,
                                int nb, hipStream_t s);
 hipError_t launch_sum_partials(const double* part, int nb, double* out, hipStream_t s);
+hipError_t launch_pair_dots(const double* A, const double* B, long long F, int G, int nms,
+                            int nchunk, double* part, double* out, hipStream_t s);
 hipError_t launch_phase_count(const uint8_t* phase, long long n, int nphase,
                               unsigned long long* counts, int* bad, hipStream_t s);
 template <typename T>

@@ -305,6 +305,9 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
   const int z1 = min(z0 + kz, nz);
   const T* __restrict__ ub = u + (long long)ld * ustride;
   T* __restrict__ qb = q + (long long)ld * qstride;
+  const int ms = ld / g.G;
+  phase += ms * g.phase_stride;
+  lm += ms * g.lm_stride;
   const int tid = threadIdx.x;
   const bool is_elem = tid < NE;
   const int ei = tid % EX, ej = tid / EX;
@@ -460,7 +463,7 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
 
 constexpr int kHexTX = 32, kHexTY = 8;
 
-static int hex_kz(const Grid& g) { return g.nz >= 64 ? 16 : 8; }
+static int hex_kz(const Grid& g) { return g.kz > 0 ? g.kz : (g.nz >= 64 ? 16 : 8); }
 
 int kop_nblocks(const Grid& g, bool hex_elastic) {
   if (hex_elastic) {

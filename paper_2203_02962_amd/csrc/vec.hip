@@ -154,6 +154,50 @@ hipError_t launch_field_sum(const double* x, long long n, double* part, int nb, 
   return hipGetLastError();
 }
 
+// All load-pair products within every microstructure of a batch:
+// out[ms][i][j] = sum_k A[ms*G+i][k] * B[ms*G+j][k], G <= 8.  Each block
+// reads its chunk of the 2G fields once; chunks are summed in a fixed order
+// by k_pair_dots_sum.
+constexpr int kPairMax = 8;
+__global__ void k_pair_dots(const double* A, const double* B, long long F, int G, int nchunk,
+                            double* part) {
+  __shared__ double sh[256];
+  const int ms = blockIdx.y, chunk = blockIdx.x;
+  const long long len = (F + nchunk - 1) / nchunk;
+  const long long k0 = chunk * len, k1 = k0 + len < F ? k0 + len : F;
+  double acc[kPairMax * kPairMax];
+  for (int t = 0; t < G * G; ++t) acc[t] = 0.0;
+  for (long long k = k0 + threadIdx.x; k < k1; k += 256) {
+    double a[kPairMax], b[kPairMax];
+    for (int i = 0; i < G; ++i) {
+      a[i] = A[((long long)ms * G + i) * F + k];
+      b[i] = B[((long long)ms * G + i) * F + k];
+    }
+    for (int i = 0; i < G; ++i)
+      for (int j = 0; j < G; ++j) acc[i * G + j] += a[i] * b[j];
+  }
+  for (int t = 0; t < G * G; ++t) {
+    const double v = block_sum_fixed(acc[t], sh);
+    if (threadIdx.x == 0) part[((long long)ms * nchunk + chunk) * G * G + t] = v;
+    __syncthreads();
+  }
+}
+__global__ void k_pair_dots_sum(const double* part, int nchunk, int GG, double* out) {
+  const int ms = blockIdx.x;
+  for (int t = threadIdx.x; t < GG; t += blockDim.x) {
+    double v = 0.0;
+    for (int c = 0; c < nchunk; ++c) v += part[((long long)ms * nchunk + c) * GG + t];
+    out[(long long)ms * GG + t] = v;
+  }
+}
+hipError_t launch_pair_dots(const double* A, const double* B, long long F, int G, int nms,
+                            int nchunk, double* part, double* out, hipStream_t s) {
+  if (G > kPairMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pair_dots, dim3(nchunk, nms), dim3(256), 0, s, A, B, F, G, nchunk, part);
+  hipLaunchKernelGGL(k_pair_dots_sum, dim3(nms), dim3(64), 0, s, part, nchunk, G * G, out);
+  return hipGetLastError();
+}
+
 // Phase histogram (integer counts, order independent) and id check.
 __global__ void k_phase_count(const uint8_t* phase, long long n, int nphase,
                               unsigned long long* counts, int* bad) {

@@ -34,6 +34,7 @@ EXPORTED = [
     "fh_workspace_size", "fh_bind_workspace", "fh_solve", "fh_get_fluctuation",
     "fh_get_homogenized", "fh_get_reference", "fh_get_history", "fh_apply_operator",
     "fh_apply_preconditioner", "fh_compute_rhs", "fh_get_symbol", "fh_solve_rhs",
+    "fh_solve_batch",
 ]
 
 
@@ -60,6 +61,29 @@ class fh_stats(ctypes.Structure):
                     setup_ms=self.setup_ms, solve_ms=self.solve_ms, chom_ms=self.chom_ms,
                     dof=self.dof, kernel_ms=list(self.kernel_ms),
                     kernel_launches=list(self.kernel_launches))
+
+
+class fh_system(ctypes.Structure):
+    _fields_ = [("phase_dev", ctypes.c_void_p), ("n", ctypes.c_int * 3),
+                ("nphase", ctypes.c_int), ("mat", ctypes.POINTER(ctypes.c_double))]
+
+
+FH_MAX_GROUPS = 16
+
+
+class fh_batch_report(ctypes.Structure):
+    _fields_ = [("ngroups", ctypes.c_int), ("n", (ctypes.c_int * 3) * FH_MAX_GROUPS),
+                ("nsys", ctypes.c_int * FH_MAX_GROUPS), ("kz", ctypes.c_int * FH_MAX_GROUPS),
+                ("zb", ctypes.c_int * FH_MAX_GROUPS), ("kyb", ctypes.c_int * FH_MAX_GROUPS),
+                ("tune_ms", ctypes.c_double * FH_MAX_GROUPS),
+                ("setup_ms", ctypes.c_double * FH_MAX_GROUPS),
+                ("solve_ms", ctypes.c_double * FH_MAX_GROUPS)]
+
+    def as_dict(self):
+        g = self.ngroups
+        return [dict(n=list(self.n[i]), nsys=self.nsys[i], kz=self.kz[i], zb=self.zb[i],
+                     kyb=self.kyb[i], tune_ms=self.tune_ms[i], setup_ms=self.setup_ms[i],
+                     solve_ms=self.solve_ms[i]) for i in range(g)]
 
 
 _lib = None
@@ -97,6 +121,9 @@ def load_library(path: str = LIB_PATH):
         "fh_compute_rhs": ([P, ctypes.POINTER(D), P], I),
         "fh_get_symbol": ([P, P], I),
         "fh_solve_rhs": ([P, P, P, ctypes.POINTER(fh_opts), ctypes.POINTER(fh_stats)], I),
+        "fh_solve_batch": ([P, I, ctypes.POINTER(fh_system), I, ctypes.POINTER(D),
+                            ctypes.POINTER(fh_opts), ctypes.POINTER(D), ctypes.POINTER(fh_stats),
+                            ctypes.POINTER(fh_batch_report)], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -265,6 +292,29 @@ class Context:
                                                ctypes.byref(o), ctypes.byref(st)),
                          allow_warning=True)
         return rc, st.as_dict()
+
+
+    def solve_batch(self, systems, E, eta=1e-6, itmax=10000, precision=FH_FP32_REFINED,
+                    poll=0, eta_inner=0.0):
+        """systems: list of (phase_dev uint8 tensor, n (3,), mat (nphase, 6, 6)).
+        Returns (rc, chom (nsys, nload, nload), [stats dicts], [group reports])."""
+        E = np.ascontiguousarray(np.atleast_2d(E), dtype=np.float64)
+        nload = E.shape[0]
+        mats = [np.ascontiguousarray(m, dtype=np.float64) for _, _, m in systems]
+        arr = (fh_system * len(systems))()
+        for i, ((ph, n, _), m) in enumerate(zip(systems, mats)):
+            arr[i].phase_dev = _tptr(ph)
+            arr[i].n = (ctypes.c_int * 3)(*[int(v) for v in n])
+            arr[i].nphase = int(m.shape[0])
+            arr[i].mat = _dptr(m)
+        chom = np.zeros((len(systems), nload, nload))
+        sts = (fh_stats * len(systems))()
+        rep = fh_batch_report()
+        o = self.opts(eta, itmax, precision, poll, eta_inner)
+        rc = self._check(self.lib.fh_solve_batch(self.ptr, len(systems), arr, nload, _dptr(E),
+                                                 ctypes.byref(o), _dptr_out(chom), sts,
+                                                 ctypes.byref(rep)), allow_warning=True)
+        return rc, chom, [x.as_dict() for x in sts], rep.as_dict()
 
 
 def _dptr_out(arr):

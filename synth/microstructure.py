@@ -203,12 +203,16 @@ def workload(name: str, seed: int = 0, n: int | None = None) -> dict:
 
 
 def batch_workload(count: int = 96, seed0: int = 1000,
-                   sizes=(32, 48, 64, 96), fixed_n: int | None = None):
+                   sizes=(32, 48, 64, 96), fixed_n: int | None = None,
+                   max_attempts: int = 20000):
     """Batched elasticity microstructures.
 
     For microstructure i (seed seed0 + i): n ~ U{sizes} (or fixed_n),
     voxel fraction ~ U[0.1, 0.4], stiffness contrast ~ U[10, 1000] (linear
     uniform), nu = 0.3, spheres with radii U[6,12] * n/128 (floor 2).
+    Random sequential addition stops after `max_attempts` rejected or
+    accepted draws; the achieved fraction is returned as 'vf' (near the
+    jamming limit it can stay below the drawn target 'vf_target').
     """
     out = []
     for i in range(count):
@@ -218,7 +222,7 @@ def batch_workload(count: int = 96, seed0: int = 1000,
         contrast = float(rng.uniform(10.0, 1000.0))
         s = n / 128.0
         rr = (max(2.0, 6.0 * s), max(2.0, 12.0 * s))
-        phase, got, _ = spheres(n, rr, vf, seed0 + i + 7919)
+        phase, got, _ = spheres(n, rr, vf, seed0 + i + 7919, max_attempts)
         mat = np.stack([isotropic_mandel(1.0, 0.3),
                         isotropic_mandel(contrast, 0.3)])
         out.append(dict(name="elastic3d_spheres_batch", dim=3, n=(n, n, n),

@@ -327,3 +327,45 @@ def test_fp32_refined_solve_reaches_fp64_accuracy(fh, name, make):
     # plain FP64 to the same tolerance for reference: same answer
     rc2, st2 = ctx.solve(eta=1e-10)
     assert _rel(ctx.get_homogenized(), H) < 1e-10
+
+
+def _batch_systems(specs):
+    """specs: list of (n, seed, contrast); isotropic two-phase spheres."""
+    out = []
+    for n, seed, contrast in specs:
+        n3 = n if isinstance(n, tuple) else (n, n, n)
+        rng = np.random.default_rng(seed)
+        if n3[0] == n3[1] == n3[2]:
+            ph, _, _ = spheres(n3[0], (1.5, 3.0), 0.25, seed)
+        else:
+            ph = (rng.random(n3[::-1]) < 0.3).astype(np.uint8)
+        mat = np.stack([isotropic_mandel(1.0, 0.3), isotropic_mandel(contrast, 0.25)])
+        out.append((ph, n3, mat))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_batch_matches_single_solves_and_oracle(fh, precision):
+    """Systems of three grid sizes (one with radix-3 FFTs, one non-cubic)
+    solved in one batch call: every system's C_hom equals its own single
+    solve (catches cross-system indexing or races in the batched launches
+    and the graph replays) and, for one system, the oracle."""
+    say("batch", precision)
+    specs = [(16, 1, 10.0), (24, 2, 100.0), (16, 3, 500.0), ((12, 18, 24), 4, 50.0),
+             (24, 5, 30.0), (16, 6, 1000.0)]
+    sysl = _batch_systems(specs)
+    from paper_2203_02962_amd.runner import setup_context
+    ctx = fh.Context(0)
+    devs = [(torch.from_numpy(ph).cuda(), n, m) for ph, n, m in sysl]
+    prec = fh.FH_FP64 if precision == "fp64" else fh.FH_FP32_REFINED
+    rc, H, sts, rep = ctx.solve_batch(devs, np.eye(6), eta=1e-10, precision=prec, eta_inner=1e-4)
+    assert rc == 0, sts
+    assert len(rep) == 3 and sorted(r["nsys"] for r in rep) == [1, 2, 3]
+    for i, (ph, n, m) in enumerate(sysl):
+        wl = dict(dim=3, n=n, problem="elastic", element="hex8", phase=ph, mat=m, loads=np.eye(6))
+        c1 = setup_context(wl)
+        c1.solve(eta=1e-10)
+        assert _rel(H[i], c1.get_homogenized()) < 1e-10, i
+    ph, n, m = sysl[1]
+    Ho, _, _ = oracle.homogenize(Problem(n, "elastic", "hex8", phase=ph, mat=m), np.eye(6), 1e-10)
+    assert _rel(H[1], Ho) < 1e-10
