@@ -97,8 +97,8 @@ typedef struct fh_opts {
   int precision;    /* FH_FP64 or FH_FP32_REFINED                                 */
   int poll;         /* iterations between host convergence polls (0 = default)   */
   int flags;        /* FH_FLAG_* bits                                             */
-  double eta_inner; /* inner FP32 tolerance for FH_FP32_REFINED (0 = eta/2 when
-                       eta >= 1e-6, else 1e-4)                                    */
+  double eta_inner; /* inner FP32 tolerance for FH_FP32_REFINED (0 = sqrt(eta)
+                       when eta >= 1e-6, else 1e-4)                               */
 } fh_opts;
 
 typedef struct fh_stats {

@@ -827,12 +827,12 @@ int pcg64(fh_ctx* c, int nload, double eta, int itmax, int poll, std::vector<fh:
   return pcg_run<double>(c, nload, bf, eta, itmax, poll, std::vector<int>(nload, 1), out);
 }
 
-// Inner FP32 tolerance when the caller gives none: a loose outer target is
-// met in about one sweep (eta/2); tight targets use 1e-4 per sweep, well
-// above the level where FP32 PCG stagnates.
+// Inner FP32 tolerance when the caller gives none.  FP32 PCG stagnates near
+// 1e-6 relative, so each sweep asks for at most 1e-3..1e-4: sqrt(eta) for
+// loose outer targets (two sweeps), 1e-4 for tight ones.
 double default_eta_inner(const fh_opts& o) {
   if (o.eta_inner > 0.0) return o.eta_inner;
-  return o.eta >= 1e-6 ? 0.5 * o.eta : 1e-4;
+  return o.eta >= 1e-6 ? std::sqrt(o.eta) : 1e-4;
 }
 
 // FP32-in-FP64 iterative refinement (FH_FP32_REFINED).  Outer loop in FP64:
