@@ -18,7 +18,11 @@ slow, independent algorithms:
   * Alg. 1 with a linear material (one Newton step from u0 = 0) and the
     relative Kref^-1-norm stopping rule of Sec. 6 (pcg.py);
   * the homogenized tensor as the energy (bilinear) form over quadrature
-    points, and the stress average as a diagnostic (homog.py).
+    points, and the stress average as a diagnostic (homog.py);
+  * PCG from an initial guess u0 (the starting point of Alg. 1) with the
+    warm-start judge (pcg.py), and the learned warm start's network, loss
+    and Adam step in FP64, optionally rounding stored tensors to BF16 as
+    the GPU stores them (convnet.py).
 
 Every function cites the passage it follows.  See pins in
 tests/test_oracle_pins.py for what fixes each part independently.

@@ -43,16 +43,20 @@ def zero_mean(x: np.ndarray, nd: int) -> np.ndarray:
 
 
 def pcg(apply_K, apply_M, b: np.ndarray, eta: float, itmax: int = 10000,
-        x0: np.ndarray | None = None, nd: int = 1) -> PCGResult:
+        x0: np.ndarray | None = None, nd: int = 1,
+        rho_ref: float | None = None) -> PCGResult:
+    """rho_ref: the squared norm the stopping test is relative to (default
+    r0.z0; a warm start passes b.M b so that the test keeps measuring the
+    residual against the zero-start one)."""
     b = np.asarray(b, dtype=float)
     x = np.zeros_like(b) if x0 is None else zero_mean(x0, nd)
     r = b - apply_K(x) if x0 is not None else b.copy()
     z = apply_M(r)
     p = z.copy()
     rho = float(np.dot(r, z))
-    rho0 = rho
+    rho0 = rho if rho_ref is None else float(rho_ref)
     res = PCGResult(x, 0, 0, rho0, rho)
-    if rho0 == 0.0:
+    if rho == 0.0 or (rho_ref is not None and rho <= eta * eta * rho0):
         return res
     for k in range(1, itmax + 1):
         q = apply_K(p)
@@ -78,6 +82,20 @@ def pcg(apply_K, apply_M, b: np.ndarray, eta: float, itmax: int = 10000,
         p = z + beta * p
     res.status = 1
     return res
+
+
+def judged_guess(apply_K, apply_M, b: np.ndarray, x0: np.ndarray, nd: int):
+    """Warm-start judge: keep the zero-mean guess only if its residual has a
+    smaller M-norm than the zero start's (r.M r < b.M b).  Returns
+    (accepted, guess or zeros, b.M b, r0.M r0)."""
+    b = np.asarray(b, dtype=float)
+    x = zero_mean(x0, nd)
+    rb = float(np.dot(b, apply_M(b)))
+    r = b - apply_K(x)
+    rx = float(np.dot(r, apply_M(r)))
+    if rx < rb:
+        return True, x, rb, rx
+    return False, np.zeros_like(b), rb, rx
 
 
 def lanczos_ritz_values(alphas, betas) -> np.ndarray:

@@ -108,3 +108,49 @@ def test_catches_zero_frequency_inverted(monkeypatch):
     monkeypatch.setattr(opre, "pseudo_inverse_blocks", bad)
     with np.errstate(all="ignore"):
         assert _caught()
+
+
+# ------------------------------------------------------------ warm-start net
+import torch  # noqa: E402
+
+import oracle.convnet as ocn  # noqa: E402
+from tests import test_oracle_convnet as npins  # noqa: E402
+
+
+def _net_pins_fail():
+    checks = [npins.test_conv_matches_library_circular_conv3d,
+              npins.test_manual_backward_matches_autograd,
+              npins.test_loss_closed_form_and_gradient,
+              npins.test_gradient_finite_differences]
+    return any(_fails(fn) for fn in checks)
+
+
+def _input_grad_wrong_shift(dy, W):
+    dx = None
+    for t, (dz, dyy, ddx) in enumerate(ocn.TAPS):
+        ds = torch.roll(dy, shifts=(-dz, -dyy, -ddx), dims=(2, 3, 4))
+        term = torch.einsum("oc,bozyx->bczyx", W[t], ds)
+        dx = term if dx is None else dx + term
+    return dx
+
+
+def _conv_taps_transposed(x, W, b):
+    y = b.view(1, -1, 1, 1, 1).expand(x.shape[0], -1, *x.shape[2:]).clone()
+    for t, (dz, dy, dx) in enumerate(ocn.TAPS):
+        xs = torch.roll(x, shifts=(-dx, -dy, -dz), dims=(2, 3, 4))
+        y += torch.einsum("oc,bczyx->bozyx", W[t], xs)
+    return y
+
+
+@pytest.mark.parametrize("name,mutant", [
+    ("conv_input_grad", _input_grad_wrong_shift),
+    ("conv", _conv_taps_transposed),
+    ("loss_grad", lambda O, T: 0.5 * (lambda e: sum(
+        2.0 * e - torch.roll(e, 1, d) - torch.roll(e, -1, d) for d in (2, 3, 4)))(O - T)
+        * (2.0 / (3.0 * O.numel()))),
+    ("up_adjoint", lambda y: ocn.pool(y)),
+    ("leaky_grad_from_output", lambda y: torch.ones_like(y)),
+])
+def test_net_pins_catch_planted_mistake(monkeypatch, name, mutant):
+    monkeypatch.setattr(ocn, name, mutant)
+    assert _net_pins_fail()

@@ -456,3 +456,41 @@ def test_operator_rows_match_assembled_rows():
         full = (K @ u).reshape(prob.ndof_node, prob.N)[:, nodes]
         from oracle.assembly import operator_rows
         assert np.abs(operator_rows(prob, u, nodes) - full).max() < 1e-13 * np.abs(full).max()
+
+
+# ------------------------------------------------ initial guess and judge
+
+def test_warm_started_pcg_reaches_dense_solution_and_judge():
+    """A guess u0 (the initial displacement of the Newton scheme of Alg. 1):
+    PCG from it with the test relative to b.M b reaches the minimum-norm
+    dense solution; the exact solution as guess needs no iteration; the
+    judge accepts a good guess and rejects a bad one."""
+    from oracle.pcg import judged_guess
+    rng = np.random.default_rng(41)
+    n = (4, 4, 4)
+    phase = rng.integers(0, 2, size=n[::-1])
+    C0 = random_spd(6, rng)
+    prob = two_phase(n, "elastic", "hex8", phase, C0, 20.0 * random_spd(6, rng))
+    K = assemble_stiffness(prob)
+    M = Preconditioner(prob, oracle.mean_material(prob))
+    b = rhs(prob, np.eye(6)[3])
+    x_ls = np.linalg.lstsq(K.toarray(), b, rcond=1e-12)[0]
+    AK = lambda v: K @ v  # noqa: E731
+    nd = prob.ndof_node
+    # exact solution shifted by a constant: accepted, zero iterations
+    ok, x0, rb, rx = judged_guess(AK, M.apply, b, x_ls + 3.0, nd)
+    assert ok and rx < 1e-20 * rb
+    res = pcg(AK, M.apply, b, 1e-10, x0=x0, nd=nd, rho_ref=rb)
+    assert res.iterations == 0 and np.abs(res.x - x_ls).max() < 1e-12 * np.abs(x_ls).max()
+    # perturbed solution: accepted, converges to the same point in fewer steps
+    ok, x0, rb, rx = judged_guess(AK, M.apply, b, x_ls + 0.01 * np.abs(x_ls).max() *
+                                  rng.standard_normal(b.size), nd)
+    assert ok and rx < rb
+    warm = pcg(AK, M.apply, b, 1e-12, x0=x0, nd=nd, rho_ref=rb)
+    cold = pcg(AK, M.apply, b, 1e-12, nd=nd)
+    assert warm.status == 0 and np.abs(warm.x - x_ls).max() < 1e-9 * np.abs(x_ls).max()
+    assert warm.iterations < cold.iterations
+    assert warm.history[-1] ** 2 * warm.rho0 <= (1e-12) ** 2 * rb * (1 + 1e-12)
+    # a guess far worse than zero is rejected
+    ok, x0, rb, rx = judged_guess(AK, M.apply, b, 1e3 * rng.standard_normal(b.size), nd)
+    assert not ok and rx >= rb and not x0.any()
