@@ -78,6 +78,9 @@ extern "C" {
 /* fh_opts.flags: rebuild the reference material, the Alg. 2 symbol and the
  * right-hand sides even if the inputs have not changed since the last solve */
 #define FH_FLAG_REBUILD 2
+/* fh_opts.flags: start every load case from the learned warm start of the
+ * network attached with fh_set_warm_start instead of from zero (see there) */
+#define FH_FLAG_WARM_START 4
 
 /* kernel classes of fh_stats.kernel_ms / kernel_launches                  */
 #define FH_K_OPERATOR 0   /* q = K p (+ p.q partials)                       */
@@ -90,6 +93,10 @@ extern "C" {
 #define FH_K_NCLASS 8
 
 typedef struct fh_ctx fh_ctx;
+#ifndef FH_NET_TYPEDEF
+#define FH_NET_TYPEDEF
+typedef struct fh_net fh_net; /* learned warm start, fh_net.h */
+#endif
 
 typedef struct fh_opts {
   double eta;       /* relative Kref^-1-norm tolerance (Sec. 6); e.g. 1e-10       */
@@ -99,6 +106,12 @@ typedef struct fh_opts {
   int flags;        /* FH_FLAG_* bits                                             */
   double eta_inner; /* inner FP32 tolerance for FH_FP32_REFINED (0 = sqrt(eta)
                        when eta >= 1e-6, else 1e-4)                               */
+  const double *guess_dev; /* initial fluctuation u_(0) of Alg. 1 for every load
+                       case (device, nload x nd x N; NULL = zero).  It is shifted
+                       to zero mean per component and judged: a load case keeps
+                       it only if r0.M r0 < b.M b (r0 = b - K u_(0)), else it
+                       starts from zero.  The stopping test stays relative to
+                       b.M b, so results are comparable with zero starts.       */
 } fh_opts;
 
 typedef struct fh_stats {
@@ -113,6 +126,9 @@ typedef struct fh_stats {
   long long dof;                /* nd * N                                         */
   double kernel_ms[FH_K_NCLASS];      /* summed event-timed durations       */
   long long kernel_launches[FH_K_NCLASS];
+  int guess_used[FH_MAX_LOADS];   /* 1 if the initial guess was kept          */
+  double guess_res[FH_MAX_LOADS]; /* sqrt(r0.M r0 / b.M b) of the guess       */
+  double guess_ms;                /* warm-start inference + judge             */
 } fh_stats;
 
 /* Context on HIP device `device`.  Returns FH_EDEVICE if it cannot be used. */
@@ -161,6 +177,15 @@ int fh_bind_workspace(fh_ctx *ctx, void *dev, size_t bytes);
  * FH_ENOTSPD on PCG breakdown (p.q <= 0) or a non-SPD Cref block.         */
 int fh_solve(fh_ctx *ctx, const fh_opts *opt, fh_stats *st);
 
+/* Learned warm start (fh_net.h): with FH_FLAG_WARM_START, fh_solve runs the
+ * network on the phase field and takes u_(0) = (l/n) sum_j E_j O_j, shifted
+ * to zero mean, as initial guess of every load case (judged as guess_dev).
+ * Needs 3D elasticity with FH_HEX8 on a cubic n^3 grid equal to the
+ * network's, cubic cell, two isotropic phases (0 = matrix, 1 = inclusion);
+ * gamma = log10(C1[0][0] / C0[0][0]) / 3.  The network must outlive its use;
+ * NULL detaches.                                                            */
+int fh_set_warm_start(fh_ctx *ctx, fh_net *net);
+
 /* Results of the last fh_solve: fluctuation u_j (device, nd*N doubles,
  * zero-mean representative) and the homogenized tensor (host, nload x nload,
  * the full m x m tensor when the loads are the m unit vectors).            */
@@ -201,6 +226,8 @@ typedef struct fh_system {
   int n[3];                 /* 3D grid, sizes as for fh_set_grid             */
   int nphase;               /* 1..16                                         */
   const double *mat;        /* nphase x 6 x 6 Mandel stiffness tables (host)  */
+  double *u_dev;            /* optional output (device, nload x 3 x N doubles):
+                               the fluctuation fields of this system           */
 } fh_system;
 
 #define FH_MAX_GROUPS 16

@@ -267,8 +267,13 @@ def gradient(params, phase, gamma, target, emulate: bool = False):
     return float(loss(O, T)), backward(cache, loss_grad(O, T), emulate)
 
 
-def adam(params, grad, m, v, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
-    """One Adam step (t counts from 1); returns new (params, m, v)."""
+def adam(params, grad, m, v, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, clip=0.0):
+    """One Adam step (t counts from 1); returns new (params, m, v).  With
+    clip > 0 the gradient is first scaled to global L2 norm <= clip."""
+    if clip > 0.0:
+        nrm = float(np.linalg.norm(grad))
+        if nrm > clip:
+            grad = grad * (clip / nrm)
     m = beta1 * m + (1.0 - beta1) * grad
     v = beta2 * v + (1.0 - beta2) * grad * grad
     mhat = m / (1.0 - beta1 ** t)

@@ -121,6 +121,7 @@ struct fh_ctx {
   std::vector<double> cmean;
   std::vector<std::vector<double>> history;
   fh_stats last{};
+  fh_net* net = nullptr;  // learned warm start (fh_set_warm_start)
 };
 
 namespace {
@@ -720,9 +721,13 @@ int apply_KT(fh_ctx* c, const float* u, float* q, int nload, long long F,
   return apply_K32(c, u, q, nload, F, st, pq);
 }
 
+// With zero_x false, x keeps its content (an initial guess whose residual is
+// already in r) and the PCG updates add to it.  eta2v (optional) gives each
+// load case its own squared tolerance relative to its initial r.z.
 template <typename T>
 int pcg_run(fh_ctx* c, int nload, const PcgBufs<T>& bf, double eta, int itmax, int poll,
-            const std::vector<int>& active, std::vector<fh::PcgState>& out) {
+            const std::vector<int>& active, std::vector<fh::PcgState>& out,
+            bool zero_x = true, const std::vector<double>* eta2v = nullptr) {
   const fh::Grid& g = c->g;
   const long long F = (long long)g.nd * g.N;
   const long long S = (long long)g.nd * g.nxh * g.ny * g.nz;
@@ -731,12 +736,12 @@ int pcg_run(fh_ctx* c, int nload, const PcgBufs<T>& bf, double eta, int itmax, i
   for (int j = 0; j < nload; ++j) {
     hs[j] = fh::PcgState{};
     hs[j].status = active[j] ? fh::ST_ACTIVE : fh::ST_CONVERGED;
-    hs[j].eta2 = eta * eta;
+    hs[j].eta2 = eta2v ? (*eta2v)[j] : eta * eta;
     hs[j].itmax = itmax;
   }
   HIPCHK(c, hipMemcpyAsync(L.st, hs.data(), sizeof(fh::PcgState) * nload, hipMemcpyHostToDevice,
                            c->stream));
-  HIPCHK(c, fh::launch_fill<T>(bf.x, T(0), F * nload, c->stream));
+  if (zero_x) HIPCHK(c, fh::launch_fill<T>(bf.x, T(0), F * nload, c->stream));
   // z0 = M r0, p0 = z0, rho0 = r0.z0
   int nbz = 0;
   HIPCHK(c, fh::launch_xfwd<T>(g, c->px, c->twx, fh::XF_PLAIN, bf.r, F, nullptr, 0, bf.A, S,
@@ -827,6 +832,36 @@ int pcg64(fh_ctx* c, int nload, double eta, int itmax, int poll, std::vector<fh:
   return pcg_run<double>(c, nload, bf, eta, itmax, poll, std::vector<int>(nload, 1), out);
 }
 
+// Plain FP64 solve from the judged initial guess in L.x, whose residual is in
+// L.r: rr[j] = r0.M r0 of the starting point, rb[j] = b.M b.  The stopping
+// test stays relative to b.M b (rho <= eta^2 rb); load cases that already
+// meet it do no iteration.  Reported residuals are relative to b.
+int pcg64_warm(fh_ctx* c, int nload, double eta, int itmax, int poll,
+               const std::vector<double>& rb, const std::vector<double>& rr,
+               std::vector<fh::PcgState>& out) {
+  fh_ctx::Layout& L = c->L;
+  std::vector<int> active(nload, 1);
+  std::vector<double> eta2(nload, eta * eta);
+  for (int j = 0; j < nload; ++j) {
+    if (!(rb[j] > 0.0) || rr[j] <= eta * eta * rb[j]) active[j] = 0;
+    else if (rr[j] != rb[j]) eta2[j] = eta * eta * rb[j] / rr[j];
+  }
+  PcgBufs<double> bf{L.x, L.r, L.p, L.q, L.A, L.B, L.kplus};
+  int rc = pcg_run<double>(c, nload, bf, eta, itmax, poll, active, out, false, &eta2);
+  if (rc) return rc;
+  for (int j = 0; j < nload; ++j) {
+    const double f = rb[j] > 0.0 ? std::sqrt(std::max(rr[j], 0.0) / rb[j]) : 0.0;
+    if (!active[j]) {
+      out[j] = fh::PcgState{};
+      out[j].status = fh::ST_CONVERGED;
+      out[j].last = f;
+    } else {
+      out[j].last *= f;
+    }
+  }
+  return FH_OK;
+}
+
 // Inner FP32 tolerance when the caller gives none.  FP32 PCG stagnates near
 // 1e-6 relative, so each sweep asks for at most 1e-3..1e-4: sqrt(eta) for
 // loose outer targets (two sweeps), 1e-4 for tight ones.
@@ -841,8 +876,11 @@ double default_eta_inner(const fh_opts& o) {
 // relative to the norm of b), then an inner PCG in FP32 for K d = r to the
 // relative tolerance eta_inner and x += d in FP64.  out[j].iter holds the
 // summed inner iterations, outer[j] the number of sweeps.
+// With rho_ref set, the caller has put an initial guess in L.x and its
+// residual in L.r, and the stopping test is relative to rho_ref (b.M b).
 int pcg_refined(fh_ctx* c, int nload, double eta, double eta_in, int itmax, int poll,
-                std::vector<fh::PcgState>& out, std::vector<int>& outer) {
+                std::vector<fh::PcgState>& out, std::vector<int>& outer,
+                const std::vector<double>* rho_ref = nullptr) {
   const fh::Grid& g = c->g;
   const long long F = (long long)g.nd * g.N;
   fh_ctx::Layout& L = c->L;
@@ -851,8 +889,10 @@ int pcg_refined(fh_ctx* c, int nload, double eta, double eta_in, int itmax, int 
   std::vector<double> last(nload, 1.0);
   outer.assign(nload, 0);
   int* mask_dev = L.mask;
-  HIPCHK(c, fh::launch_fill<double>(L.x, 0.0, F * nload, c->stream));
-  HIPCHK(c, fh::launch_copy(L.r, L.b, F * nload, c->stream));
+  if (!rho_ref) {
+    HIPCHK(c, fh::launch_fill<double>(L.x, 0.0, F * nload, c->stream));
+    HIPCHK(c, fh::launch_copy(L.r, L.b, F * nload, c->stream));
+  }
   const int max_outer = 64;
   for (int sweep = 0; sweep <= max_outer; ++sweep) {
     // Kref^-1-norm of the FP64 residual
@@ -869,7 +909,7 @@ int pcg_refined(fh_ctx* c, int nload, double eta, double eta_in, int itmax, int 
     for (int j = 0; j < nload; ++j) {
       if (!active[j]) continue;
       rho[j] = dots[j];
-      if (sweep == 0) rho0[j] = rho[j];
+      if (sweep == 0) rho0[j] = rho_ref ? (*rho_ref)[j] : rho[j];
       if (!(rho0[j] > 0.0)) {
         active[j] = 0;
         status[j] = rho0[j] == 0.0 ? fh::ST_CONVERGED : fh::ST_BREAKDOWN;
@@ -926,7 +966,8 @@ int pcg_refined(fh_ctx* c, int nload, double eta, double eta_in, int itmax, int 
   return FH_OK;
 }
 
-void record_history(fh_ctx* c, const std::vector<fh::PcgState>& hs, int nload) {
+void record_history(fh_ctx* c, const std::vector<fh::PcgState>& hs, int nload,
+                    const std::vector<double>* scale = nullptr) {
   c->history.assign(nload, {});
   std::vector<double> h((size_t)c->L.hist_len * nload);
   hipMemcpyAsync(h.data(), c->L.hist, h.size() * sizeof(double), hipMemcpyDeviceToHost,
@@ -936,7 +977,66 @@ void record_history(fh_ctx* c, const std::vector<fh::PcgState>& hs, int nload) {
     const int n = std::min(hs[j].iter, c->L.hist_len);
     c->history[j].assign(h.begin() + (size_t)j * c->L.hist_len,
                          h.begin() + (size_t)j * c->L.hist_len + n);
+    if (scale)
+      for (double& v : c->history[j]) v *= (*scale)[j];
   }
+}
+
+// Initial guess for fh_solve (opts.guess_dev or the learned warm start) into
+// L.x, shifted to zero mean per component, and the judge: rb = b.M b, rr =
+// r0.M r0 of the kept starting point (a load case whose guess is not better
+// than zero restarts from zero, rr = rb).  L.r holds the starting residual.
+int prepare_guess(fh_ctx* c, const fh_opts& o, std::vector<double>& rb,
+                  std::vector<double>& rr, std::vector<double>& gres, std::vector<int>& used) {
+  const fh::Grid& g = c->g;
+  const int nl = c->nload;
+  const long long F = (long long)g.nd * g.N;
+  fh_ctx::Layout& L = c->L;
+  if (o.flags & FH_FLAG_WARM_START) {
+    if (!c->net) return fail(c, FH_ESTATE, "warm start requested but no network attached");
+    const int n = g.nx;
+    if (!hex_elastic(c) || g.dim != 3 || g.ny != n || g.nz != n || fh::net_grid(c->net) != n ||
+        c->l[1] != c->l[0] || c->l[2] != c->l[0])
+      return fail(c, FH_EINVAL, "warm start needs 3D hex8 elasticity on the network's cubic grid");
+    if (c->mat_kind != 1 || c->nphase != 2 || !c->iso)
+      return fail(c, FH_EINVAL, "warm start needs two isotropic phases");
+    const double r = c->mat[36] / c->mat[0];
+    if (!(r > 0.0)) return fail(c, FH_EINVAL, "warm start: bad phase stiffness ratio");
+    const float gamma = (float)(std::log10(r) / 3.0);
+    std::string err;
+    const int rc = fh::net_warm_guess(c->net, c->stream, c->phase_dev, gamma, nl,
+                                      c->loads.data(), c->l[0] / n, L.x, F, &err);
+    if (rc) return fail(c, rc, err);
+  } else {
+    HIPCHK(c, hipMemcpyAsync(L.x, o.guess_dev, sizeof(double) * F * nl, hipMemcpyDeviceToDevice,
+                             c->stream));
+  }
+  HIPCHK(c, fh::launch_remove_mean(L.x, nl * g.nd, g.N, L.sysdot_part, 16, c->stream));
+  auto dots = [&](const double* a, const double* b, std::vector<double>& out) -> int {
+    HIPCHK(c, fh::launch_pair_dots(a, b, F, 1, nl, 64, L.sysdot_part, L.sysdot, c->stream));
+    out.assign(nl, 0.0);
+    HIPCHK(c, hipMemcpyAsync(out.data(), L.sysdot, sizeof(double) * nl, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return FH_OK;
+  };
+  int rc = precond_fields(c, L.b, L.q, nl, F);
+  if (rc || (rc = dots(L.b, L.q, rb))) return rc;
+  if ((rc = apply_K(c, false, L.x, L.q, nl, F, nullptr, nullptr))) return rc;
+  HIPCHK(c, fh::launch_residual(L.r, L.b, L.q, F * nl, c->stream));
+  if ((rc = precond_fields(c, L.r, L.q, nl, F)) || (rc = dots(L.r, L.q, rr))) return rc;
+  used.assign(nl, 0);
+  gres.assign(nl, 0.0);
+  for (int j = 0; j < nl; ++j) {
+    gres[j] = rb[j] > 0.0 ? std::sqrt(std::max(rr[j], 0.0) / rb[j]) : 0.0;
+    used[j] = rr[j] < rb[j] ? 1 : 0;
+    if (!used[j]) {
+      HIPCHK(c, fh::launch_fill<double>(L.x + j * F, 0.0, F, c->stream));
+      HIPCHK(c, fh::launch_copy(L.r + j * F, L.b + j * F, F, c->stream));
+      rr[j] = rb[j];
+    }
+  }
+  return FH_OK;
 }
 
 int status_code(int st) {
@@ -1247,6 +1347,12 @@ int batch_group(fh_ctx* parent, const std::vector<int>& idx, const fh_system* sy
   hipFree(dots);
   if (e1 || e2 || e3 || e4) return fail(parent, FH_EDEVICE, "batched C_hom reduction failed");
   const double solve_ms = ms_since(t1);
+  for (int ms = 0; ms < nms; ++ms)
+    if (sys[idx[ms]].u_dev)
+      HIPCHK(parent, hipMemcpyAsync(sys[idx[ms]].u_dev, L.x + (size_t)ms * nload * F,
+                                    sizeof(double) * nload * F, hipMemcpyDeviceToDevice,
+                                    c->stream));
+  HIPCHK(parent, hipStreamSynchronize(c->stream));
   const double vol = c->l[0] * c->l[1] * c->l[2];
   for (int ms = 0; ms < nms; ++ms) {
     const int sid = idx[ms];
@@ -1586,9 +1692,21 @@ int fh_solve(fh_ctx* c, const fh_opts* opt, fh_stats* st) {
   auto t1 = std::chrono::steady_clock::now();
   std::vector<fh::PcgState> hs;
   std::vector<int> outer;
+  const bool warm = (o.flags & FH_FLAG_WARM_START) || o.guess_dev;
+  std::vector<double> rb, rr, gres;
+  std::vector<int> used;
+  double guess_ms = 0.0;
+  if (warm) {
+    if ((rc = ensure_layout(c))) return rc;
+    rc = prepare_guess(c, o, rb, rr, gres, used);
+    if (rc) return rc;
+    guess_ms = ms_since(t1);
+  }
   if (o.precision == FH_FP32_REFINED) {
     rc = pcg_refined(c, c->nload, o.eta, default_eta_inner(o), o.itmax, o.poll > 0 ? o.poll : 8,
-                     hs, outer);
+                     hs, outer, warm ? &rb : nullptr);
+  } else if (warm) {
+    rc = pcg64_warm(c, c->nload, o.eta, o.itmax, poll, rb, rr, hs);
   } else {
     rc = pcg64(c, c->nload, o.eta, o.itmax, poll, hs);
   }
@@ -1636,10 +1754,20 @@ int fh_solve(fh_ctx* c, const fh_opts* opt, fh_stats* st) {
           e + (-bu[(size_t)i * nl + j] - bu[(size_t)j * nl + i] + uKu[(size_t)i * nl + j]) / vol;
     }
   const double chom_ms = ms_since(t2);
+  std::vector<double> hscale;
+  if (warm && o.precision != FH_FP32_REFINED) {
+    hscale.resize(nl);
+    for (int j = 0; j < nl; ++j) hscale[j] = rb[j] > 0.0 ? std::sqrt(rr[j] / rb[j]) : 0.0;
+  }
   if (o.precision == FH_FP32_REFINED) c->history.assign(nl, {});
-  else record_history(c, hs, nl);
+  else record_history(c, hs, nl, warm ? &hscale : nullptr);
   c->solved = true;
   rc = fill_stats(c, hs, nl, st);
+  for (int j = 0; j < nl && j < FH_MAX_LOADS && warm; ++j) {
+    c->last.guess_used[j] = used[j];
+    c->last.guess_res[j] = gres[j];
+  }
+  c->last.guess_ms = guess_ms;
   for (int j = 0; j < nl && j < FH_MAX_LOADS && j < (int)outer.size(); ++j)
     c->last.outer[j] = outer[j];
   c->last.setup_ms = setup_ms;
@@ -1652,6 +1780,12 @@ int fh_solve(fh_ctx* c, const fh_opts* opt, fh_stats* st) {
   c->kt.on = false;
   if (st) *st = c->last;
   return rc;
+}
+
+int fh_set_warm_start(fh_ctx* c, fh_net* net) {
+  if (!c) return FH_EINVAL;
+  c->net = net;
+  return FH_OK;
 }
 
 int fh_get_fluctuation(fh_ctx* c, int load, double* u_dev) {

@@ -168,5 +168,18 @@ hipError_t launch_add_masked(double* dst, const float* src, long long F, int nlo
 hipError_t launch_impulse(double* f, long long n, long long pos, hipStream_t s);
 hipError_t launch_field_sum(const double* x, long long n, double* out_part, int nb,
                             hipStream_t s);
+// x[seg][.] -= its mean for nseg segments of n values (part: nseg x nchunk)
+hipError_t launch_remove_mean(double* x, int nseg, long long n, double* part, int nchunk,
+                              hipStream_t s);
 
+}  // namespace fh
+
+// learned warm start (net.hip)
+struct fh_net;
+#include <string>
+namespace fh {
+int net_warm_guess(fh_net* net, hipStream_t stream, const uint8_t* phase_dev, float gamma,
+                   int nload, const double* E, double scale, double* x, long long F,
+                   std::string* err);
+int net_grid(const fh_net* net);
 }  // namespace fh

@@ -149,6 +149,33 @@ hipError_t launch_sum_partials(const double* part, int nb, double* out, hipStrea
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, part, nb, out);
   return hipGetLastError();
 }
+// x[seg][k] -= mean_k x[seg][k]: per segment nchunk fixed-order partial sums,
+// then every thread sums its segment's partials in the same order.
+__global__ void k_seg_part(const double* x, long long n, int nchunk, double* part) {
+  __shared__ double sh[256];
+  const int seg = blockIdx.y, chunk = blockIdx.x;
+  const long long len = (n + nchunk - 1) / nchunk;
+  const long long k0 = chunk * len, k1 = k0 + len < n ? k0 + len : n;
+  double v = 0.0;
+  for (long long k = k0 + threadIdx.x; k < k1; k += 256) v += x[(long long)seg * n + k];
+  const double s = block_sum_fixed(v, sh);
+  if (threadIdx.x == 0) part[(long long)seg * nchunk + chunk] = s;
+}
+__global__ void k_seg_sub(double* x, long long n, int nchunk, const double* part) {
+  const int seg = blockIdx.y;
+  double tot = 0.0;
+  for (int c = 0; c < nchunk; ++c) tot += part[(long long)seg * nchunk + c];
+  const double mean = tot / (double)n;
+  for (long long k = blockIdx.x * 256LL + threadIdx.x; k < n; k += (long long)gridDim.x * 256)
+    x[(long long)seg * n + k] -= mean;
+}
+hipError_t launch_remove_mean(double* x, int nseg, long long n, double* part, int nchunk,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_part, dim3(nchunk, nseg), dim3(256), 0, s, x, n, nchunk, part);
+  hipLaunchKernelGGL(k_seg_sub, dim3(256, nseg), dim3(256), 0, s, x, n, nchunk, part);
+  return hipGetLastError();
+}
+
 hipError_t launch_field_sum(const double* x, long long n, double* part, int nb, hipStream_t s) {
   hipLaunchKernelGGL(k_field_sum, dim3(nb), dim3(256), 0, s, x, n, part);
   return hipGetLastError();

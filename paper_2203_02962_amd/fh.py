@@ -1,4 +1,5 @@
-"""Thin ctypes binding of the C-ABI declared in include/fh.h.
+"""Thin ctypes binding of the C-ABI declared in include/fh.h and
+include/fh_net.h.
 
 Argument marshalling only: every step of the solver runs in libfh.so.  Device
 arrays are passed as torch tensors on the context's device (their data
@@ -23,6 +24,8 @@ FH_FP64, FH_FP32_REFINED = 0, 1
 FH_MAX_LOADS = 32
 FH_FLAG_TIME_KERNELS = 1
 FH_FLAG_REBUILD = 2
+FH_FLAG_WARM_START = 4
+NET_CLASSES = ["conv", "dgrad", "wgrad", "other"]
 KERNEL_CLASSES = ["operator", "xfwd", "yfwd", "zsolve", "yinv", "xinv", "scalar", "other"]
 
 ELEMENTS = {"hex8": FH_HEX8, "quad4": FH_QUAD4, "tri2": FH_TRI2}
@@ -34,14 +37,19 @@ EXPORTED = [
     "fh_workspace_size", "fh_bind_workspace", "fh_solve", "fh_get_fluctuation",
     "fh_get_homogenized", "fh_get_reference", "fh_get_history", "fh_apply_operator",
     "fh_apply_preconditioner", "fh_compute_rhs", "fh_get_symbol", "fh_solve_rhs",
-    "fh_solve_batch",
+    "fh_solve_batch", "fh_set_warm_start",
+    "fh_net_param_count", "fh_net_create", "fh_net_destroy", "fh_net_last_error",
+    "fh_net_set_stream", "fh_net_set_params", "fh_net_get_params", "fh_net_forward",
+    "fh_net_gradient", "fh_net_adam", "fh_net_train", "fh_net_pack_target",
+    "fh_net_set_timing", "fh_net_get_stats", "fh_net_guess",
 ]
 
 
 class fh_opts(ctypes.Structure):
     _fields_ = [("eta", ctypes.c_double), ("itmax", ctypes.c_int),
                 ("precision", ctypes.c_int), ("poll", ctypes.c_int),
-                ("flags", ctypes.c_int), ("eta_inner", ctypes.c_double)]
+                ("flags", ctypes.c_int), ("eta_inner", ctypes.c_double),
+                ("guess_dev", ctypes.c_void_p)]
 
 
 class fh_stats(ctypes.Structure):
@@ -52,7 +60,9 @@ class fh_stats(ctypes.Structure):
                 ("outer", ctypes.c_int * FH_MAX_LOADS),
                 ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
                 ("chom_ms", ctypes.c_double), ("dof", ctypes.c_longlong),
-                ("kernel_ms", ctypes.c_double * 8), ("kernel_launches", ctypes.c_longlong * 8)]
+                ("kernel_ms", ctypes.c_double * 8), ("kernel_launches", ctypes.c_longlong * 8),
+                ("guess_used", ctypes.c_int * FH_MAX_LOADS),
+                ("guess_res", ctypes.c_double * FH_MAX_LOADS), ("guess_ms", ctypes.c_double)]
 
     def as_dict(self):
         n = self.nload
@@ -60,12 +70,31 @@ class fh_stats(ctypes.Structure):
                     rel_res=list(self.rel_res[:n]), outer=list(self.outer[:n]),
                     setup_ms=self.setup_ms, solve_ms=self.solve_ms, chom_ms=self.chom_ms,
                     dof=self.dof, kernel_ms=list(self.kernel_ms),
-                    kernel_launches=list(self.kernel_launches))
+                    kernel_launches=list(self.kernel_launches),
+                    guess_used=list(self.guess_used[:n]), guess_res=list(self.guess_res[:n]),
+                    guess_ms=self.guess_ms)
 
 
 class fh_system(ctypes.Structure):
     _fields_ = [("phase_dev", ctypes.c_void_p), ("n", ctypes.c_int * 3),
-                ("nphase", ctypes.c_int), ("mat", ctypes.POINTER(ctypes.c_double))]
+                ("nphase", ctypes.c_int), ("mat", ctypes.POINTER(ctypes.c_double)),
+                ("u_dev", ctypes.c_void_p)]
+
+
+class fh_adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double),
+                ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
+                ("clip", ctypes.c_double)]
+
+
+class fh_net_stats(ctypes.Structure):
+    _fields_ = [("kernel_ms", ctypes.c_double * 4), ("kernel_launches", ctypes.c_longlong * 4),
+                ("flops", ctypes.c_double * 4), ("adam_steps", ctypes.c_longlong)]
+
+    def as_dict(self):
+        return {k: dict(ms=self.kernel_ms[i], launches=self.kernel_launches[i],
+                        flops=self.flops[i]) for i, k in enumerate(NET_CLASSES)} | \
+            dict(adam_steps=self.adam_steps)
 
 
 FH_MAX_GROUPS = 16
@@ -124,6 +153,24 @@ def load_library(path: str = LIB_PATH):
         "fh_solve_batch": ([P, I, ctypes.POINTER(fh_system), I, ctypes.POINTER(D),
                             ctypes.POINTER(fh_opts), ctypes.POINTER(D), ctypes.POINTER(fh_stats),
                             ctypes.POINTER(fh_batch_report)], I),
+        "fh_set_warm_start": ([P, P], I),
+        "fh_net_param_count": ([], ctypes.c_longlong),
+        "fh_net_create": ([ctypes.POINTER(P), I, I, I], I),
+        "fh_net_destroy": ([P], None),
+        "fh_net_last_error": ([P], ctypes.c_char_p),
+        "fh_net_set_stream": ([P, P], I),
+        "fh_net_set_params": ([P, ctypes.POINTER(ctypes.c_float)], I),
+        "fh_net_get_params": ([P, ctypes.POINTER(ctypes.c_float)], I),
+        "fh_net_forward": ([P, I, P, ctypes.POINTER(ctypes.c_float), P], I),
+        "fh_net_gradient": ([P, I, P, ctypes.POINTER(ctypes.c_float), P,
+                             ctypes.POINTER(D), ctypes.POINTER(ctypes.c_float)], I),
+        "fh_net_adam": ([P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(fh_adam)], I),
+        "fh_net_train": ([P, I, P, ctypes.POINTER(ctypes.c_float), P, I, I,
+                          ctypes.POINTER(I), ctypes.POINTER(fh_adam), ctypes.POINTER(D)], I),
+        "fh_net_pack_target": ([P, P, D, P], I),
+        "fh_net_set_timing": ([P, I], I),
+        "fh_net_get_stats": ([P, ctypes.POINTER(fh_net_stats)], I),
+        "fh_net_guess": ([P, P, ctypes.c_float, I, ctypes.POINTER(D), D, P], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -240,10 +287,18 @@ class Context:
     def opts(eta=1e-10, itmax=10000, precision=FH_FP64, poll=0, eta_inner=0.0, flags=0):
         return fh_opts(eta, itmax, precision, poll, flags, eta_inner)
 
+    def set_warm_start(self, net):
+        """Attach a Net (None detaches) for solves with warm_start=True."""
+        self._net = net
+        return self._check(self.lib.fh_set_warm_start(self.ptr, net.ptr if net else None))
+
     def solve(self, eta=1e-10, itmax=10000, precision=FH_FP64, poll=0, eta_inner=0.0,
-              time_kernels=False, rebuild=False):
-        flags = (FH_FLAG_TIME_KERNELS if time_kernels else 0) | (FH_FLAG_REBUILD if rebuild else 0)
+              time_kernels=False, rebuild=False, warm_start=False, guess_dev=None):
+        flags = (FH_FLAG_TIME_KERNELS if time_kernels else 0) | \
+            (FH_FLAG_REBUILD if rebuild else 0) | (FH_FLAG_WARM_START if warm_start else 0)
         o = self.opts(eta, itmax, precision, poll, eta_inner, flags)
+        if guess_dev is not None:
+            o.guess_dev = _tptr(guess_dev).value
         st = fh_stats()
         rc = self._check(self.lib.fh_solve(self.ptr, ctypes.byref(o), ctypes.byref(st)),
                          allow_warning=True)
@@ -295,8 +350,10 @@ class Context:
 
 
     def solve_batch(self, systems, E, eta=1e-6, itmax=10000, precision=FH_FP32_REFINED,
-                    poll=0, eta_inner=0.0):
+                    poll=0, eta_inner=0.0, u_out=None):
         """systems: list of (phase_dev uint8 tensor, n (3,), mat (nphase, 6, 6)).
+        u_out: optional list of float64 CUDA tensors (nload x 3 x N each) that
+        receive the fluctuation fields.
         Returns (rc, chom (nsys, nload, nload), [stats dicts], [group reports])."""
         E = np.ascontiguousarray(np.atleast_2d(E), dtype=np.float64)
         nload = E.shape[0]
@@ -307,6 +364,7 @@ class Context:
             arr[i].n = (ctypes.c_int * 3)(*[int(v) for v in n])
             arr[i].nphase = int(m.shape[0])
             arr[i].mat = _dptr(m)
+            arr[i].u_dev = _tptr(u_out[i]).value if u_out is not None else None
         chom = np.zeros((len(systems), nload, nload))
         sts = (fh_stats * len(systems))()
         rep = fh_batch_report()
@@ -325,3 +383,104 @@ def _dptr_out(arr):
 # C-ABI names as module-level functions (same names as include/fh.h)
 def fh_create(device=0):
     return Context(device)
+
+
+class Net:
+    """Owns one fh_net (learned warm start, include/fh_net.h)."""
+
+    def __init__(self, n: int = 64, max_batch: int = 8, device: int = 0):
+        self.lib = load_library()
+        self.ptr = ctypes.c_void_p()
+        rc = self.lib.fh_net_create(ctypes.byref(self.ptr), device, int(n), int(max_batch))
+        if rc != FH_OK:
+            raise FHError(rc, f"fh_net_create(n={n}, max_batch={max_batch}) failed")
+        self.n, self.max_batch, self.device = n, max_batch, device
+        self.P = int(self.lib.fh_net_param_count())
+
+    def _check(self, rc):
+        if rc != FH_OK:
+            raise FHError(rc, self.lib.fh_net_last_error(self.ptr).decode())
+        return rc
+
+    def close(self):
+        if self.ptr:
+            self.lib.fh_net_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _f32(a):
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+    def set_stream(self, stream):
+        raw = getattr(stream, "cuda_stream", stream)
+        return self._check(self.lib.fh_net_set_stream(self.ptr, ctypes.c_void_p(raw)))
+
+    def set_params(self, params):
+        a, p = self._f32(params)
+        assert a.size == self.P
+        return self._check(self.lib.fh_net_set_params(self.ptr, p))
+
+    def get_params(self):
+        a, p = self._f32(np.zeros(self.P))
+        self._check(self.lib.fh_net_get_params(self.ptr, p))
+        return a
+
+    def forward(self, phase_dev, gamma, out_dev):
+        g, gp = self._f32(gamma)
+        return self._check(self.lib.fh_net_forward(self.ptr, int(g.size), _tptr(phase_dev), gp,
+                                                   _tptr(out_dev)))
+
+    def gradient(self, phase_dev, gamma, target_dev):
+        g, gp = self._f32(gamma)
+        loss = ctypes.c_double()
+        grad, grp = self._f32(np.zeros(self.P))
+        self._check(self.lib.fh_net_gradient(self.ptr, int(g.size), _tptr(phase_dev), gp,
+                                             _tptr(target_dev), ctypes.byref(loss), grp))
+        return loss.value, grad
+
+    def adam(self, grad=None, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, clip=0.0):
+        o = fh_adam(lr, beta1, beta2, eps, clip)
+        if grad is None:
+            return self._check(self.lib.fh_net_adam(self.ptr, None, ctypes.byref(o)))
+        a, p = self._f32(grad)
+        return self._check(self.lib.fh_net_adam(self.ptr, p, ctypes.byref(o)))
+
+    def train(self, phase_dev, gamma, target_dev, order, batch, lr=1e-3, beta1=0.9,
+              beta2=0.999, eps=1e-8, clip=0.0):
+        """order: int array (steps, batch) of sample indices.  Returns the
+        loss of every step."""
+        order = np.ascontiguousarray(order, dtype=np.int32)
+        steps = order.shape[0]
+        g, gp = self._f32(gamma)
+        loss = np.zeros(max(steps, 1))
+        o = fh_adam(lr, beta1, beta2, eps, clip)
+        self._check(self.lib.fh_net_train(
+            self.ptr, int(g.size), _tptr(phase_dev), gp, _tptr(target_dev), int(batch),
+            int(steps), order.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(o),
+            _dptr_out(loss)))
+        return loss[:steps]
+
+    def guess(self, phase_dev, gamma, E, length, x_dev):
+        E = np.ascontiguousarray(np.atleast_2d(E), dtype=np.float64)
+        return self._check(self.lib.fh_net_guess(self.ptr, _tptr(phase_dev), float(gamma),
+                                                 E.shape[0], _dptr(E), float(length),
+                                                 _tptr(x_dev)))
+
+    def pack_target(self, u_dev, scale, target_dev):
+        return self._check(self.lib.fh_net_pack_target(self.ptr, _tptr(u_dev), float(scale),
+                                                       _tptr(target_dev)))
+
+    def set_timing(self, on=True):
+        return self._check(self.lib.fh_net_set_timing(self.ptr, 1 if on else 0))
+
+    def stats(self):
+        st = fh_net_stats()
+        self._check(self.lib.fh_net_get_stats(self.ptr, ctypes.byref(st)))
+        return st.as_dict()

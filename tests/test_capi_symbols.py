@@ -1,4 +1,4 @@
-"""The C-ABI library loads and exports every symbol include/fh.h declares
+"""The C-ABI library loads and exports every symbol include/*.h declares
 (CPU only: no compute call is made)."""
 import ctypes
 import os
@@ -7,12 +7,12 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "fh.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("fh.h", "fh_net.h")]
 LIB = os.path.join(ROOT, "paper_2203_02962_amd", "libfh.so")
 
 
 def declared_functions():
-    src = open(HEADER).read()
+    src = "".join(open(h).read() for h in HEADERS)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(fh_[a-z_0-9]+)\s*\(", src)))
 

@@ -188,3 +188,21 @@ def test_param_count():
     p = cn.init_params(0)
     assert p.size == cn.param_count()
     assert sum(v[0].numel() + v[1].numel() for v in cn.unflatten(p).values()) == p.size
+
+
+def test_clipped_adam_matches_library():
+    rng = np.random.default_rng(9)
+    p0 = rng.standard_normal(40)
+    grads = [rng.standard_normal(40) * s for s in (0.1, 5.0, 20.0)]
+    t = torch.tensor(p0, requires_grad=True)
+    opt = torch.optim.Adam([t], lr=1e-3)
+    p, m, v = p0.copy(), np.zeros(40), np.zeros(40)
+    for k, gk in enumerate(grads, start=1):
+        opt.zero_grad()
+        t.grad = torch.tensor(gk)
+        torch.nn.utils.clip_grad_norm_([t], 1.0)
+        opt.step()
+        p, m, v = cn.adam(p, gk, m, v, k, lr=1e-3, clip=1.0)
+    # the library scales by clip / (norm + 1e-6): a relative 1e-6 difference
+    # in the clipped gradient, far below the lr-sized updates
+    assert np.abs(p - t.detach().numpy()).max() < 1e-9
