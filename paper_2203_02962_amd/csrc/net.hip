@@ -168,18 +168,26 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a) {
 // ------------------------------------------------------- weight gradient
 // dW[t][o][c] = sum_v dZ[o][v] X[c][v + d_t].  MFMA roles: rows = 16 output
 // channels (A = dZ, channel-major), columns = 16 input channels (B = X,
-// channel-major, x-shifted copy dx), k = 32 consecutive voxels.  A wave owns
-// one (o, c) tile for all 27 taps and a contiguous range of k steps; partial
-// sums go to part[split][t][o][c] and the per-channel sums of dZ (the bias
-// gradient) to bpart[split][o].
+// channel-major), k = 32 consecutive voxels (four 8-voxel groups of one x
+// row, one group per 16 lanes).  For every (dz, dy) row a lane loads its
+// aligned 8 voxels once plus the single voxel on each side (periodic in x)
+// and forms the dx = -1, 0, +1 operands with 16-bit funnel shifts, so each
+// input row is read once for its three x taps.  A wave owns one (o, c) tile
+// for all 27 taps and a contiguous range of k steps; partial sums go to
+// part[split][t][o][c] and the per-channel sums of dZ (the bias gradient)
+// to bpart[split][o].
 struct WgradArgs {
-  const uint16_t* xs;   // [3][B][cinp][V], copy d holds X[.][x + d - 1]
+  const uint16_t* xt;   // [B][cinp][V] channel-major layer input
   const uint16_t* dzt;  // [B][cout][V]
   float* part;
   float* bpart;
   int B, s, cinp, cout, nsplit, ntiles;
   long long ksteps;
 };
+
+__device__ __forceinline__ unsigned fshift16(unsigned lo, unsigned hi) {
+  return (lo >> 16) | (hi << 16);
+}
 
 __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
   const int lane = threadIdx.x & 63;
@@ -201,24 +209,31 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
     const int b = (int)(kv / V);
     const long long v = kv - (long long)b * V + 8 * g;
     const int x = (int)(v % s), y = (int)((v / s) % s), z = (int)(v / ((long long)s * s));
+    const int xl = x == 0 ? s - 1 : x - 1, xr = x + 8 == s ? 0 : x + 8;
     const bf16x8 av = *reinterpret_cast<const bf16x8*>(
         a.dzt + ((long long)b * a.cout + ot * 16 + i16) * V + v);
 #pragma unroll
     for (int e = 0; e < 8; ++e) bsum += bf2f((unsigned short)av[e]);
+    const uint16_t* xc = a.xt + ((long long)b * a.cinp + it * 16 + i16) * V;
 #pragma unroll
     for (int dzi = 0; dzi < 3; ++dzi) {
       const int zz = wrap(z + dzi - 1, s);
 #pragma unroll
       for (int dyi = 0; dyi < 3; ++dyi) {
         const int yy = wrap(y + dyi - 1, s);
-        const long long row = ((long long)zz * s + yy) * s + x;
-#pragma unroll
-        for (int dxi = 0; dxi < 3; ++dxi) {
-          const bf16x8 bv = *reinterpret_cast<const bf16x8*>(
-              a.xs + (((long long)dxi * a.B + b) * a.cinp + it * 16 + i16) * V + row);
-          const int t = dzi * 9 + dyi * 3 + dxi;
-          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
-        }
+        const uint16_t* row = xc + ((long long)zz * s + yy) * s;
+        const uint4 c = *reinterpret_cast<const uint4*>(row + x);
+        const unsigned L = row[xl], R = row[xr];
+        const unsigned s0 = fshift16(c.x, c.y), s1 = fshift16(c.y, c.z), s2 = fshift16(c.z, c.w);
+        const uint4 lft = {L | (c.x << 16), s0, s1, s2};
+        const uint4 rgt = {s0, s1, s2, fshift16(c.w, R)};
+        const int t0 = dzi * 9 + dyi * 3;
+        acc[t0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+            av, *reinterpret_cast<const bf16x8*>(&lft), acc[t0], 0, 0, 0);
+        acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+            av, *reinterpret_cast<const bf16x8*>(&c), acc[t0 + 1], 0, 0, 0);
+        acc[t0 + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+            av, *reinterpret_cast<const bf16x8*>(&rgt), acc[t0 + 2], 0, 0, 0);
       }
     }
   }
@@ -233,25 +248,28 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
   if (it == 0 && g == 0) a.bpart[(long long)split * a.cout + ot * 16 + i16] = bsum;
 }
 
-__global__ void k_wgrad_reduce(const float* part, const float* bpart, int nsplit, int cout,
-                               int cinp, int cin, float* gw, float* gb) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long nw = 27LL * cout * cin;
-  if (i < nw) {
-    const int c = (int)(i % cin);
-    const long long to = i / cin;  // t * cout + o
-    double acc = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) acc += part[((long long)sp * 27 * cout + to) * cinp + c];
-    gw[i] = (float)acc;
-  } else if (i < nw + cout) {
-    const int o = (int)(i - nw);
-    double acc = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) acc += bpart[(long long)sp * cout + o];
-    gb[o] = (float)acc;
-  }
+// Column sums of part[nrow][ncol] in two fixed-order stages: block (x, r)
+// sums rows r, r + R, r + 2R, ... of its 256 columns into p2[r][col]; then
+// out[map(col)] = sum_r p2[r][col], where col = a * cinp + c maps to
+// a * cin + c for c < cin (dropping padded channels) and is dropped else.
+__global__ void k_colsum1(const float* part, long long nrow, long long ncol, int R, double* p2) {
+  const long long col = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (col >= ncol) return;
+  double acc = 0.0;
+  for (long long row = blockIdx.y; row < nrow; row += R) acc += part[row * ncol + col];
+  p2[(long long)blockIdx.y * ncol + col] = acc;
+}
+__global__ void k_colsum2(const double* p2, int R, long long ncol, int cinp, int cin, float* out) {
+  const long long col = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (col >= ncol) return;
+  double acc = 0.0;
+  for (int r = 0; r < R; ++r) acc += p2[(long long)r * ncol + col];
+  const int c = (int)(col % cinp);
+  if (c < cin) out[(col / cinp) * cin + c] = (float)acc;
 }
 
-// channels-last [B][V][C] -> channel-major, x-shifted copies [3][B][C][V]
+// channels-last [B][V][C] -> channel-major [ncopy][B][C][V]; with ncopy = 3,
+// copy d holds the input shifted by d - 1 in x
 __global__ void k_prep_shifted(const uint16_t* x, int C, int s, int B, int ncopy, uint16_t* out) {
   const long long V = (long long)s * s * s;
   const int ng = C / 8;
@@ -462,22 +480,17 @@ __global__ void __launch_bounds__(320) k_head_wgrad(const float* dO, const uint1
   part[(long long)blockIdx.x * kHeadNP + p] = acc;
 }
 
-__global__ void k_reduce_cols(const float* part, int nrow, int ncol, float* out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncol) return;
-  double acc = 0.0;
-  for (int r = 0; r < nrow; ++r) acc += part[(long long)r * ncol + c];
-  out[c] = (float)acc;
-}
 
 // loss = mean_{b,o,v,d} (e[v + e_d] - e[v])^2, e = O - T; dO = dloss/dO.
+constexpr int kLossBlocks = 2048;
 __global__ void k_loss(const float* O, const uint16_t* T, const int* order, int s, int B,
                        double inv_m, float* dO, double* part) {
   __shared__ double sh[256];
   const long long V = (long long)s * s * s;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = (long long)B * kOut * V;
   double contrib = 0.0;
-  if (i < (long long)B * kOut * V) {
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < total;
+       i += (long long)gridDim.x * 256) {
     const long long v = i % V;
     const long long bo = i / V;
     const int o = (int)(bo % kOut), b = (int)(bo / kOut);
@@ -494,8 +507,8 @@ __global__ void k_loss(const float* O, const uint16_t* T, const int* order, int 
     const float ey = e(z, wrap(y + 1, s), x), eym = e(z, wrap(y - 1, s), x);
     const float ez = e(wrap(z + 1, s), y, x), ezm = e(wrap(z - 1, s), y, x);
     dO[i] = (float)(2.0 * inv_m) * (6.0f * e0 - ex - exm - ey - eym - ez - ezm);
-    contrib = (double)(ex - e0) * (ex - e0) + (double)(ey - e0) * (ey - e0) +
-              (double)(ez - e0) * (ez - e0);
+    contrib += (double)(ex - e0) * (ex - e0) + (double)(ey - e0) * (ey - e0) +
+               (double)(ez - e0) * (ez - e0);
   }
   sh[threadIdx.x] = contrib;
   __syncthreads();
@@ -541,13 +554,16 @@ __global__ void k_clip_factor(const double* part, int nb, double clip, float* fa
   *factor = (float)(nrm > clip ? clip / nrm : 1.0);
 }
 
+// omb1 = 1 - b1 and omb2 = 1 - b2 come from the host in FP64 (in FP32,
+// 1 - 0.999f is 0.00100005, a 5e-5 relative error in the second moment)
 __global__ void k_adam(float* p, const float* g, float* m, float* v, long long n, float lr,
-                       float b1, float b2, float eps, float c1, float c2, const float* factor) {
+                       float b1, float b2, float omb1, float omb2, float eps, float c1, float c2,
+                       const float* factor) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float gi = factor ? g[i] * *factor : g[i];
-  const float mi = b1 * m[i] + (1.0f - b1) * gi;
-  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  const float mi = b1 * m[i] + omb1 * gi;
+  const float vi = b2 * v[i] + omb2 * gi * gi;
   m[i] = mi;
   v[i] = vi;
   p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
@@ -664,7 +680,8 @@ struct fh_net {
   float *O, *dO;
   uint16_t *dc0, *dc1, *dc2, *ta, *tb, *xs, *dzt;
   float *wpart, *bpart, *hpart;
-  size_t wpart_n = 0, bpart_n = 0;
+  double* csum;
+  size_t wpart_n = 0, bpart_n = 0, csum_n = 0;
   double *lpart, *scal, *chpart, *chmean, *Edev;
   float* gamma_dev;
   float* clipf;
@@ -778,6 +795,19 @@ int conv(fh_net* N, const uint16_t* x, int cin, const uint16_t* w, const float* 
   return FH_OK;
 }
 
+// out <- column sums of part[nrow][ncol] (see k_colsum1/2)
+int colsum(fh_net* N, const float* part, long long nrow, long long ncol, int cinp, int cin,
+           float* out) {
+  int R = (int)std::min<long long>(nrow, 64);
+  R = (int)std::max<long long>(1, std::min<long long>(R, (long long)(N->csum_n / ncol)));
+  hipLaunchKernelGGL(k_colsum1, dim3(nblk(ncol), R), dim3(256), 0, N->stream, part, nrow, ncol, R,
+                     N->csum);
+  hipLaunchKernelGGL(k_colsum2, dim3(nblk(ncol)), dim3(256), 0, N->stream, N->csum, R, ncol, cinp,
+                     cin, out);
+  NCHK(N, hipGetLastError());
+  return FH_OK;
+}
+
 // weight and bias gradient of layer l from its input x (channels last,
 // cinp channels) and the output gradient dz (cout channels)
 int wgrad(fh_net* N, int l, const uint16_t* x, const uint16_t* dz, int B) {
@@ -786,7 +816,7 @@ int wgrad(fh_net* N, int l, const uint16_t* x, const uint16_t* dz, int B) {
   TScope ts(N, FH_NET_K_WGRAD);
   N->flops[FH_NET_K_WGRAD] += 2.0 * B * V * 27.0 * cin * co;
   hipLaunchKernelGGL(k_prep_shifted, dim3(nblk((long long)B * (ci / 8) * V)), dim3(256), 0,
-                     N->stream, x, ci, s, B, 3, N->xs);
+                     N->stream, x, ci, s, B, 1, N->xs);
   NCHK(N, hipGetLastError());
   hipLaunchKernelGGL(k_prep_shifted, dim3(nblk((long long)B * (co / 8) * V)), dim3(256), 0,
                      N->stream, dz, co, s, B, 1, N->dzt);
@@ -794,18 +824,17 @@ int wgrad(fh_net* N, int l, const uint16_t* x, const uint16_t* dz, int B) {
   const int ntiles = (co / 16) * (ci / 16);
   const long long ksteps = (long long)B * V / 32;
   long long nsplit = std::max<long long>(1, (4096 + ntiles - 1) / ntiles);
-  nsplit = std::min(nsplit, std::max<long long>(1, ksteps / 8));
+  nsplit = std::min(nsplit, std::max<long long>(1, ksteps / 16));
+  nsplit = std::min<long long>(nsplit, 1024);
   nsplit = std::min<long long>(nsplit, (long long)(N->wpart_n / (27LL * co * ci)));
   nsplit = std::min<long long>(nsplit, (long long)(N->bpart_n / co));
   WgradArgs a{N->xs, N->dzt, N->wpart, N->bpart, B, s, ci, co, (int)nsplit, ntiles, ksteps};
   hipLaunchKernelGGL(k_wgrad, dim3(nblk((long long)ntiles * nsplit, 4)), dim3(256), 0, N->stream,
                      a);
   NCHK(N, hipGetLastError());
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblk(27LL * co * cin + co)), dim3(256), 0, N->stream,
-                     N->wpart, N->bpart, (int)nsplit, co, ci, cin, N->gr + N->offw[l],
-                     N->gr + N->offb[l]);
-  NCHK(N, hipGetLastError());
-  return FH_OK;
+  int rc = colsum(N, N->wpart, nsplit, 27LL * co * ci, ci, cin, N->gr + N->offw[l]);
+  if (!rc) rc = colsum(N, N->bpart, nsplit, co, co, co, N->gr + N->offb[l]);
+  return rc;
 }
 
 int pack_all(fh_net* N) {
@@ -887,17 +916,17 @@ int backward(fh_net* N, int B, const uint16_t* target, const int* order, double*
   {
     TScope ts(N, FH_NET_K_OTHER);
     const long long tot = (long long)B * kOut * V0;
-    const unsigned nb = nblk(tot);
-    hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, N->stream, N->O, target, order, s0, B,
-                       1.0 / (3.0 * (double)tot), N->dO, N->lpart);
-    hipLaunchKernelGGL(k_sum_double, dim3(1), dim3(256), 0, N->stream, N->lpart, (int)nb,
+    hipLaunchKernelGGL(k_loss, dim3(kLossBlocks), dim3(256), 0, N->stream, N->O, target, order,
+                       s0, B, 1.0 / (3.0 * (double)tot), N->dO, N->lpart);
+    hipLaunchKernelGGL(k_sum_double, dim3(1), dim3(256), 0, N->stream, N->lpart, kLossBlocks,
                        loss_dev);
     // head
     const unsigned nhb = (unsigned)(B * (V0 / kHeadChunk));
     hipLaunchKernelGGL(k_head_wgrad, dim3(nhb), dim3(320), 0, N->stream, N->dO, N->d0, V0,
                        N->hpart);
-    hipLaunchKernelGGL(k_reduce_cols, dim3(nblk(kHeadNP)), dim3(256), 0, N->stream, N->hpart,
-                       (int)nhb, kHeadNP, N->gr + N->offw[kLayers]);
+    NCHK(N, hipGetLastError());
+    int rc0 = colsum(N, N->hpart, nhb, kHeadNP, kHeadNP, kHeadNP, N->gr + N->offw[kLayers]);
+    if (rc0) return rc0;
     hipLaunchKernelGGL(k_head_bwd, dim3(nblk((long long)B * V0)), dim3(256), 0, N->stream, N->dO,
                        N->d0, N->wh, V0, B, N->ta);
     NCHK(N, hipGetLastError());
@@ -963,8 +992,8 @@ int adam_step(fh_net* N, const fh_adam& o) {
     factor = N->clipf;
   }
   hipLaunchKernelGGL(k_adam, dim3(nblk(N->P)), dim3(256), 0, N->stream, N->p, N->gr, N->m, N->v,
-                     N->P, (float)o.lr, (float)o.beta1, (float)o.beta2, (float)o.eps, (float)c1,
-                     (float)c2, factor);
+                     N->P, (float)o.lr, (float)o.beta1, (float)o.beta2, (float)(1.0 - o.beta1),
+                     (float)(1.0 - o.beta2), (float)o.eps, (float)c1, (float)c2, factor);
   NCHK(N, hipGetLastError());
   N->packed = false;
   return pack_all(N);
@@ -1051,7 +1080,9 @@ int fh_net_create(fh_net** out, int device, int n, int max_batch) {
   add((void**)&N->wpart, sizeof(float) * N->wpart_n);
   add((void**)&N->bpart, sizeof(float) * N->bpart_n);
   add((void**)&N->hpart, sizeof(float) * (size_t)(B * (V[0] / kHeadChunk)) * kHeadNP);
-  add((void**)&N->lpart, sizeof(double) * (size_t)nblk(B * kOut * V[0]));
+  add((void**)&N->lpart, sizeof(double) * kLossBlocks);
+  N->csum_n = 4ULL << 20;  // doubles
+  add((void**)&N->csum, sizeof(double) * N->csum_n);
   add((void**)&N->scal, sizeof(double) * 8);
   add((void**)&N->chpart, sizeof(double) * kOut * 256);
   add((void**)&N->chmean, sizeof(double) * kOut);

@@ -7,5 +7,5 @@ produced here as plain inputs.
 """
 from .microstructure import (  # noqa: F401
     isotropic_mandel, isotropic_conductivity, spheres, circles2d, laminate,
-    gaussian_random_field, conductivity_grf, workload, batch_workload,
+    gaussian_random_field, conductivity_grf, workload, batch_workload, batch_workload_parallel,
 )

@@ -230,3 +230,19 @@ def batch_workload(count: int = 96, seed0: int = 1000,
                         mat=mat, loads=_unit_loads(6), eta=1e-6, vf=got,
                         vf_target=vf, contrast=contrast, seed=seed0 + i))
     return out
+
+
+def batch_workload_parallel(count: int = 96, seed0: int = 1000,
+                            sizes=(32, 48, 64, 96), fixed_n: int | None = None,
+                            max_attempts: int = 20000, workers: int = 8):
+    """The microstructures of batch_workload(count, seed0, ...), generated in
+    `workers` fresh processes (each one is drawn from its own seed, so the
+    result is identical to the serial call)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    if workers <= 1 or count <= 1:
+        return batch_workload(count, seed0, sizes, fixed_n, max_attempts)
+    with ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        futs = [ex.submit(batch_workload, 1, seed0 + i, sizes, fixed_n, max_attempts)
+                for i in range(count)]
+        return [f.result()[0] for f in futs]

@@ -43,3 +43,11 @@ def test_named_workloads():
     assert w["phase"].shape == (32, 32, 32) and w["vf"] >= 0.3
     b = batch_workload(count=3)
     assert [x["n"][0] for x in b] == [x["n"][0] for x in batch_workload(count=3)]
+
+
+def test_parallel_batch_workload_equals_serial():
+    from synth.microstructure import batch_workload, batch_workload_parallel
+    a = batch_workload(count=3, seed0=77, fixed_n=16)
+    b = batch_workload_parallel(count=3, seed0=77, fixed_n=16, workers=2)
+    for x, y in zip(a, b):
+        assert np.array_equal(x["phase"], y["phase"]) and x["contrast"] == y["contrast"]
