@@ -140,6 +140,117 @@ def batch_comparison(count: int):
     }
 
 
+MFMA_BF16_PEAK_TFS = 2500.0
+
+
+def warm_start_comparison(ntrain: int, neval: int, steps: int, batch: int = 8, n: int = 64):
+    """Learned warm start at n^3: `ntrain` seeded microstructures of the
+    batched workload's kind (vf ~ U[0.1,0.4], contrast ~ U[10,1000]) solved
+    for the 6 unit strains to 1e-6 (FP32-refined batched solves) give the
+    training targets; the network is trained on the GPU (Adam, `steps`
+    minibatches of `batch`, learning rate 5e-4 -> 1.7e-4 -> 5e-5, global-norm
+    clip 1); `neval` further seeded microstructures are then solved to 1e-6
+    from zero and from the network's guess (FP64 and FP32-refined), and PCG
+    iterations and wall times are compared."""
+    import numpy as np
+    import torch
+
+    from paper_2203_02962_amd import fh
+    from paper_2203_02962_amd.runner import setup_context
+    from synth import batch_workload_parallel
+    from synth.netinit import init_params
+
+    V = n ** 3
+    t0 = time.perf_counter()
+    wls = batch_workload_parallel(count=ntrain + neval, seed0=20000, fixed_n=n, workers=16)
+    t_gen = time.perf_counter() - t0
+    print(f"[bench] warm: {len(wls)} microstructures generated in {t_gen:.0f} s",
+          file=sys.stderr, flush=True)
+    gamma = np.array([np.log10(w["contrast"]) / 3.0 for w in wls], dtype=np.float32)
+    phase = torch.empty((ntrain, V), dtype=torch.uint8, device="cuda")
+    target = torch.empty((ntrain, 18, V), dtype=torch.int16, device="cuda")
+    net = fh.Net(n, batch)
+    ctx = fh.Context(0)
+    t0 = time.perf_counter()
+    for c0 in range(0, ntrain, 64):
+        sel = range(c0, min(ntrain, c0 + 64))
+        ph = [torch.from_numpy(wls[i]["phase"].reshape(-1)).cuda() for i in sel]
+        us = [torch.empty((6, 3, V), dtype=torch.float64, device="cuda") for _ in sel]
+        ctx.solve_batch([(p_, (n, n, n), wls[i]["mat"]) for p_, i in zip(ph, sel)], np.eye(6),
+                        eta=1e-6, u_out=us)
+        for k, i in enumerate(sel):
+            phase[i] = ph[k]
+            net.pack_target(us[k], float(n), target[i])
+        del us
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    print(f"[bench] warm: {ntrain} training solves in {t_data:.0f} s", file=sys.stderr, flush=True)
+    net.set_params(init_params(1).astype(np.float32))
+    rng = np.random.default_rng(0)
+    order = np.concatenate([rng.permutation(ntrain) for _ in range(steps * batch // ntrain + 1)])
+    order = order[:steps * batch].reshape(steps, batch).astype(np.int32)
+    net.set_timing(True)
+    t0 = time.perf_counter()
+    losses = []
+    for a, b, lr in ((0.0, 0.6, 5e-4), (0.6, 0.85, 5e-4 / 3), (0.85, 1.0, 5e-5)):
+        losses.append(net.train(phase, gamma[:ntrain], target, order[int(a * steps):int(b * steps)],
+                                batch, lr=lr, clip=1.0))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    losses = np.concatenate(losses)
+    nst = net.stats()
+    net.set_timing(False)
+    print(f"[bench] warm: {steps} training steps in {t_train:.0f} s, loss {losses[:50].mean():.4f}"
+          f" -> {losses[-50:].mean():.4f}", file=sys.stderr, flush=True)
+    del phase, target
+    tot = {k: 0.0 for k in ("cold_it", "warm_it", "cold_ms", "warm_ms", "cold_r_it", "warm_r_it",
+                            "cold_r_ms", "warm_r_ms")}
+    used, gres = 0, []
+    for w in wls[ntrain:]:
+        wl = dict(w)
+        wl["loads"] = np.eye(6)
+        c = setup_context(wl)
+        c.set_warm_start(net)
+        for prec, key in ((fh.FH_FP64, ""), (fh.FH_FP32_REFINED, "_r")):
+            c.solve(eta=1e-6, precision=prec)     # builds symbol and right-hand sides
+            for mode in ("cold", "warm"):
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                rc, st = c.solve(eta=1e-6, precision=prec, warm_start=(mode == "warm"))
+                torch.cuda.synchronize()
+                tot[mode + key + "_ms"] += (time.perf_counter() - ta) * 1000.0
+                tot[mode + key + "_it"] += sum(st["iterations"])
+                if mode == "warm" and key == "":
+                    used += sum(st["guess_used"])
+                    gres += st["guess_res"]
+        c.close()
+    conv = nst["conv"]
+    conv_tfs = conv["flops"] / (conv["ms"] / 1000.0) / 1e12 if conv["ms"] > 0 else None
+    return {
+        "grid": n, "train_systems": ntrain, "eval_systems": neval, "steps": steps,
+        "batch": batch, "data_gen_s": round(t_gen, 1), "train_solves_s": round(t_data, 1),
+        "train_s": round(t_train, 1),
+        "loss_first50": float(losses[:50].mean()), "loss_last50": float(losses[-50:].mean()),
+        "kernels": {k: {"ms": round(v["ms"], 1), "launches": v["launches"],
+                        "TFLOPs": (round(v["flops"] / (v["ms"] / 1000.0) / 1e12, 1)
+                                   if v["flops"] and v["ms"] else None)}
+                    for k, v in nst.items() if isinstance(v, dict)},
+        "conv_roofline": {"bound": "mfma", "achieved": conv_tfs, "peak": MFMA_BF16_PEAK_TFS,
+                          "unit": "TFLOP/s", "dtype": "bf16",
+                          "frac": round(conv_tfs / MFMA_BF16_PEAK_TFS, 4) if conv_tfs else None},
+        "guess_accepted": f"{used}/{6 * neval}",
+        "guess_residual_median": float(np.median(gres)) if gres else None,
+        "fp64_1e-6": {"cold_iterations": int(tot["cold_it"]), "warm_iterations": int(tot["warm_it"]),
+                      "cold_ms": round(tot["cold_ms"], 1), "warm_ms": round(tot["warm_ms"], 1),
+                      "speedup": round(tot["cold_ms"] / tot["warm_ms"], 3)},
+        "fp32_refined_1e-6": {"cold_inner_iterations": int(tot["cold_r_it"]),
+                              "warm_inner_iterations": int(tot["warm_r_it"]),
+                              "cold_ms": round(tot["cold_r_ms"], 1),
+                              "warm_ms": round(tot["warm_r_ms"], 1),
+                              "speedup": round(tot["cold_r_ms"] / tot["warm_r_ms"], 3)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +264,11 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 96-microstructure batched comparison")
     ap.add_argument("--batch-count", type=int, default=96)
+    ap.add_argument("--no-warm", action="store_true",
+                    help="skip the learned warm-start training and comparison")
+    ap.add_argument("--warm-train", type=int, default=2000)
+    ap.add_argument("--warm-eval", type=int, default=200)
+    ap.add_argument("--warm-steps", type=int, default=4000)
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run a plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -296,6 +412,9 @@ def main():
     }
     if not args.no_batch:
         out["config"]["batched_vs_plain_1e-6"] = batch_comparison(args.batch_count)
+    if not args.no_warm:
+        out["config"]["warm_start_vs_zero_1e-6"] = warm_start_comparison(
+            args.warm_train, args.warm_eval, args.warm_steps)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_iters)

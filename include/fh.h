@@ -104,8 +104,9 @@ typedef struct fh_opts {
   int precision;    /* FH_FP64 or FH_FP32_REFINED                                 */
   int poll;         /* iterations between host convergence polls (0 = default)   */
   int flags;        /* FH_FLAG_* bits                                             */
-  double eta_inner; /* inner FP32 tolerance for FH_FP32_REFINED (0 = sqrt(eta)
-                       when eta >= 1e-6, else 1e-4)                               */
+  double eta_inner; /* FH_FP32_REFINED: sweep k of the refinement brings the
+                       residual to max(eta_inner^(k+1), eta/2) times that of b
+                       (0 = sqrt(eta) when eta >= 1e-6, else 1e-4)                */
   const double *guess_dev; /* initial fluctuation u_(0) of Alg. 1 for every load
                        case (device, nload x nd x N; NULL = zero).  It is shifted
                        to zero mean per component and judged: a load case keeps

@@ -87,16 +87,8 @@ def flatten(grads) -> np.ndarray:
     return torch.cat(parts).numpy()
 
 
-def init_params(seed: int) -> np.ndarray:
-    """He-normal convolution weights, small random biases and head (seeded)."""
-    rng = np.random.default_rng(seed)
-    parts = []
-    for _, ci, co, _ in LAYERS:
-        parts.append(rng.normal(0.0, np.sqrt(2.0 / (27 * ci)), 27 * co * ci))
-        parts.append(rng.normal(0.0, 0.01, co))
-    parts.append(rng.normal(0.0, 0.1 / np.sqrt(HEAD_IN), NOUT * HEAD_IN))
-    parts.append(np.zeros(NOUT))
-    return np.concatenate(parts)
+# seeded initial weights are inputs: drawn by the shared input generators
+from synth.netinit import init_params  # noqa: E402,F401
 
 
 def bf16(x: torch.Tensor) -> torch.Tensor:

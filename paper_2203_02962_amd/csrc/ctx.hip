@@ -937,8 +937,20 @@ int pcg_refined(fh_ctx* c, int nload, double eta, double eta_in, int itmax, int 
                              hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, fh::launch_cast_masked(L.r, L.r32, F, nload, L.st, c->stream));
     PcgBufs<float> bf{L.x32, L.r32, L.p32, L.q32, L.A32, L.B32, L.kplus_f};
+    // sweep k aims at |r| <= tau_k |b| (M-norms), tau_k = max(eta_in^(k+1),
+    // eta/2): the inner tolerance relative to the current residual is
+    // tau_k sqrt(rho0 / rho), kept within [1e-5, 0.5] (FP32 PCG stalls
+    // below about 1e-6).  A warm start that already removed part of b, or a
+    // last sweep that only needs a little more, asks the inner solve for less.
+    std::vector<double> eta2(nload, eta_in * eta_in);
+    const double tau = std::max(std::pow(eta_in, sweep + 1), 0.5 * eta);
+    for (int j = 0; j < nload; ++j)
+      if (active[j] && rho[j] > 0.0) {
+        const double rel = std::min(0.5, std::max(1e-5, tau * std::sqrt(rho0[j] / rho[j])));
+        eta2[j] = rel * rel;
+      }
     std::vector<fh::PcgState> hs;
-    rc = pcg_run<float>(c, nload, bf, eta_in, std::max(1, itmax), poll, active, hs);
+    rc = pcg_run<float>(c, nload, bf, eta_in, std::max(1, itmax), poll, active, hs, true, &eta2);
     if (rc) return rc;
     for (int j = 0; j < nload; ++j)
       if (active[j]) {

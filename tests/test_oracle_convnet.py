@@ -184,6 +184,11 @@ def test_warm_start_is_linear_and_zero_mean():
     assert np.abs(u1 - ref).max() < 1e-14
 
 
+def test_shared_generator_describes_the_oracle_architecture():
+    from synth.netinit import NET_HEAD_IN, NET_LAYERS, NET_OUT
+    assert NET_LAYERS == cn.LAYERS and NET_OUT == cn.NOUT and NET_HEAD_IN == cn.HEAD_IN
+
+
 def test_param_count():
     p = cn.init_params(0)
     assert p.size == cn.param_count()
