@@ -148,8 +148,9 @@ def warm_start_comparison(ntrain: int, neval: int, steps: int, batch: int = 8, n
     batched workload's kind (vf ~ U[0.1,0.4], contrast ~ U[10,1000]) solved
     for the 6 unit strains to 1e-6 (FP32-refined batched solves) give the
     training targets; the network is trained on the GPU (Adam, `steps`
-    minibatches of `batch`, learning rate 5e-4 -> 1.7e-4 -> 5e-5, global-norm
-    clip 1); `neval` further seeded microstructures are then solved to 1e-6
+    minibatches of `batch`, learning rate 3e-4 -> 1e-4 -> 3e-5, global-norm
+    clip 0.01, about twice the gradient norm at initialisation); `neval`
+    further seeded microstructures are then solved to 1e-6
     from zero and from the network's guess (FP64 and FP32-refined), and PCG
     iterations and wall times are compared."""
     import numpy as np
@@ -192,9 +193,9 @@ def warm_start_comparison(ntrain: int, neval: int, steps: int, batch: int = 8, n
     net.set_timing(True)
     t0 = time.perf_counter()
     losses = []
-    for a, b, lr in ((0.0, 0.6, 5e-4), (0.6, 0.85, 5e-4 / 3), (0.85, 1.0, 5e-5)):
+    for a, b, lr in ((0.0, 0.6, 3e-4), (0.6, 0.85, 1e-4), (0.85, 1.0, 3e-5)):
         losses.append(net.train(phase, gamma[:ntrain], target, order[int(a * steps):int(b * steps)],
-                                batch, lr=lr, clip=1.0))
+                                batch, lr=lr, clip=0.01))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     losses = np.concatenate(losses)

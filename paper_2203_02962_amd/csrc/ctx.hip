@@ -753,7 +753,7 @@ int pcg_run(fh_ctx* c, int nload, const PcgBufs<T>& bf, double eta, int itmax, i
   HIPCHK(c, fh::launch_xinv<T>(g, c->px, c->twx, fh::XI_INIT_P, bf.A, S, nullptr, nullptr, bf.p,
                                F, nload, L.st, c->stream));
   HIPCHK(c, fh::launch_finalize_init(L.st, L.rz_part, nbz, nload, c->stream));
-  const int nbk = fh::kop_nblocks(g, hex_elastic(c));
+  const int nbk = fh::kop_nblocks(g, hex_elastic(c), (int)sizeof(T));
   auto one_iteration = [&]() -> int {
       int rc = 0;
       KT(FH_K_OPERATOR, rc = apply_KT(c, bf.p, bf.q, nload, F, L.st, L.pq_part));

@@ -97,6 +97,23 @@ __device__ __forceinline__ void dft_small(cplx<T>* x, int s) {
   }
 }
 
+// In FP64 LDS lines, element e sits at sw<T>(e) = e + e/8 (one pad slot after
+// every 8 complex values), so the power-of-two strides of the early Stockham
+// writes (8 or 64 elements apart) spread over all banks; lines are
+// lds_stride<T>(n) apart, an odd count, so accesses to the same element of
+// consecutive lines (the transposed loads and stores of the passes) fall into
+// different banks too.
+// FP32 lines (8-byte complex values) keep the plain layout, stride n + 1,
+// which measured faster for them.
+template <typename T>
+__host__ __device__ __forceinline__ int sw(int e) {
+  return sizeof(T) == 8 ? e + (e >> 3) : e;
+}
+template <typename T>
+__host__ __device__ __forceinline__ int lds_stride(int n) {
+  return sizeof(T) == 8 ? ((n + (n >> 3) + 1) | 1) : n + 1;
+}
+
 // One in-place Stockham stage on `nlines` lines of length n (line stride n):
 // every thread first reads its butterflies' inputs into registers, the
 // block synchronises, then the results are written back.  L = product of the
@@ -112,7 +129,7 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int n, int ls, int 
   const int items = nlines * m;
   const int twstep = n / (L * R);
   cplx<T> v[MAXIT][R];
-  int dst[MAXIT];
+  int dst[MAXIT], de[MAXIT];
 #pragma unroll
   for (int k = 0; k < MAXIT; ++k) {
     const int it = threadIdx.x + k * kThreads;
@@ -124,7 +141,7 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int n, int ls, int 
       const cplx<T>* src = buf + line * ls;
 #pragma unroll
       for (int t = 0; t < R; ++t) {
-        cplx<T> a = src[j + t * m];
+        cplx<T> a = src[sw<T>(j + t * m)];
         if (t > 0) {
           // t*kk < R*L, so the index stays below n
           cplx<T> w = tw[t * kk * twstep];
@@ -133,7 +150,8 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int n, int ls, int 
         }
         v[k][t] = a;
       }
-      dst[k] = line * ls + (j / L) * L * R + kk;
+      dst[k] = line * ls;
+      de[k] = (j / L) * L * R + kk;
     }
   }
   __syncthreads();
@@ -142,7 +160,7 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int n, int ls, int 
     if (dst[k] >= 0) {
       dft_small<T, R>(v[k], sign);
 #pragma unroll
-      for (int t = 0; t < R; ++t) buf[dst[k] + t * L] = v[k][t];
+      for (int t = 0; t < R; ++t) buf[dst[k] + sw<T>(de[k] + t * L)] = v[k][t];
     }
   }
   __syncthreads();
@@ -152,16 +170,12 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int n, int ls, int 
 // returns `a` after a final barrier.
 // P3: the length has a factor 3 (radix-3 stages compiled in).  Lengths are
 // products of 2 and 3 only.
-// Lines are stored with stride ls = n + 1 complex values in LDS, so that
-// accesses to the same index of consecutive lines (the transposed loads and
-// stores of the passes) fall into different banks.
-__host__ __device__ __forceinline__ int lds_stride(int n) { return n + 1; }
 
 template <typename T, bool P3>
 __device__ cplx<T>* fft_lines(cplx<T>* a, const AxisPlan& plan, int nlines, const cplx<T>* tw,
                               int sign) {
   int L = 1;
-  const int n = plan.n, ls = lds_stride(n);
+  const int n = plan.n, ls = lds_stride<T>(n);
   for (int st = 0; st < plan.nstage; ++st) {
     const int R = (plan.code >> (4 * st)) & 15u;
     if (R == 8) stockham_stage<T, 8>(a, n, ls, nlines, L, tw, sign);
@@ -213,7 +227,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(Grid g, AxisPlan px, const cp
   const int y0 = blockIdx.x * kRows, z = blockIdx.y;
   const long long rbase = (long long)ld * rstride + ((long long)c * g.nz + z) * ny * nx;
   const T alpha = (mode == XF_UPDATE_R) ? T(st[ld].alpha) : T(0);
-  const int lsx = lds_stride(nx);
+  const int lsx = lds_stride<T>(nx);
   for (int idx = threadIdx.x; idx < kRows * nx; idx += blockDim.x) {
     const int row = idx / nx, x = idx - row * nx, y = y0 + row;
     T v = T(0);
@@ -226,7 +240,7 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(Grid g, AxisPlan px, const cp
         r[o] = v;
       }
     }
-    cplx<T>& d = a[(row >> 1) * lsx + x];
+    cplx<T>& d = a[(row >> 1) * lsx + sw<T>(x)];
     if (row & 1) d.im = v; else d.re = v;
   }
   __syncthreads();
@@ -236,8 +250,8 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(Grid g, AxisPlan px, const cp
     const int yl = idx % kRows, kx = idx / kRows, y = y0 + yl;
     if (y >= ny) continue;
     const cplx<T>* line = res + (yl >> 1) * lsx;
-    const cplx<T> ck = line[kx];
-    const cplx<T> cn = line[(nx - kx) % nx];
+    const cplx<T> ck = line[sw<T>(kx)];
+    const cplx<T> cn = line[sw<T>((nx - kx) % nx)];
     cplx<T> X;
     if ((yl & 1) == 0) {
       X = {T(0.5) * (ck.re + cn.re), T(0.5) * (ck.im - cn.im)};
@@ -265,19 +279,19 @@ __global__ void __launch_bounds__(kThreads) k_yfwd(Grid g, AxisPlan py, const cp
   load_twiddles(tw, twy, ny);
   const int z0 = blockIdx.x * zb, kx = blockIdx.y;
   const long long base = (long long)ld * sstride;
-  const int ls = lds_stride(ny);
+  const int ls = lds_stride<T>(ny);
   for (int idx = threadIdx.x; idx < zb * ny; idx += blockDim.x) {
     const int zl = idx / ny, y = idx - zl * ny, z = z0 + zl;
     cplx<T> v = {T(0), T(0)};
     if (z < nz) v = A[base + (((long long)c * nz + z) * nxh + kx) * ny + y];
-    a[zl * ls + y] = v;
+    a[zl * ls + sw<T>(y)] = v;
   }
   __syncthreads();
   cplx<T>* res = fft_lines<T, P3>(a, py, zb, tw, -1);
   const long long obase = base + ((long long)c * nxh + kx) * (long long)ny * nz;
   for (int idx = threadIdx.x; idx < zb * ny; idx += blockDim.x) {
     const int zl = idx % zb, ky = idx / zb, z = z0 + zl;
-    if (z < nz) B[obase + (long long)ky * nz + z] = res[zl * ls + ky];
+    if (z < nz) B[obase + (long long)ky * nz + z] = res[zl * ls + sw<T>(ky)];
   }
 }
 
@@ -288,7 +302,18 @@ __global__ void __launch_bounds__(kThreads) k_zpass(Grid g, AxisPlan pz, const c
                                                    int mode, int kyb, cplx<T>* B,
                                                    long long sstride, const T* kplus,
                                                    const PcgState* st, double* rz_part) {
-  const int ld = blockIdx.z;
+  // Workgroups go round-robin to the 8 XCDs.  Renumber them so that the load
+  // cases of one group of lines run back to back on the same XCD: K^+ of
+  // those lines then comes from HBM once and from that XCD's L2 after.
+  // The grid is (line groups rounded up to a multiple of 8, 1, loads);
+  // padding blocks exit at once.
+  const int gx = (g.ny + kyb - 1) / kyb, lg_n = gx * g.nxh;
+  const int b = blockIdx.x + gridDim.x * blockIdx.z;
+  const int k = b >> 3;
+  const int ld = k % gridDim.z;
+  const int lg = (k / gridDim.z) * 8 + (b & 7);
+  if (lg >= lg_n) return;
+  const int bx = lg % gx, by = lg / gx;
   __shared__ double red[16];
   const int active = load_status(st, ld) == ST_ACTIVE;
   if (!active) return;
@@ -297,19 +322,19 @@ __global__ void __launch_bounds__(kThreads) k_zpass(Grid g, AxisPlan pz, const c
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* a = tw + nz;
   load_twiddles(tw, twz, nz);
-  const int ky0 = blockIdx.x * kyb, kx = blockIdx.y;
+  const int ky0 = bx * kyb, kx = by;
   if (kplus) kplus += (ld / g.G) * g.kplus_stride;
   const long long cstride = (long long)nxh * ny * nz;
   const long long base = (long long)ld * sstride + (long long)kx * ny * nz;
   const int per = kyb * nz;
-  const int ls = lds_stride(nz);
+  const int ls = lds_stride<T>(nz);
   const int cls = kyb * ls;  // LDS stride between components
   for (int idx = threadIdx.x; idx < nd * per; idx += blockDim.x) {
     const int c = idx / per, rem = idx - c * per, kyl = rem / nz, z = rem - kyl * nz;
     const int ky = ky0 + kyl;
     cplx<T> v = {T(0), T(0)};
     if (ky < ny) v = B[base + c * cstride + (long long)ky * nz + z];
-    a[c * cls + kyl * ls + z] = v;
+    a[c * cls + kyl * ls + sw<T>(z)] = v;
   }
   __syncthreads();
   cplx<T>* res = fft_lines<T, P3>(a, pz, nd * kyb, tw, -1);
@@ -320,7 +345,7 @@ __global__ void __launch_bounds__(kThreads) k_zpass(Grid g, AxisPlan pz, const c
     for (int idx0 = threadIdx.x; idx0 < per; idx0 += blockDim.x) {
       const int kyl = idx0 / nz, kz = idx0 - kyl * nz, ky = ky0 + kyl;
       if (ky >= ny) continue;
-      const int idx = kyl * ls + kz;
+      const int idx = kyl * ls + sw<T>(kz);
       const long long f = ((long long)kx * ny + ky) * nz + kz;
       if (nd == 3) {
         const T k00 = kplus[f], k11 = kplus[nfreq + f], k22 = kplus[2 * nfreq + f];
@@ -362,13 +387,12 @@ __global__ void __launch_bounds__(kThreads) k_zpass(Grid g, AxisPlan pz, const c
   for (int idx = threadIdx.x; idx < nd * per; idx += blockDim.x) {
     const int c = idx / per, rem = idx - c * per, kyl = rem / nz, z = rem - kyl * nz;
     const int ky = ky0 + kyl;
-    if (ky < ny) B[base + c * cstride + (long long)ky * nz + z] = res[c * cls + kyl * ls + z];
+    if (ky < ny) B[base + c * cstride + (long long)ky * nz + z] = res[c * cls + kyl * ls + sw<T>(z)];
   }
   if (mode == Z_SOLVE && rz_part) {
     const double s = block_sum(part, red);
     if (threadIdx.x == 0) {
-      const long long nb = (long long)gridDim.x * gridDim.y;
-      rz_part[(long long)ld * nb + (long long)blockIdx.y * gridDim.x + blockIdx.x] = s;
+      rz_part[(long long)ld * lg_n + lg] = s;
     }
   }
 }
@@ -388,18 +412,18 @@ __global__ void __launch_bounds__(kThreads) k_yinv(Grid g, AxisPlan py, const cp
   const int z0 = blockIdx.x * zb, kx = blockIdx.y;
   const long long base = (long long)ld * sstride;
   const long long ibase = base + ((long long)c * nxh + kx) * (long long)ny * nz;
-  const int ls = lds_stride(ny);
+  const int ls = lds_stride<T>(ny);
   for (int idx = threadIdx.x; idx < zb * ny; idx += blockDim.x) {
     const int zl = idx % zb, ky = idx / zb, z = z0 + zl;
     cplx<T> v = {T(0), T(0)};
     if (z < nz) v = B[ibase + (long long)ky * nz + z];
-    a[zl * ls + ky] = v;
+    a[zl * ls + sw<T>(ky)] = v;
   }
   __syncthreads();
   cplx<T>* res = fft_lines<T, P3>(a, py, zb, tw, +1);
   for (int idx = threadIdx.x; idx < zb * ny; idx += blockDim.x) {
     const int zl = idx / ny, y = idx - zl * ny, z = z0 + zl;
-    if (z < nz) A[base + (((long long)c * nz + z) * nxh + kx) * ny + y] = res[zl * ls + y];
+    if (z < nz) A[base + (((long long)c * nz + z) * nxh + kx) * ny + y] = res[zl * ls + sw<T>(y)];
   }
 }
 
@@ -429,7 +453,7 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
   if (status != ST_ACTIVE) return;
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
-  const int lsx = lds_stride(nx);
+  const int lsx = lds_stride<T>(nx);
   cplx<T>* a = tw + nx;
   cplx<T>* S = a + (kRows / 2) * lsx;  // 16 x nxh raw tile, row stride nxh + 1
   load_twiddles(tw, twx, nx);
@@ -456,7 +480,7 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
       xa = conjg(S[(2 * j) * (nxh + 1) + (nx - k)]);
       xb = conjg(S[(2 * j + 1) * (nxh + 1) + (nx - k)]);
     }
-    a[j * lsx + k] = {xa.re - xb.im, xa.im + xb.re};
+    a[j * lsx + sw<T>(k)] = {xa.re - xb.im, xa.im + xb.re};
   }
   __syncthreads();
   cplx<T>* res = fft_lines<T, P3>(a, px, kRows / 2, tw, +1);
@@ -465,7 +489,7 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
   for (int idx = threadIdx.x; idx < kRows * nx; idx += blockDim.x) {
     const int row = idx / nx, xx = idx - row * nx, y = y0 + row;
     if (y >= ny) continue;
-    const cplx<T> v = res[(row >> 1) * lsx + xx];
+    const cplx<T> v = res[(row >> 1) * lsx + sw<T>(xx)];
     const T zv = (row & 1) ? v.im : v.re;
     const long long o = fbase + (long long)y * nx + xx;
     if (mode == XI_PLAIN) {
@@ -546,7 +570,7 @@ hipError_t launch_xfwd(const Grid& g, const AxisPlan& px, const cplx<double>* tw
                        long long sstride, int nload, const PcgState* st, hipStream_t s) {
   const bool P3K = px.n % 3 == 0;
   dim3 grid((g.ny + kRows - 1) / kRows, g.nz, nload * g.nd);
-  size_t lds = sizeof(cplx<T>) * (size_t)(g.nx + (kRows / 2) * lds_stride(g.nx));
+  size_t lds = sizeof(cplx<T>) * (size_t)(g.nx + (kRows / 2) * lds_stride<T>(g.nx));
   if (lds > 65536)
     hipFuncSetAttribute(P3K ? (const void*)k_xfwd<T, true> : (const void*)k_xfwd<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
@@ -574,7 +598,7 @@ hipError_t launch_yfwd(const Grid& g, const AxisPlan& py, const cplx<double>* tw
   const bool P3K = py.n % 3 == 0;
   const int zb = ypass_zb(g);
   dim3 grid((g.nz + zb - 1) / zb, g.nxh, nload * g.nd);
-  size_t lds = sizeof(cplx<T>) * (size_t)(g.ny + zb * lds_stride(g.ny));
+  size_t lds = sizeof(cplx<T>) * (size_t)(g.ny + zb * lds_stride<T>(g.ny));
   if (lds > 65536)
     hipFuncSetAttribute(P3K ? (const void*)k_yfwd<T, true> : (const void*)k_yfwd<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
@@ -609,9 +633,10 @@ hipError_t launch_zpass(const Grid& g, const AxisPlan& pz, const cplx<double>* t
                         const PcgState* st, double* rz_part, int* nblocks_out, hipStream_t s) {
   const bool P3K = pz.n % 3 == 0;
   const int kyb = zpass_kyb<T>(g);
-  dim3 grid((g.ny + kyb - 1) / kyb, g.nxh, nload);
-  if (nblocks_out) *nblocks_out = grid.x * grid.y;
-  size_t lds = sizeof(cplx<T>) * (size_t)(g.nz + g.nd * kyb * lds_stride(g.nz));
+  const int lg_n = ((g.ny + kyb - 1) / kyb) * g.nxh;
+  dim3 grid((lg_n + 7) / 8 * 8, 1, nload);
+  if (nblocks_out) *nblocks_out = lg_n;
+  size_t lds = sizeof(cplx<T>) * (size_t)(g.nz + g.nd * kyb * lds_stride<T>(g.nz));
   if (lds > 65536)
     hipFuncSetAttribute(P3K ? (const void*)k_zpass<T, true> : (const void*)k_zpass<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
@@ -631,7 +656,7 @@ hipError_t launch_yinv(const Grid& g, const AxisPlan& py, const cplx<double>* tw
   const bool P3K = py.n % 3 == 0;
   const int zb = ypass_zb(g);
   dim3 grid((g.nz + zb - 1) / zb, g.nxh, nload * g.nd);
-  size_t lds = sizeof(cplx<T>) * (size_t)(g.ny + zb * lds_stride(g.ny));
+  size_t lds = sizeof(cplx<T>) * (size_t)(g.ny + zb * lds_stride<T>(g.ny));
   if (lds > 65536)
     hipFuncSetAttribute(P3K ? (const void*)k_yinv<T, true> : (const void*)k_yinv<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
@@ -648,7 +673,7 @@ hipError_t launch_xinv(const Grid& g, const AxisPlan& px, const cplx<double>* tw
                        long long fstride, int nload, const PcgState* st, hipStream_t s) {
   const bool P3K = px.n % 3 == 0;
   dim3 grid((g.ny + kRows - 1) / kRows, g.nz, nload * g.nd);
-  size_t lds = sizeof(cplx<T>) * (size_t)(g.nx + (kRows / 2) * lds_stride(g.nx) +
+  size_t lds = sizeof(cplx<T>) * (size_t)(g.nx + (kRows / 2) * lds_stride<T>(g.nx) +
                                           kRows * (g.nxh + 1));
   if (lds > 65536)
     hipFuncSetAttribute(P3K ? (const void*)k_xinv<T, true> : (const void*)k_xinv<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,

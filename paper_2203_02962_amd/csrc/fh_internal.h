@@ -132,7 +132,8 @@ hipError_t launch_symbol(const Grid& g, const cplx<double>* spec, long long sstr
 hipError_t launch_cast_symbol(long long count, const double* src, float* dst, hipStream_t s);
 
 // Number of per-load partial sums the operator and z-pass launches write.
-int kop_nblocks(const Grid& g, bool hex_elastic);
+// (tbytes = sizeof of the field type: the default z chunk depends on it)
+int kop_nblocks(const Grid& g, bool hex_elastic, int tbytes = 8);
 template <typename T>
 int zpass_nblocks(const Grid& g);
 

@@ -463,11 +463,17 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
 
 constexpr int kHexTX = 32, kHexTY = 8;
 
-static int hex_kz(const Grid& g) { return g.kz > 0 ? g.kz : (g.nz >= 64 ? 16 : 8); }
+// z chunk per block.  Measured at 128^3 with 6 loads: FP64 kz 8 / 16 / 32
+// -> 547 / 504 / 480 us; FP32 is fastest at 16.
+static int hex_kz(const Grid& g, int tbytes) {
+  if (g.kz > 0) return g.kz;
+  if (tbytes == 8 && g.nz >= 128) return 32;
+  return g.nz >= 64 ? 16 : 8;
+}
 
-int kop_nblocks(const Grid& g, bool hex_elastic) {
+int kop_nblocks(const Grid& g, bool hex_elastic, int tbytes) {
   if (hex_elastic) {
-    const int kz = hex_kz(g);
+    const int kz = hex_kz(g, tbytes);
     const int ntiles = ((g.nx + kHexTX - 1) / kHexTX) * ((g.ny + kHexTY - 1) / kHexTY);
     return ntiles * ((g.nz + kz - 1) / kz);
   }
@@ -482,7 +488,7 @@ hipError_t launch_kop_hex8_elastic(const Grid& g, const T* u, T* q, const uint8_
                                    hipStream_t s) {
   constexpr int TX = kHexTX, TY = kHexTY;
   using Cfg = HexCfg<T, TX, TY>;
-  const int kz = hex_kz(g);
+  const int kz = hex_kz(g, (int)sizeof(T));
   const int ntiles = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
   dim3 grid(ntiles, (g.nz + kz - 1) / kz, nload);
   if (nblocks_out) *nblocks_out = grid.x * grid.y;
@@ -630,7 +636,7 @@ hipError_t launch_kop_hex8_iso(const Grid& g, const T* u, T* q, const uint8_t* p
                                hipStream_t s) {
   constexpr int TX = kHexTX, TY = kHexTY;
   using Cfg = HexCfg<T, TX, TY>;
-  const int kz = hex_kz(g);
+  const int kz = hex_kz(g, (int)sizeof(T));
   const int ntiles = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
   dim3 grid(ntiles, (g.nz + kz - 1) / kz, nload);
   if (nblocks_out) *nblocks_out = grid.x * grid.y;
