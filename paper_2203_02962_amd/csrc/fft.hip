@@ -196,6 +196,26 @@ __device__ __forceinline__ int load_status(const PcgState* st, int ld) {
   return st ? st[ld].status : ST_ACTIVE;
 }
 
+// for (idx = threadIdx.x; idx < n; idx += kThreads) store(idx, load(idx)),
+// with the global reads of CH consecutive trips issued before their LDS
+// writes: one memory round trip per CH trips instead of one per trip.
+template <int CH, typename V, typename Load, typename Store>
+__device__ __forceinline__ void staged_fill(int n, Load load, Store store) {
+  for (int base = threadIdx.x; base < n; base += CH * kThreads) {
+    V v[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      const int idx = base + k * kThreads;
+      if (idx < n) v[k] = load(idx);
+    }
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      const int idx = base + k * kThreads;
+      if (idx < n) store(idx, v[k]);
+    }
+  }
+}
+
 // Deterministic block sum (wave shuffles, then waves in order).
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -228,21 +248,27 @@ __global__ void __launch_bounds__(kThreads) k_xfwd(Grid g, AxisPlan px, const cp
   const long long rbase = (long long)ld * rstride + ((long long)c * g.nz + z) * ny * nx;
   const T alpha = (mode == XF_UPDATE_R) ? T(st[ld].alpha) : T(0);
   const int lsx = lds_stride<T>(nx);
-  for (int idx = threadIdx.x; idx < kRows * nx; idx += blockDim.x) {
-    const int row = idx / nx, x = idx - row * nx, y = y0 + row;
-    T v = T(0);
-    if (y < ny) {
-      const long long o = rbase + (long long)y * nx + x;
-      v = r[o];
-      if (mode == XF_UPDATE_R) {
-        v -= alpha * q[(long long)ld * qstride + ((long long)c * g.nz + z) * ny * nx +
-                       (long long)y * nx + x];
-        r[o] = v;
-      }
-    }
-    cplx<T>& d = a[(row >> 1) * lsx + sw<T>(x)];
-    if (row & 1) d.im = v; else d.re = v;
-  }
+  const T* qb = q ? q + (long long)ld * qstride + ((long long)c * g.nz + z) * ny * nx : nullptr;
+  staged_fill<8, T>(
+      kRows * nx,
+      [&](int idx) {
+        const int row = idx / nx, x = idx - row * nx, y = y0 + row;
+        T v = T(0);
+        if (y < ny) {
+          const long long o = rbase + (long long)y * nx + x;
+          v = r[o];
+          if (mode == XF_UPDATE_R) {
+            v -= alpha * qb[(long long)y * nx + x];
+            r[o] = v;
+          }
+        }
+        return v;
+      },
+      [&](int idx, T v) {
+        const int row = idx / nx, x = idx - row * nx;
+        cplx<T>& d = a[(row >> 1) * lsx + sw<T>(x)];
+        if (row & 1) d.im = v; else d.re = v;
+      });
   __syncthreads();
   cplx<T>* res = fft_lines<T, P3>(a, px, kRows / 2, tw, -1);
   const long long abase = (long long)ld * sstride + ((long long)c * g.nz + z) * nxh * ny;
@@ -280,12 +306,18 @@ __global__ void __launch_bounds__(kThreads) k_yfwd(Grid g, AxisPlan py, const cp
   const int z0 = blockIdx.x * zb, kx = blockIdx.y;
   const long long base = (long long)ld * sstride;
   const int ls = lds_stride<T>(ny);
-  for (int idx = threadIdx.x; idx < zb * ny; idx += blockDim.x) {
-    const int zl = idx / ny, y = idx - zl * ny, z = z0 + zl;
-    cplx<T> v = {T(0), T(0)};
-    if (z < nz) v = A[base + (((long long)c * nz + z) * nxh + kx) * ny + y];
-    a[zl * ls + sw<T>(y)] = v;
-  }
+  staged_fill<8, cplx<T>>(
+      zb * ny,
+      [&](int idx) {
+        const int zl = idx / ny, y = idx - zl * ny, z = z0 + zl;
+        cplx<T> v = {T(0), T(0)};
+        if (z < nz) v = A[base + (((long long)c * nz + z) * nxh + kx) * ny + y];
+        return v;
+      },
+      [&](int idx, cplx<T> v) {
+        const int zl = idx / ny, y = idx - zl * ny;
+        a[zl * ls + sw<T>(y)] = v;
+      });
   __syncthreads();
   cplx<T>* res = fft_lines<T, P3>(a, py, zb, tw, -1);
   const long long obase = base + ((long long)c * nxh + kx) * (long long)ny * nz;
@@ -329,13 +361,19 @@ __global__ void __launch_bounds__(kThreads) k_zpass(Grid g, AxisPlan pz, const c
   const int per = kyb * nz;
   const int ls = lds_stride<T>(nz);
   const int cls = kyb * ls;  // LDS stride between components
-  for (int idx = threadIdx.x; idx < nd * per; idx += blockDim.x) {
-    const int c = idx / per, rem = idx - c * per, kyl = rem / nz, z = rem - kyl * nz;
-    const int ky = ky0 + kyl;
-    cplx<T> v = {T(0), T(0)};
-    if (ky < ny) v = B[base + c * cstride + (long long)ky * nz + z];
-    a[c * cls + kyl * ls + sw<T>(z)] = v;
-  }
+  staged_fill<8, cplx<T>>(
+      nd * per,
+      [&](int idx) {
+        const int c = idx / per, rem = idx - c * per, kyl = rem / nz, z = rem - kyl * nz;
+        const int ky = ky0 + kyl;
+        cplx<T> v = {T(0), T(0)};
+        if (ky < ny) v = B[base + c * cstride + (long long)ky * nz + z];
+        return v;
+      },
+      [&](int idx, cplx<T> v) {
+        const int c = idx / per, rem = idx - c * per, kyl = rem / nz, z = rem - kyl * nz;
+        a[c * cls + kyl * ls + sw<T>(z)] = v;
+      });
   __syncthreads();
   cplx<T>* res = fft_lines<T, P3>(a, pz, nd * kyb, tw, -1);
   double part = 0.0;
@@ -413,12 +451,18 @@ __global__ void __launch_bounds__(kThreads) k_yinv(Grid g, AxisPlan py, const cp
   const long long base = (long long)ld * sstride;
   const long long ibase = base + ((long long)c * nxh + kx) * (long long)ny * nz;
   const int ls = lds_stride<T>(ny);
-  for (int idx = threadIdx.x; idx < zb * ny; idx += blockDim.x) {
-    const int zl = idx % zb, ky = idx / zb, z = z0 + zl;
-    cplx<T> v = {T(0), T(0)};
-    if (z < nz) v = B[ibase + (long long)ky * nz + z];
-    a[zl * ls + sw<T>(ky)] = v;
-  }
+  staged_fill<8, cplx<T>>(
+      zb * ny,
+      [&](int idx) {
+        const int zl = idx % zb, ky = idx / zb, z = z0 + zl;
+        cplx<T> v = {T(0), T(0)};
+        if (z < nz) v = B[ibase + (long long)ky * nz + z];
+        return v;
+      },
+      [&](int idx, cplx<T> v) {
+        const int zl = idx % zb, ky = idx / zb;
+        a[zl * ls + sw<T>(ky)] = v;
+      });
   __syncthreads();
   cplx<T>* res = fft_lines<T, P3>(a, py, zb, tw, +1);
   for (int idx = threadIdx.x; idx < zb * ny; idx += blockDim.x) {
@@ -458,12 +502,18 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
   cplx<T>* S = a + (kRows / 2) * lsx;  // 16 x nxh raw tile, row stride nxh + 1
   load_twiddles(tw, twx, nx);
   const long long abase = (long long)ld * sstride + ((long long)c * g.nz + z) * nxh * ny;
-  for (int idx = threadIdx.x; idx < kRows * nxh; idx += blockDim.x) {
-    const int yl = idx % kRows, kx = idx / kRows, y = y0 + yl;
-    cplx<T> v = {T(0), T(0)};
-    if (y < ny) v = A[abase + (long long)kx * ny + y];
-    S[yl * (nxh + 1) + kx] = v;
-  }
+  staged_fill<8, cplx<T>>(
+      kRows * nxh,
+      [&](int idx) {
+        const int yl = idx % kRows, kx = idx / kRows, y = y0 + yl;
+        cplx<T> v = {T(0), T(0)};
+        if (y < ny) v = A[abase + (long long)kx * ny + y];
+        return v;
+      },
+      [&](int idx, cplx<T> v) {
+        const int yl = idx % kRows, kx = idx / kRows;
+        S[yl * (nxh + 1) + kx] = v;
+      });
   __syncthreads();
   const int half = nx / 2;
   for (int idx = threadIdx.x; idx < (kRows / 2) * nx; idx += blockDim.x) {
@@ -486,20 +536,39 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
   cplx<T>* res = fft_lines<T, P3>(a, px, kRows / 2, tw, +1);
   const T alpha = (mode == XI_PCG) ? T(st[ld].alpha) : T(0);
   const T beta = (mode == XI_PCG) ? T(st[ld].beta) : T(0);
-  for (int idx = threadIdx.x; idx < kRows * nx; idx += blockDim.x) {
-    const int row = idx / nx, xx = idx - row * nx, y = y0 + row;
-    if (y >= ny) continue;
-    const cplx<T> v = res[(row >> 1) * lsx + sw<T>(xx)];
-    const T zv = (row & 1) ? v.im : v.re;
-    const long long o = fbase + (long long)y * nx + xx;
-    if (mode == XI_PLAIN) {
-      out[o] = zv;
-    } else if (mode == XI_INIT_P) {
-      p[o] = zv;
-    } else {
-      const T pv = p[o];
-      x[o] += alpha * pv;
-      p[o] = zv + beta * pv;
+  // PCG mode reads p and x: the reads of 8 trips are issued before their use
+  constexpr int CH = 8;
+  const int nout = kRows * nx;
+  for (int base = threadIdx.x; base < nout; base += CH * kThreads) {
+    T pv[CH], xv[CH];
+    if (mode == XI_PCG) {
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int idx = base + k * kThreads;
+        const int row = idx / nx, xx = idx - row * nx, y = y0 + row;
+        if (idx < nout && y < ny) {
+          const long long o = fbase + (long long)y * nx + xx;
+          pv[k] = p[o];
+          xv[k] = x[o];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      const int idx = base + k * kThreads;
+      const int row = idx / nx, xx = idx - row * nx, y = y0 + row;
+      if (idx >= nout || y >= ny) continue;
+      const cplx<T> v = res[(row >> 1) * lsx + sw<T>(xx)];
+      const T zv = (row & 1) ? v.im : v.re;
+      const long long o = fbase + (long long)y * nx + xx;
+      if (mode == XI_PLAIN) {
+        out[o] = zv;
+      } else if (mode == XI_INIT_P) {
+        p[o] = zv;
+      } else {
+        x[o] = xv[k] + alpha * pv[k];
+        p[o] = zv + beta * pv[k];
+      }
     }
   }
 }
