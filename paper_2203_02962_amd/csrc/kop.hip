@@ -281,7 +281,9 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
   __shared__ T force[12][NE];   // lower-face totals of the current slab
   __shared__ T carry[12][NE];   // upper-face forces of the previous slab (own slot)
   __shared__ double red[32];
-  __shared__ T lmt[2 * 256];
+  // per-phase {V lambda, 2 V mu}, sized by the launch (2 nphase_max)
+  extern __shared__ __align__(16) unsigned char kop_dyn[];
+  T* lmt = reinterpret_cast<T*>(kop_dyn);
   // Workgroups are dispatched round-robin over the 8 XCDs; renumber them so
   // that each XCD receives a contiguous range of tiles, whose halos then
   // meet in the same L2.
@@ -461,13 +463,16 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
   }
 }
 
-constexpr int kHexTX = 32, kHexTY = 8;
+// 16 x 8 output nodes per block (17 x 9 elements, 3 waves, about 38 KB of
+// LDS in FP64): four blocks fit a CU.  Measured at 128^3, 6 loads, FP64:
+// 32x8 480 us, 32x4 353 us, 16x4 363 us, 16x8 317 us per launch.
+constexpr int kHexTX = 16, kHexTY = 8;
 
-// z chunk per block.  Measured at 128^3 with 6 loads: FP64 kz 8 / 16 / 32
-// -> 547 / 504 / 480 us; FP32 is fastest at 16.
+// z chunk per block (16 x 8 tiles, 128^3, FP64: kz 16 / 32 / 64 -> 317 /
+// 320 / 338 us).
 static int hex_kz(const Grid& g, int tbytes) {
+  (void)tbytes;
   if (g.kz > 0) return g.kz;
-  if (tbytes == 8 && g.nz >= 128) return 32;
   return g.nz >= 64 ? 16 : 8;
 }
 
@@ -640,7 +645,8 @@ hipError_t launch_kop_hex8_iso(const Grid& g, const T* u, T* q, const uint8_t* p
   const int ntiles = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
   dim3 grid(ntiles, (g.nz + kz - 1) / kz, nload);
   if (nblocks_out) *nblocks_out = grid.x * grid.y;
-  hipLaunchKernelGGL((k_kop_hex8_iso<T, TX, TY>), grid, dim3(Cfg::NT), 0, s, g, kz, u, q, phase,
+  const size_t lds = sizeof(T) * 2 * (size_t)(g.nphase_max > 0 ? g.nphase_max : 1);
+  hipLaunchKernelGGL((k_kop_hex8_iso<T, TX, TY>), grid, dim3(Cfg::NT), lds, s, g, kz, u, q, phase,
                      lm, ustride, qstride, st, pq_part);
   return hipGetLastError();
 }
