@@ -297,3 +297,25 @@ def test_warm_start_flag_uses_network_guess(fh):
     assert st_a["iterations"] == st_b["iterations"]
     assert np.allclose(st_a["guess_res"], st_b["guess_res"], rtol=1e-12, atol=0)
     assert np.abs(a.get_homogenized() - b.get_homogenized()).max() == 0.0
+
+
+def test_warm_start_validation_and_recovery(fh):
+    """Requests the warm start cannot serve fail with a clear error and leave
+    the context usable for a zero start."""
+    from paper_2203_02962_amd.runner import setup_context
+    from tests.test_gpu_parity import _spheres_case
+    say("warm start validation")
+    wl, _ = _spheres_case(32, (2.5, 4.5), 50.0, 3)
+    c = setup_context(wl)
+    with pytest.raises(fh.FHError) as e:
+        c.solve(eta=1e-6, warm_start=True)          # no network attached
+    assert e.value.code == fh.FH_ESTATE
+    net = fh.Net(N64, 1)
+    net.set_params(_params(5).astype(np.float32))
+    c.set_warm_start(net)
+    with pytest.raises(fh.FHError) as e:
+        c.solve(eta=1e-6, warm_start=True)          # 32^3 grid, 64^3 network
+    assert e.value.code == fh.FH_EINVAL and "grid" in str(e.value)
+    rc, st = c.solve(eta=1e-6)                      # zero start still works
+    assert rc == 0 and st["guess_used"] == [0] * 6
+    c.set_warm_start(None)
