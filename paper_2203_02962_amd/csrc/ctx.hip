@@ -66,6 +66,12 @@ struct fh_ctx {
   size_t mat_dev_n = 0, ref_dev_n = 0, fe_dev_n = 0;
   // isotropic hex8 elasticity: {V lambda, 2 V mu} per phase (and for Cref)
   bool iso = false, ref_iso = false;
+  // scalar hex8 with isotropic conductivity: V k per phase (a field: {V})
+  bool sc = false, ref_sc = false;
+  double* sk_dev = nullptr;
+  float* sk_dev_f = nullptr;
+  double* ref_sk_dev = nullptr;
+  size_t sk_dev_n = 0, ref_sk_dev_n = 0;
   double* lm_dev = nullptr;
   float* lm_dev_f = nullptr;
   double* ref_lm_dev = nullptr;
@@ -325,11 +331,34 @@ bool cholesky_ok(const std::vector<double>& A, int m) {
 }
 
 bool hex_elastic(const fh_ctx* c) { return c->element == FH_HEX8 && c->problem == FH_ELASTIC; }
+bool hex_scalar(const fh_ctx* c) {
+  return c->element == FH_HEX8 && c->problem == FH_SCALAR && c->g.dim == 3;
+}
+// the material operator runs the tiled z-march kernels (elastic, or scalar
+// with isotropic conductivity): their partial-sum count differs
+bool hex_tiled(const fh_ctx* c) { return hex_elastic(c) || (hex_scalar(c) && c->sc); }
+// A = k I (d x d): returns k, or -1
+double isotropic_k(const double* A, int d) {
+  double mx = 0.0;
+  for (int i = 0; i < d * d; ++i) mx = std::max(mx, std::fabs(A[i]));
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) {
+      const double v = A[i * d + j];
+      if (i != j && std::fabs(v) > 1e-14 * mx) return -1.0;
+      if (i == j && std::fabs(v - A[0]) > 1e-14 * mx) return -1.0;
+    }
+  return A[0] > 0.0 ? A[0] : -1.0;
+}
 
 void free_tables(fh_ctx* c) {
   hipFree(c->lm_dev); c->lm_dev = nullptr;
   hipFree(c->lm_dev_f); c->lm_dev_f = nullptr;
   hipFree(c->ref_lm_dev); c->ref_lm_dev = nullptr;
+  hipFree(c->sk_dev); c->sk_dev = nullptr;
+  hipFree(c->sk_dev_f); c->sk_dev_f = nullptr;
+  hipFree(c->ref_sk_dev); c->ref_sk_dev = nullptr;
+  c->sk_dev_n = c->ref_sk_dev_n = 0;
+  c->sc = c->ref_sc = false;
   c->lm_dev_n = c->ref_lm_dev_n = 0;
   c->iso = c->ref_iso = false;
   hipFree(c->mat_dev); c->mat_dev = nullptr;
@@ -418,7 +447,7 @@ size_t layout(fh_ctx* c, char* base, fh_ctx::Layout* Lout) {
     fh::Grid gw = g;
     gw.kz = 4;
     gw.kyb = 1;
-    L.nb_kop = fh::kop_nblocks(gw, hex_elastic(c));
+    L.nb_kop = std::max(fh::kop_nblocks(gw, true), fh::kop_nblocks(gw, false));
     L.nb_z = fh::zpass_nblocks<double>(gw);
     L.nb_z32 = fh::zpass_nblocks<float>(gw);
   }
@@ -510,7 +539,11 @@ int apply_K(fh_ctx* c, bool ref, const double* u, double* q, int nload, long lon
   const double* kf = ref ? nullptr : (c->mat_kind == 2 ? c->kfield_dev : nullptr);
   const double* tab = ref ? c->ref_dev : c->mat_dev;
   int nb = 0;
-  if (hex_elastic(c) && (ref ? c->ref_iso : c->iso)) {
+  if (hex_scalar(c) && (ref ? c->ref_sc : c->sc)) {
+    HIPCHK(c, fh::launch_kop_hex8_scalar<double>(g, u, q, kf ? nullptr : (ph ? ph : c->L.phase0),
+                                                 kf, ref ? c->ref_sk_dev : c->sk_dev, nload,
+                                                 stride, stride, st, pq, &nb, c->stream));
+  } else if (hex_elastic(c) && (ref ? c->ref_iso : c->iso)) {
     const double* lm = ref ? c->ref_lm_dev : c->lm_dev;
     HIPCHK(c, fh::launch_kop_hex8_iso<double>(g, u, q, ph, lm, nload, stride, stride, st, pq,
                                               &nb, c->stream));
@@ -531,7 +564,11 @@ int apply_K32(fh_ctx* c, const float* u, float* q, int nload, long long stride,
   g.nphase_max = c->mat_kind == 1 ? c->nphase : 1;
   const uint8_t* ph = c->mat_kind == 1 ? c->phase_dev : nullptr;
   int nb = 0;
-  if (hex_elastic(c) && c->iso) {
+  if (hex_scalar(c) && c->sc) {
+    const float* kf = c->mat_kind == 2 ? c->L.kf32 : nullptr;
+    HIPCHK(c, fh::launch_kop_hex8_scalar<float>(g, u, q, kf ? nullptr : ph, kf, c->sk_dev_f,
+                                                nload, stride, stride, st, pq, &nb, c->stream));
+  } else if (hex_elastic(c) && c->iso) {
     HIPCHK(c, fh::launch_kop_hex8_iso<float>(g, u, q, ph, c->lm_dev_f, nload, stride, stride,
                                              st, pq, &nb, c->stream));
   } else if (hex_elastic(c)) {
@@ -629,6 +666,16 @@ int build_symbol(fh_ctx* c) {
       rc = upload(c, &c->ref_lm_dev, &c->ref_lm_dev_n, lm);
       if (rc) return rc;
       c->ref_iso = true;
+    }
+  }
+  c->ref_sc = false;
+  if (hex_scalar(c)) {
+    const double kr = isotropic_k(c->cref.data(), 3);
+    if (kr > 0.0) {
+      rc = upload(c, &c->ref_sk_dev, &c->ref_sk_dev_n,
+                  std::vector<double>{voxel_volume(c) * kr});
+      if (rc) return rc;
+      c->ref_sc = true;
     }
   }
   // Alg. 2: impulse responses of Kref, forward FFT, per-frequency inverse
@@ -753,7 +800,7 @@ int pcg_run(fh_ctx* c, int nload, const PcgBufs<T>& bf, double eta, int itmax, i
   HIPCHK(c, fh::launch_xinv<T>(g, c->px, c->twx, fh::XI_INIT_P, bf.A, S, nullptr, nullptr, bf.p,
                                F, nload, L.st, c->stream));
   HIPCHK(c, fh::launch_finalize_init(L.st, L.rz_part, nbz, nload, c->stream));
-  const int nbk = fh::kop_nblocks(g, hex_elastic(c), (int)sizeof(T));
+  const int nbk = fh::kop_nblocks(g, hex_tiled(c), (int)sizeof(T));
   auto one_iteration = [&]() -> int {
       int rc = 0;
       KT(FH_K_OPERATOR, rc = apply_KT(c, bf.p, bf.q, nload, F, L.st, L.pq_part));
@@ -1597,6 +1644,21 @@ int fh_set_phases(fh_ctx* c, const uint8_t* phase_dev, int nphase, const double*
   }
   rc = upload_f(c, &c->mat_dev_f, tab);
   if (rc) return rc;
+  c->sc = false;
+  if (hex_scalar(c)) {
+    std::vector<double> sk((size_t)nphase);
+    bool all = true;
+    for (int p = 0; p < nphase && all; ++p) {
+      const double k = isotropic_k(c->mat.data() + (size_t)p * 9, 3);
+      all = k > 0.0;
+      sk[p] = voxel_volume(c) * k;
+    }
+    if (all) {
+      if ((rc = upload(c, &c->sk_dev, &c->sk_dev_n, sk)) || (rc = upload_f(c, &c->sk_dev_f, sk)))
+        return rc;
+      c->sc = true;
+    }
+  }
   c->symbol_ok = c->rhs_ok = c->solved = false;
   return FH_OK;
 }
@@ -1619,6 +1681,13 @@ int fh_set_conductivity_field(fh_ctx* c, const double* k_dev) {
   if (rc) return rc;
   rc = upload_f(c, &c->mat_dev_f, tab);
   if (rc) return rc;
+  c->sc = false;
+  if (hex_scalar(c)) {
+    const std::vector<double> sk{voxel_volume(c)};
+    if ((rc = upload(c, &c->sk_dev, &c->sk_dev_n, sk)) || (rc = upload_f(c, &c->sk_dev_f, sk)))
+      return rc;
+    c->sc = true;
+  }
   c->symbol_ok = c->rhs_ok = c->solved = false;
   return FH_OK;
 }

@@ -85,6 +85,13 @@ hipError_t launch_kop_hex8_iso(const Grid& g, const T* u, T* q, const uint8_t* p
                                const T* lm, int nload, long long ustride, long long qstride,
                                const PcgState* st, double* pq_part, int* nblocks_out,
                                hipStream_t s);
+// scalar hex8 conduction, isotropic k per voxel: kk = sk[0] * kfield[e]
+// (field) or sk[phase[e]] (sk = V k per phase); g.nphase_max table entries.
+template <typename T>
+hipError_t launch_kop_hex8_scalar(const Grid& g, const T* u, T* q, const uint8_t* phase,
+                                  const T* kfield, const T* sk, int nload, long long ustride,
+                                  long long qstride, const PcgState* st, double* pq_part,
+                                  int* nblocks_out, hipStream_t s);
 // node-centric generic operator with per-phase element matrices (2D
 // elements, 3D scalar hex8): ke = nphase x (nc*nd)^2, or a unit element
 // matrix scaled by a per-voxel field kfield.

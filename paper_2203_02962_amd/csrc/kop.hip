@@ -463,6 +463,174 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
   }
 }
 
+// ------------------------------------------------- scalar hex8 kernel
+// q = K u for heat conduction with an isotropic conductivity k per voxel
+// (a per-voxel field, or a per-phase table): Sec. 3 with A = k I (App. A).
+// In the modal (mean/difference) basis of a voxel's 8 corner values the
+// 2x2x2 Gauss energy is diagonal: mode m with bit beta set carries the
+// gradient along beta, and the element force of mode m is the mode times
+// V k sum_beta c_M(m, beta) a_beta^2, with c_M = (1/12)^|M| and a_beta =
+// 2^-(2-|M|) / h_beta as in the isotropic elastic kernel (M = the other
+// difference bits of m).  Same z march as that kernel: node planes in LDS,
+// lower-face forces exchanged, upper-face forces carried to the next slab.
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 4)
+    k_kop_hex8_scalar(Grid g, int kz, const T* __restrict__ u, T* __restrict__ q,
+                      const uint8_t* __restrict__ phase, const T* __restrict__ kfield,
+                      const T* __restrict__ sk, long long ustride, long long qstride,
+                      const PcgState* st, double* pq_part) {
+  using Cfg = HexCfg<T, TX, TY>;
+  constexpr int EX = Cfg::EX, PX = Cfg::PX, NE = Cfg::NE, NP = Cfg::NP, NT = Cfg::NT;
+  constexpr int NPF = (NP + NT - 1) / NT;
+  __shared__ T plane[2][NP];
+  __shared__ T force[4][NE];
+  __shared__ T carry[4][NE];
+  __shared__ double red[32];
+  extern __shared__ __align__(16) unsigned char kop_dyn[];
+  T* skt = reinterpret_cast<T*>(kop_dyn);  // V k per phase (field: V)
+  int bt = blockIdx.x, bz = blockIdx.y, ld = blockIdx.z;
+  {
+    const int nb = gridDim.x * gridDim.y * gridDim.z;
+    if ((nb & 7) == 0) {
+      const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+      const int l = (b & 7) * (nb >> 3) + (b >> 3);
+      bt = l % gridDim.x;
+      bz = (l / gridDim.x) % gridDim.y;
+      ld = l / (gridDim.x * gridDim.y);
+    }
+  }
+  if (st && st[ld].status != ST_ACTIVE) return;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int ntx = (nx + TX - 1) / TX;
+  const int x0 = (bt % ntx) * TX, y0 = (bt / ntx) * TY;
+  const int z0 = bz * kz;
+  const int z1 = min(z0 + kz, nz);
+  const T* __restrict__ ub = u + (long long)ld * ustride;
+  T* __restrict__ qb = q + (long long)ld * qstride;
+  const int tid = threadIdx.x;
+  const bool is_elem = tid < NE;
+  const int ei = tid % EX, ej = tid / EX;
+  const int ex = wrapi(x0 - 1 + ei, nx), ey = wrapi(y0 - 1 + ej, ny);
+  // modal factors: d[m] = sum over the difference bits beta of m of
+  // c_M(m, beta) a_beta^2 (mode 0, the mean, carries no gradient)
+  T d[8];
+  {
+    const T ih[3] = {T(1.0 / g.h[0]), T(1.0 / g.h[1]), T(1.0 / g.h[2])};
+    d[0] = T(0);
+#pragma unroll
+    for (int m = 1; m < 8; ++m) {
+      const int nbits = (m & 1) + ((m >> 1) & 1) + ((m >> 2) & 1);
+      const int mo = nbits - 1;  // |M| for every beta of m
+      const T cm = mo == 0 ? T(1) : (mo == 1 ? T(1.0 / 12.0) : T(1.0 / 144.0));
+      const T sc = mo == 0 ? T(0.25) : (mo == 1 ? T(0.5) : T(1));
+      T acc = T(0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        if (m & (1 << b)) acc += cm * (sc * ih[b]) * (sc * ih[b]);
+      d[m] = acc;
+    }
+  }
+  int poff[NPF];
+#pragma unroll
+  for (int k = 0; k < NPF; ++k) {
+    const int idx = tid + k * NT;
+    const int a = idx % PX, b = idx / PX;
+    poff[k] = idx < NP ? wrapi(y0 - 1 + b, ny) * nx + wrapi(x0 - 1 + a, nx) : -1;
+  }
+  T pf[NPF];
+  auto fetch = [&](int zp) {
+    const long long zb = (long long)wrapi(zp, nz) * ny * nx;
+#pragma unroll
+    for (int k = 0; k < NPF; ++k)
+      if (poff[k] >= 0) pf[k] = ub[zb + poff[k]];
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int k = 0; k < NPF; ++k)
+      if (poff[k] >= 0) plane[buf][tid + k * NT] = pf[k];
+  };
+  for (int i = tid; i < g.nphase_max; i += NT) skt[i] = sk[i];
+  const long long ecol = (long long)ey * nx + ex;
+  // coefficient of this thread's voxel column, one slab ahead
+  auto coef_src = [&](int zs) -> T {
+    const long long e = (long long)wrapi(zs, nz) * ny * nx + ecol;
+    return kfield ? kfield[e] : T(phase[e]);
+  };
+  T c_next = is_elem ? coef_src(z0 - 1) : T(0);
+  double dot = 0.0;
+  fetch(z0 - 1);
+  store(0);
+  fetch(z0);
+  store(1);
+  if (z0 + 1 <= z1) fetch(z0 + 1);
+  const int nsteps = z1 - z0 + 1;
+  for (int s = 0; s < nsteps; ++s) {
+    const int zs = z0 - 1 + s;
+    const int blo = s & 1, bhi = blo ^ 1;
+    const T csrc = c_next;
+    if (is_elem && s + 1 < nsteps) c_next = coef_src(zs + 1);
+    const int ox = tid % TX, oy = tid / TX;
+    const bool out_ok = s > 0 && tid < TX * TY && x0 + ox < nx && y0 + oy < ny;
+    const long long o = ((long long)zs * ny + (y0 + oy)) * nx + (x0 + ox);
+    __syncthreads();
+    if (is_elem) {
+      const T kk = kfield ? skt[0] * csrc : skt[(int)csrc];
+      T w[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int idx = (ej + ((a >> 1) & 1)) * PX + (ei + (a & 1));
+        w[a] = plane[(a >> 2) ? bhi : blo][idx];
+      }
+#pragma unroll
+      for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          if (a & bit) continue;
+          const T u0 = w[a], u1 = w[a | bit];
+          w[a] = u0 + u1;
+          w[a | bit] = u1 - u0;
+        }
+      T f[8];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) f[a] = kk * d[a] * w[a];
+#pragma unroll
+      for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          if (a & bit) continue;
+          const T fm = f[a], fd = f[a | bit];
+          f[a] = fm - fd;
+          f[a | bit] = fm + fd;
+        }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (s > 0) force[k][tid] = f[k] + carry[k][tid];
+        carry[k][tid] = f[k + 4];
+      }
+    }
+    T pd = T(0);
+    if (out_ok) pd = plane[blo][(oy + 1) * PX + (ox + 1)];
+    __syncthreads();
+    if (zs + 2 <= z1) {
+      store(blo);
+      if (zs + 3 <= z1) fetch(zs + 3);
+    }
+    if (out_ok) {
+      const int e00 = oy * EX + ox;
+      const T v = force[3][e00] + force[2][e00 + 1] + force[1][e00 + EX] + force[0][e00 + EX + 1];
+      qb[o] = v;
+      dot += (double)pd * (double)v;
+    }
+  }
+  if (pq_part) {
+    const double tot = block_sum_k(dot, red);
+    if (tid == 0) {
+      const long long nb = (long long)gridDim.x * gridDim.y;
+      pq_part[(long long)ld * nb + (long long)bz * gridDim.x + bt] = tot;
+    }
+  }
+}
+
 // 16 x 8 output nodes per block (17 x 9 elements, 3 waves, about 38 KB of
 // LDS in FP64): four blocks fit a CU.  Measured at 128^3, 6 loads, FP64:
 // 32x8 480 us, 32x4 353 us, 16x4 363 us, 16x8 317 us per launch.
@@ -650,6 +818,30 @@ hipError_t launch_kop_hex8_iso(const Grid& g, const T* u, T* q, const uint8_t* p
                      lm, ustride, qstride, st, pq_part);
   return hipGetLastError();
 }
+template <typename T>
+hipError_t launch_kop_hex8_scalar(const Grid& g, const T* u, T* q, const uint8_t* phase,
+                                  const T* kfield, const T* sk, int nload, long long ustride,
+                                  long long qstride, const PcgState* st, double* pq_part,
+                                  int* nblocks_out, hipStream_t s) {
+  constexpr int TX = kHexTX, TY = kHexTY;
+  const int kz = hex_kz(g, (int)sizeof(T));
+  const int ntiles = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
+  dim3 grid(ntiles, (g.nz + kz - 1) / kz, nload);
+  if (nblocks_out) *nblocks_out = grid.x * grid.y;
+  const size_t lds = sizeof(T) * (size_t)(g.nphase_max > 0 ? g.nphase_max : 1);
+  hipLaunchKernelGGL((k_kop_hex8_scalar<T, TX, TY>), grid, dim3(HexCfg<T, TX, TY>::NT), lds, s,
+                     g, kz, u, q, phase, kfield, sk, ustride, qstride, st, pq_part);
+  return hipGetLastError();
+}
+template hipError_t launch_kop_hex8_scalar<double>(const Grid&, const double*, double*,
+                                                   const uint8_t*, const double*, const double*,
+                                                   int, long long, long long, const PcgState*,
+                                                   double*, int*, hipStream_t);
+template hipError_t launch_kop_hex8_scalar<float>(const Grid&, const float*, float*,
+                                                  const uint8_t*, const float*, const float*, int,
+                                                  long long, long long, const PcgState*, double*,
+                                                  int*, hipStream_t);
+
 template hipError_t launch_kop_hex8_iso<double>(const Grid&, const double*, double*,
                                                 const uint8_t*, const double*, int, long long,
                                                 long long, const PcgState*, double*, int*,

@@ -42,7 +42,10 @@ def _case(elem, problem, n, nphase=3, kind="phase", seed=0, l=None):
               loads=np.eye(m), l=l)
     if kind in ("phase", "iso"):
         wl["phase"] = rng.integers(0, nphase, size=n[::-1]).astype(np.uint8)
-        if kind == "iso":
+        if kind == "iso" and problem == "scalar":
+            wl["mat"] = np.stack([isotropic_conductivity(1.0 + 20 * p, dim)
+                                  for p in range(nphase)])
+        elif kind == "iso":
             wl["mat"] = np.stack([isotropic_mandel(1.0 + 20 * p, 0.2 + 0.1 * p, dim)
                                   for p in range(nphase)])
         else:
@@ -63,6 +66,9 @@ CASES = [
     ("hex8", "elastic", (4, 2, 2), "iso", None),
     ("hex8", "scalar", (12, 18, 6), "phase", None),
     ("hex8", "scalar", (12, 18, 6), "field", (0.5, 1.0, 1.5)),
+    ("hex8", "scalar", (12, 18, 6), "iso", (1.0, 0.8, 1.2)),
+    ("hex8", "scalar", (24, 12, 18), "iso", None),
+    ("hex8", "scalar", (36, 18, 24), "field", None),
     ("tri2", "scalar", (12, 18), "phase", None),
     ("tri2", "elastic", (12, 6), "phase", None),
     ("quad4", "elastic", (12, 8), "phase", (1.0, 0.7)),
