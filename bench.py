@@ -143,6 +143,42 @@ def batch_comparison(count: int):
 MFMA_BF16_PEAK_TFS = 2500.0
 
 
+def conduction_comparison():
+    """256^3 heat conduction, k = exp of a periodic Gaussian random field
+    (correlation length 8 voxels, sigma 1.5, contrast clipped to 1e3), 3 unit
+    gradients: FP64 PCG vs FP32 operator/FFT inside FP64 refinement, both to
+    1e-8 (setup included, second of two solves timed)."""
+    import numpy as np
+    import torch
+
+    from paper_2203_02962_amd import fh
+    from paper_2203_02962_amd.runner import setup_context
+    from synth import workload
+
+    wl = workload("conduction3d_grf", seed=0)
+    c = setup_context(wl)
+    out = {}
+    H = {}
+    for prec, name in ((fh.FH_FP64, "fp64"), (fh.FH_FP32_REFINED, "fp32_refined")):
+        c.solve(eta=1e-8, precision=prec, rebuild=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = c.solve(eta=1e-8, precision=prec, rebuild=True)
+        torch.cuda.synchronize()
+        H[name] = c.get_homogenized()
+        out[name] = {"ms": round((time.perf_counter() - t0) * 1000.0, 1), "rc": rc,
+                     "iterations": st["iterations"], "sweeps": st["outer"],
+                     "dof_iter_per_s": st["dof"] * sum(st["iterations"]) /
+                     ((time.perf_counter() - t0))}
+    c.close()
+    out["chom_rel_diff"] = float(np.abs(H["fp32_refined"] - H["fp64"]).max() /
+                                 np.abs(H["fp64"]).max())
+    out["speedup"] = round(out["fp64"]["ms"] / out["fp32_refined"]["ms"], 3)
+    out["workload"] = ("conduction3d_grf 256^3, trilinear hex 8 Gauss points, k = exp(GRF), "
+                       "ell 8, sigma 1.5, contrast <= 1e3, 3 unit gradients, eta 1e-8")
+    return out
+
+
 def warm_start_comparison(ntrain: int, neval: int, steps: int, batch: int = 8, n: int = 64):
     """Learned warm start at n^3: `ntrain` seeded microstructures of the
     batched workload's kind (vf ~ U[0.1,0.4], contrast ~ U[10,1000]) solved
@@ -265,6 +301,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 96-microstructure batched comparison")
     ap.add_argument("--batch-count", type=int, default=96)
+    ap.add_argument("--no-conduction", action="store_true",
+                    help="skip the 256^3 conduction FP64 vs FP32-refined comparison")
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the learned warm-start training and comparison")
     ap.add_argument("--warm-train", type=int, default=2000)
@@ -413,6 +451,9 @@ def main():
     }
     if not args.no_batch:
         out["config"]["batched_vs_plain_1e-6"] = batch_comparison(args.batch_count)
+    if not args.no_conduction:
+        print("[bench] conduction 256^3 ...", file=sys.stderr, flush=True)
+        out["config"]["conduction_256_fp64_vs_refined_1e-8"] = conduction_comparison()
     if not args.no_warm:
         out["config"]["warm_start_vs_zero_1e-6"] = warm_start_comparison(
             args.warm_train, args.warm_eval, args.warm_steps)
