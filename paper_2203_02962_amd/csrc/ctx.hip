@@ -26,6 +26,9 @@
 
 using fh::cplx;
 
+// chunks of the load-pair dot products behind C_hom
+constexpr int kPairChunks = 256;
+
 struct fh_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -95,6 +98,7 @@ struct fh_ctx {
     fh::PcgState* st;
     double *pq_part, *rz_part, *hist, *dot_part, *scal;
     double *sysdot, *sysdot_part;  // one dot per system (refinement norms)
+    double* pair_part;             // load-pair dot partials + results (C_hom)
     int* mask;                     // per-system flags
     uint8_t* phase0;
     int nb_kop, nb_z, nb_z32, hist_len;
@@ -460,6 +464,7 @@ size_t layout(fh_ctx* c, char* base, fh_ctx::Layout* Lout) {
   L.scal = (double*)take(sizeof(double) * 64);
   L.sysdot = (double*)take(sizeof(double) * nl);
   L.sysdot_part = (double*)take(sizeof(double) * nl * 64);
+  L.pair_part = (double*)take(sizeof(double) * (kPairChunks * 64 + 128));
   L.mask = (int*)take(sizeof(int) * nl);
   L.phase0 = (uint8_t*)take((size_t)g.N);
   L.bytes = off;
@@ -1802,25 +1807,40 @@ int fh_solve(fh_ctx* c, const fh_opts* opt, fh_stats* st) {
   rc = apply_K(c, false, c->L.x, c->L.q, nl, F, nullptr, nullptr);
   if (rc) return rc;
   std::vector<double> bu((size_t)nl * nl), uKu((size_t)nl * nl);
-  double* scal = c->L.scal;
-  const int nb = 1024;
-  std::vector<double> vals;
-  for (int i = 0; i < nl; ++i)
-    for (int j = 0; j < nl; ++j) {
-      HIPCHK(c, fh::launch_dot_partials(c->L.b + i * F, c->L.x + j * F, F, c->L.dot_part, nb,
-                                        c->stream));
-      HIPCHK(c, fh::launch_sum_partials(c->L.dot_part, nb, scal, c->stream));
-      double v = 0;
-      HIPCHK(c, hipMemcpyAsync(&v, scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(c, fh::launch_dot_partials(c->L.x + i * F, c->L.q + j * F, F, c->L.dot_part, nb,
-                                        c->stream));
-      HIPCHK(c, fh::launch_sum_partials(c->L.dot_part, nb, scal + 1, c->stream));
-      double w = 0;
-      HIPCHK(c, hipMemcpyAsync(&w, scal + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(c, hipStreamSynchronize(c->stream));
-      bu[(size_t)i * nl + j] = v;
-      uKu[(size_t)i * nl + j] = w;
-    }
+  if (nl <= 8) {
+    // all load pairs in one pass over the fields (fixed-order chunk sums)
+    const int nchunk = kPairChunks;
+    double* part = c->L.pair_part;            // nchunk x nl^2
+    double* out = part + (size_t)nchunk * 64;  // 2 x 64
+    HIPCHK(c, fh::launch_pair_dots(c->L.b, c->L.x, F, nl, 1, nchunk, part, out, c->stream));
+    HIPCHK(c, fh::launch_pair_dots(c->L.x, c->L.q, F, nl, 1, nchunk, part, out + 64,
+                                   c->stream));
+    HIPCHK(c, hipMemcpyAsync(bu.data(), out, sizeof(double) * nl * nl, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(uKu.data(), out + 64, sizeof(double) * nl * nl,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  } else {
+    double* scal = c->L.scal;
+    const int nb = 1024;
+    for (int i = 0; i < nl; ++i)
+      for (int j = 0; j < nl; ++j) {
+        HIPCHK(c, fh::launch_dot_partials(c->L.b + i * F, c->L.x + j * F, F, c->L.dot_part, nb,
+                                          c->stream));
+        HIPCHK(c, fh::launch_sum_partials(c->L.dot_part, nb, scal, c->stream));
+        double v = 0;
+        HIPCHK(c, hipMemcpyAsync(&v, scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, fh::launch_dot_partials(c->L.x + i * F, c->L.q + j * F, F, c->L.dot_part, nb,
+                                          c->stream));
+        HIPCHK(c, fh::launch_sum_partials(c->L.dot_part, nb, scal + 1, c->stream));
+        double w = 0;
+        HIPCHK(c, hipMemcpyAsync(&w, scal + 1, sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        bu[(size_t)i * nl + j] = v;
+        uKu[(size_t)i * nl + j] = w;
+      }
+  }
   double vol = 1.0;
   for (int k = 0; k < g.dim; ++k) vol *= c->l[k];
   c->chom.assign((size_t)nl * nl, 0.0);
