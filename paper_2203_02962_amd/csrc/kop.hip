@@ -278,6 +278,7 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
   constexpr int EX = Cfg::EX, PX = Cfg::PX, NE = Cfg::NE, NP = Cfg::NP, NT = Cfg::NT;
   constexpr int NPF = (NP + NT - 1) / NT;  // plane nodes per thread
   __shared__ T plane[2][3][NP];
+  __shared__ uint8_t phl[2][NP];  // voxel phases of the slab above each plane
   __shared__ T force[12][NE];   // lower-face totals of the current slab
   __shared__ T carry[12][NE];   // upper-face forces of the previous slab (own slot)
   __shared__ double red[32];
@@ -313,7 +314,6 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
   const int tid = threadIdx.x;
   const bool is_elem = tid < NE;
   const int ei = tid % EX, ej = tid / EX;
-  const int ex = wrapi(x0 - 1 + ei, nx), ey = wrapi(y0 - 1 + ej, ny);
   const T ihx = T(1.0 / g.h[0]), ihy = T(1.0 / g.h[1]), ihz = T(1.0 / g.h[2]);
 
   int poff[NPF];
@@ -323,7 +323,10 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
     const int a = idx % PX, b = idx / PX;
     poff[k] = idx < NP ? wrapi(y0 - 1 + b, ny) * nx + wrapi(x0 - 1 + a, nx) : -1;
   }
+  // A plane fetch also brings the phases of the voxels whose lowest corner
+  // is in that plane, so that one wait covers every global read of a step.
   T pf[NPF][3];
+  uint8_t pph[NPF];
   auto fetch = [&](int zp) {
     const long long zb = (long long)wrapi(zp, nz) * ny * nx;
 #pragma unroll
@@ -332,6 +335,7 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
         pf[k][0] = ub[zb + poff[k]];
         pf[k][1] = ub[N + zb + poff[k]];
         pf[k][2] = ub[2 * N + zb + poff[k]];
+        pph[k] = phase[zb + poff[k]];
       }
   };
   auto store = [&](int buf) {
@@ -342,13 +346,11 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
         plane[buf][0][idx] = pf[k][0];
         plane[buf][1][idx] = pf[k][1];
         plane[buf][2][idx] = pf[k][2];
+        phl[buf][idx] = pph[k];
       }
   };
 
   for (int i = tid; i < 2 * g.nphase_max; i += NT) lmt[i] = lm[i];
-  // phase of this thread's voxel column, one slab ahead
-  const long long ecol = (long long)ey * nx + ex;
-  int ph_next = is_elem ? phase[(long long)wrapi(z0 - 1, nz) * ny * nx + ecol] : 0;
   double dot = 0.0;
   fetch(z0 - 1);
   store(0);
@@ -359,8 +361,6 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
   for (int s = 0; s < nsteps; ++s) {
     const int zs = z0 - 1 + s;
     const int blo = s & 1, bhi = blo ^ 1;
-    const int ph = ph_next;
-    if (is_elem && s + 1 < nsteps) ph_next = phase[(long long)wrapi(zs + 1, nz) * ny * nx + ecol];
     const int ox = tid % TX, oy = tid / TX;
     const bool out_ok = s > 0 && tid < TX * TY && x0 + ox < nx && y0 + oy < ny;
     const long long o = ((long long)zs * ny + (y0 + oy)) * nx + (x0 + ox);
@@ -385,6 +385,7 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
             w[c][a] = u0 + u1;
             w[c][a | bit] = u1 - u0;
           }
+      const int ph = phl[blo][ej * PX + ei];
       const T lam = lmt[2 * ph], mu2 = lmt[2 * ph + 1];
       T f[3][8];
 #pragma unroll
@@ -483,6 +484,7 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 4)
   constexpr int EX = Cfg::EX, PX = Cfg::PX, NE = Cfg::NE, NP = Cfg::NP, NT = Cfg::NT;
   constexpr int NPF = (NP + NT - 1) / NT;
   __shared__ T plane[2][NP];
+  __shared__ T cpl[2][NP];  // coefficients of the slab above each plane
   __shared__ T force[4][NE];
   __shared__ T carry[4][NE];
   __shared__ double red[32];
@@ -510,7 +512,6 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 4)
   const int tid = threadIdx.x;
   const bool is_elem = tid < NE;
   const int ei = tid % EX, ej = tid / EX;
-  const int ex = wrapi(x0 - 1 + ei, nx), ey = wrapi(y0 - 1 + ej, ny);
   // modal factors: d[m] = sum over the difference bits beta of m of
   // c_M(m, beta) a_beta^2 (mode 0, the mean, carries no gradient)
   T d[8];
@@ -537,26 +538,27 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 4)
     const int a = idx % PX, b = idx / PX;
     poff[k] = idx < NP ? wrapi(y0 - 1 + b, ny) * nx + wrapi(x0 - 1 + a, nx) : -1;
   }
-  T pf[NPF];
+  // A plane fetch also brings the coefficients (field value or phase) of the
+  // voxels whose lowest corner is in that plane: one wait per step.
+  T pf[NPF], pc[NPF];
   auto fetch = [&](int zp) {
     const long long zb = (long long)wrapi(zp, nz) * ny * nx;
 #pragma unroll
     for (int k = 0; k < NPF; ++k)
-      if (poff[k] >= 0) pf[k] = ub[zb + poff[k]];
+      if (poff[k] >= 0) {
+        pf[k] = ub[zb + poff[k]];
+        pc[k] = kfield ? kfield[zb + poff[k]] : T(phase[zb + poff[k]]);
+      }
   };
   auto store = [&](int buf) {
 #pragma unroll
     for (int k = 0; k < NPF; ++k)
-      if (poff[k] >= 0) plane[buf][tid + k * NT] = pf[k];
+      if (poff[k] >= 0) {
+        plane[buf][tid + k * NT] = pf[k];
+        cpl[buf][tid + k * NT] = pc[k];
+      }
   };
   for (int i = tid; i < g.nphase_max; i += NT) skt[i] = sk[i];
-  const long long ecol = (long long)ey * nx + ex;
-  // coefficient of this thread's voxel column, one slab ahead
-  auto coef_src = [&](int zs) -> T {
-    const long long e = (long long)wrapi(zs, nz) * ny * nx + ecol;
-    return kfield ? kfield[e] : T(phase[e]);
-  };
-  T c_next = is_elem ? coef_src(z0 - 1) : T(0);
   double dot = 0.0;
   fetch(z0 - 1);
   store(0);
@@ -567,13 +569,12 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 4)
   for (int s = 0; s < nsteps; ++s) {
     const int zs = z0 - 1 + s;
     const int blo = s & 1, bhi = blo ^ 1;
-    const T csrc = c_next;
-    if (is_elem && s + 1 < nsteps) c_next = coef_src(zs + 1);
     const int ox = tid % TX, oy = tid / TX;
     const bool out_ok = s > 0 && tid < TX * TY && x0 + ox < nx && y0 + oy < ny;
     const long long o = ((long long)zs * ny + (y0 + oy)) * nx + (x0 + ox);
     __syncthreads();
     if (is_elem) {
+      const T csrc = cpl[blo][ej * PX + ei];
       const T kk = kfield ? skt[0] * csrc : skt[(int)csrc];
       T w[8];
 #pragma unroll
