@@ -93,7 +93,10 @@ template <typename T, int TX, int TY>
 struct HexCfg {
   static constexpr int EX = TX + 1, EY = TY + 1, PX = TX + 2, PY = TY + 2;
   static constexpr int NE = EX * EY, NP = PX * PY;
-  static constexpr int NT = ((NE + 63) / 64) * 64;
+  // element slots laid out with the node-plane pitch PX (one unused slot per
+  // row), so that the lanes of a wave touch consecutive LDS words
+  static constexpr int NEL = (EY - 1) * PX + EX;
+  static constexpr int NT = ((NEL + 63) / 64) * 64;
 };
 
 template <typename T, int TX, int TY>
@@ -275,12 +278,12 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
                    const uint8_t* __restrict__ phase, const T* __restrict__ lm,
                    long long ustride, long long qstride, const PcgState* st, double* pq_part) {
   using Cfg = HexCfg<T, TX, TY>;
-  constexpr int EX = Cfg::EX, PX = Cfg::PX, NE = Cfg::NE, NP = Cfg::NP, NT = Cfg::NT;
+  constexpr int EX = Cfg::EX, PX = Cfg::PX, NEL = Cfg::NEL, NP = Cfg::NP, NT = Cfg::NT;
   constexpr int NPF = (NP + NT - 1) / NT;  // plane nodes per thread
   __shared__ T plane[2][3][NP];
   __shared__ uint8_t phl[2][NP];  // voxel phases of the slab above each plane
-  __shared__ T force[12][NE];   // lower-face totals of the current slab
-  __shared__ T carry[12][NE];   // upper-face forces of the previous slab (own slot)
+  __shared__ T force[12][NEL];  // lower-face totals of the current slab
+  __shared__ T carry[12][NEL];  // upper-face forces of the previous slab (own slot)
   __shared__ double red[32];
   // per-phase {V lambda, 2 V mu}, sized by the launch (2 nphase_max)
   extern __shared__ __align__(16) unsigned char kop_dyn[];
@@ -312,8 +315,9 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
   phase += ms * g.phase_stride;
   lm += ms * g.lm_stride;
   const int tid = threadIdx.x;
-  const bool is_elem = tid < NE;
-  const int ei = tid % EX, ej = tid / EX;
+  // element (ei, ej) and output node (ox, oy) of this thread, both with pitch PX
+  const int ei = tid % PX, ej = tid / PX;
+  const bool is_elem = tid < NEL && ei < EX;
   const T ihx = T(1.0 / g.h[0]), ihy = T(1.0 / g.h[1]), ihz = T(1.0 / g.h[2]);
 
   int poff[NPF];
@@ -361,8 +365,8 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
   for (int s = 0; s < nsteps; ++s) {
     const int zs = z0 - 1 + s;
     const int blo = s & 1, bhi = blo ^ 1;
-    const int ox = tid % TX, oy = tid / TX;
-    const bool out_ok = s > 0 && tid < TX * TY && x0 + ox < nx && y0 + oy < ny;
+    const int ox = ei, oy = ej;
+    const bool out_ok = s > 0 && ox < TX && oy < TY && x0 + ox < nx && y0 + oy < ny;
     const long long o = ((long long)zs * ny + (y0 + oy)) * nx + (x0 + ox);
     __syncthreads();
     if (is_elem) {
@@ -444,12 +448,12 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
       if (zs + 3 <= z1) fetch(zs + 3);
     }
     if (out_ok) {
-      const int e00 = oy * EX + ox;
+      const int e00 = oy * PX + ox;
       const T pd[3] = {pd0, pd1, pd2};
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const T v = force[c * 4 + 3][e00] + force[c * 4 + 2][e00 + 1] +
-                    force[c * 4 + 1][e00 + EX] + force[c * 4 + 0][e00 + EX + 1];
+                    force[c * 4 + 1][e00 + PX] + force[c * 4 + 0][e00 + PX + 1];
         qb[c * N + o] = v;
         dot += (double)pd[c] * (double)v;
       }
@@ -481,12 +485,12 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 4)
                       const T* __restrict__ sk, long long ustride, long long qstride,
                       const PcgState* st, double* pq_part) {
   using Cfg = HexCfg<T, TX, TY>;
-  constexpr int EX = Cfg::EX, PX = Cfg::PX, NE = Cfg::NE, NP = Cfg::NP, NT = Cfg::NT;
+  constexpr int EX = Cfg::EX, PX = Cfg::PX, NEL = Cfg::NEL, NP = Cfg::NP, NT = Cfg::NT;
   constexpr int NPF = (NP + NT - 1) / NT;
   __shared__ T plane[2][NP];
   __shared__ T cpl[2][NP];  // coefficients of the slab above each plane
-  __shared__ T force[4][NE];
-  __shared__ T carry[4][NE];
+  __shared__ T force[4][NEL];
+  __shared__ T carry[4][NEL];
   __shared__ double red[32];
   extern __shared__ __align__(16) unsigned char kop_dyn[];
   T* skt = reinterpret_cast<T*>(kop_dyn);  // V k per phase (field: V)
@@ -510,8 +514,9 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 4)
   const T* __restrict__ ub = u + (long long)ld * ustride;
   T* __restrict__ qb = q + (long long)ld * qstride;
   const int tid = threadIdx.x;
-  const bool is_elem = tid < NE;
-  const int ei = tid % EX, ej = tid / EX;
+  // element (ei, ej) and output node (ox, oy) of this thread, both with pitch PX
+  const int ei = tid % PX, ej = tid / PX;
+  const bool is_elem = tid < NEL && ei < EX;
   // modal factors: d[m] = sum over the difference bits beta of m of
   // c_M(m, beta) a_beta^2 (mode 0, the mean, carries no gradient)
   T d[8];
@@ -569,8 +574,8 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 4)
   for (int s = 0; s < nsteps; ++s) {
     const int zs = z0 - 1 + s;
     const int blo = s & 1, bhi = blo ^ 1;
-    const int ox = tid % TX, oy = tid / TX;
-    const bool out_ok = s > 0 && tid < TX * TY && x0 + ox < nx && y0 + oy < ny;
+    const int ox = ei, oy = ej;
+    const bool out_ok = s > 0 && ox < TX && oy < TY && x0 + ox < nx && y0 + oy < ny;
     const long long o = ((long long)zs * ny + (y0 + oy)) * nx + (x0 + ox);
     __syncthreads();
     if (is_elem) {
@@ -617,8 +622,8 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 4)
       if (zs + 3 <= z1) fetch(zs + 3);
     }
     if (out_ok) {
-      const int e00 = oy * EX + ox;
-      const T v = force[3][e00] + force[2][e00 + 1] + force[1][e00 + EX] + force[0][e00 + EX + 1];
+      const int e00 = oy * PX + ox;
+      const T v = force[3][e00] + force[2][e00 + 1] + force[1][e00 + PX] + force[0][e00 + PX + 1];
       qb[o] = v;
       dot += (double)pd * (double)v;
     }
