@@ -21,10 +21,17 @@ from .precond import Preconditioner
 
 
 def mean_material(prob: Problem) -> np.ndarray:
-    """Cref_mean = (1/|Y|) sum_Q C(x_Q) w_Q (Sec. 6.2)."""
+    """Cref_mean = (1/|Y|) sum_Q C(x_Q) w_Q (Sec. 6.2).
+
+    The voxel sum runs along a contiguous axis, where numpy sums pairwise
+    (error ~ eps log N); a sum down the first axis of the (N, m, m) stack
+    would add one voxel at a time, and for grids of two materials that
+    rounding is systematic (about N eps, 1.5e-11 relative at 128^3)."""
     w = quadrature_weights(prob)
     C = prob.voxel_materials()
-    return C.sum(axis=0) * w.sum() / prob.volume
+    m = C.shape[1]
+    total = np.ascontiguousarray(C.reshape(prob.N, m * m).T).sum(axis=1).reshape(m, m)
+    return total * w.sum() / prob.volume
 
 
 def homogenized_energy(prob: Problem, loads: np.ndarray, sols) -> np.ndarray:

@@ -22,7 +22,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .assembly import Problem, assemble_stiffness
+from .assembly import Problem, assemble_stiffness, operator_rows
 from .naive_dft import dft, idft
 
 
@@ -68,3 +68,67 @@ class Preconditioner:
         z = np.concatenate([np.real(idft(Z[:, a].reshape(prob.grid_shape))).ravel()
                             for a in range(nd)])
         return z
+
+
+def _uniform_problem(prob: Problem, Cref: np.ndarray) -> Problem:
+    """The same grid and stencil with the uniform reference material."""
+    return Problem(prob.n, prob.problem, prob.elem,
+                   phase=np.zeros(prob.grid_shape, dtype=np.int64),
+                   mat=np.asarray(Cref, dtype=float)[None], l=prob.l)
+
+
+def stencil_symbol(prob: Problem, Cref: np.ndarray) -> np.ndarray:
+    """(N, nd, nd) complex K^(xi) by Alg. 2 for grids too large to assemble.
+
+    The response of Kref to the unit impulse of component beta at node 0 is
+    nonzero only at the nodes that share a pixel with node 0 (offsets in
+    {-1, 0, 1}^d); those rows come from assembly.operator_rows with the
+    uniform Cref.  The DFT of that column (naive_dft's convention) is then
+    the sum over those nodes J of col[J] exp(-2 pi i sum_k xi_k J_k / n_k),
+    evaluated at every frequency.  Same ordering as reference_symbol."""
+    ref = _uniform_problem(prob, Cref)
+    nd, N, dim = prob.ndof_node, prob.N, prob.dim
+    n = np.array(prob.n)
+    offs = np.array(list(np.ndindex(*(3,) * dim))) - 1          # (3^d, dim), x first
+    coords = np.unique(offs % n[None, :], axis=0)                # distinct nodes
+    flat = np.zeros(len(coords), dtype=np.int64)
+    stride = 1
+    for ax in range(dim):
+        flat += coords[:, ax] * stride
+        stride *= prob.n[ax]
+    # per-axis phase factors exp(-2 pi i xi_k J_k / n_k), exponent reduced mod n_k
+    xi = [np.arange(prob.n[ax]) for ax in range(dim)]
+    Khat = np.zeros(prob.grid_shape + (nd, nd), dtype=complex)
+    for beta in range(nd):
+        impulse = np.zeros(nd * N)
+        impulse[beta * N] = 1.0
+        col = operator_rows(ref, impulse, flat)                  # (nd, nodes)
+        for j, c in enumerate(coords):
+            ph = np.ones((1,) * dim, dtype=complex)
+            for ax in range(dim):
+                e = np.exp(-2j * np.pi * ((xi[ax] * c[ax]) % prob.n[ax]) / prob.n[ax])
+                shape = [1] * dim
+                shape[dim - 1 - ax] = prob.n[ax]                 # numpy axes are z, y, x
+                ph = ph * e.reshape(shape)
+            for alpha in range(nd):
+                Khat[..., alpha, beta] += col[alpha, j] * ph
+    return Khat.reshape(N, nd, nd)
+
+
+class FFTPreconditioner:
+    """The M^+ r of Preconditioner for grids too large for the dense DFT:
+    symbol from stencil_symbol, transforms by numpy.fft (a library FFT with
+    the same unnormalised forward / 1/N inverse convention as naive_dft)."""
+
+    def __init__(self, prob: Problem, Cref: np.ndarray):
+        self.prob = prob
+        self.Kplus = pseudo_inverse_blocks(stencil_symbol(prob, Cref))
+
+    def apply(self, r: np.ndarray) -> np.ndarray:
+        prob = self.prob
+        nd, N = prob.ndof_node, prob.N
+        R = np.stack([np.fft.fftn(r[a * N:(a + 1) * N].reshape(prob.grid_shape)).ravel()
+                      for a in range(nd)], axis=1)
+        Z = np.einsum("fab,fb->fa", self.Kplus, R)
+        return np.concatenate([np.real(np.fft.ifftn(Z[:, a].reshape(prob.grid_shape))).ravel()
+                               for a in range(nd)])
