@@ -364,7 +364,8 @@ class Context:
             arr[i].n = (ctypes.c_int * 3)(*[int(v) for v in n])
             arr[i].nphase = int(m.shape[0])
             arr[i].mat = _dptr(m)
-            arr[i].u_dev = _tptr(u_out[i]).value if u_out is not None else None
+            arr[i].u_dev = (_tptr(u_out[i]).value
+                            if u_out is not None and u_out[i] is not None else None)
         chom = np.zeros((len(systems), nload, nload))
         sts = (fh_stats * len(systems))()
         rep = fh_batch_report()

@@ -162,3 +162,49 @@ def test_conduction_256_solves(fh):
         assert lam.min() > reuss * (1 - 1e-12) and lam.max() < voigt * (1 + 1e-12)
     say("C_hom FP32-refined vs FP64", _rel(H[fh.FH_FP32_REFINED], H[fh.FH_FP64]))
     assert _rel(H[fh.FH_FP32_REFINED], H[fh.FH_FP64]) < 1e-10
+
+
+def test_batch_96_benchmark_workload(fh):
+    """The benchmark's batch: 96 microstructures (n in {32, 48, 64, 96}) x 6
+    unit strains in one FP32-refined call to 1e-6.  Every system's C_hom
+    agrees with its own FP64 single solve to 1e-10 within 1e-8 (C_hom is
+    quadratic in the 1e-6 solver error; measured 1.6e-9), and the fluctuation
+    fields of one system per grid size satisfy the oracle's equations at
+    sampled nodes to 1e-5 (ten times the tolerance, which bounds the residual
+    in the preconditioner's norm, not the 2-norm; measured 1-2e-6)."""
+    from paper_2203_02962_amd.runner import setup_context
+    from synth import batch_workload_parallel
+    say("batch: generate 96")
+    wls = batch_workload_parallel(count=96, workers=16)
+    devs = [(torch.from_numpy(w["phase"]).cuda(), w["n"], w["mat"]) for w in wls]
+    pick = {}
+    for i, w in enumerate(wls):
+        pick.setdefault(w["n"][0], i)
+    u_out = [None] * len(wls)
+    for i in pick.values():
+        u_out[i] = torch.empty(6 * 3 * int(np.prod(wls[i]["n"])), dtype=torch.float64,
+                               device="cuda")
+    ctx = fh.Context(0)
+    say("batch: solve")
+    rc, Hb, sts, rep = ctx.solve_batch(devs, np.eye(6), eta=1e-6,
+                                       precision=fh.FH_FP32_REFINED, u_out=u_out)
+    assert rc == 0
+    worst = 0.0
+    for i, w in enumerate(wls):
+        wl = dict(dim=3, n=w["n"], problem="elastic", element="hex8", phase=w["phase"],
+                  mat=w["mat"], loads=np.eye(6))
+        c1 = setup_context(wl)
+        c1.solve(eta=1e-10)
+        worst = max(worst, _rel(Hb[i], c1.get_homogenized()))
+        c1.close()
+    say("batch: worst C_hom difference vs FP64 single solves", worst)
+    assert worst < 1e-8
+    for n, i in pick.items():
+        w = wls[i]
+        prob = Problem(tuple(w["n"]), "elastic", "hex8", phase=w["phase"], mat=w["mat"])
+        u = u_out[i].cpu().numpy().reshape(6, -1)
+        nodes = _nodes(prob, 16)
+        for j in range(6):
+            rr = _residual_ratio(prob, np.eye(6)[j], u[j], nodes)
+            say("batch system", i, "n", n, "load", j, "residual ratio", rr)
+            assert rr < 1e-5, (i, j)
