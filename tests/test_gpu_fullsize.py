@@ -14,8 +14,9 @@ gradients).  These grids are too large for the assembled oracle, so:
   K^+;
 - solves are checked through properties that hold at any size: the residual
   of the GPU solution in the oracle's own system (right-hand side and operator
-  rows at sampled nodes), symmetry of C_hom, the Voigt and Reuss bounds, and
-  FP64 against FP32-refined results.
+  rows at sampled nodes) within 100 times the PCG tolerance (which bounds the
+  residual in the preconditioner's norm, not over sampled rows), symmetry of
+  C_hom, the Voigt and Reuss bounds, and FP64 against FP32-refined results.
 """
 import sys
 
@@ -132,7 +133,7 @@ def test_elastic_128_solution_solves_oracle_system(fh):
     for j, u in enumerate(_fields(ctx, prob, 6)):
         rr = _residual_ratio(prob, wl["loads"][j], u, nodes)
         say("load", j, "residual ratio", rr)
-        assert rr < 1e-7, j
+        assert rr < 100 * 1e-10, j  # measured 2e-10
 
 
 def test_conduction_256_solves(fh):
@@ -155,7 +156,7 @@ def test_conduction_256_solves(fh):
         for j, u in enumerate(_fields(ctx, prob, 3)):
             rr = _residual_ratio(prob, wl["loads"][j], u, nodes)
             say("load", j, "residual ratio", rr)
-            assert rr < 1e-5, (prec, j)
+            assert rr < 100 * 1e-8, (prec, j)  # measured 6e-8
         C = H[prec]
         assert _rel(C, C.T) < 1e-12
         lam = np.linalg.eigvalsh(0.5 * (C + C.T))
