@@ -81,6 +81,11 @@ extern "C" {
 /* fh_opts.flags: start every load case from the learned warm start of the
  * network attached with fh_set_warm_start instead of from zero (see there) */
 #define FH_FLAG_WARM_START 4
+/* fh_opts.flags, with FH_FLAG_TIME_KERNELS: record the event pairs only in
+ * every 8th PCG iteration.  Each timed launch leaves the GPU idle for a few
+ * microseconds around its events, so timing every launch slows the loop;
+ * the per-class totals then cover the sampled iterations only.             */
+#define FH_FLAG_TIME_SAMPLED 8
 
 /* kernel classes of fh_stats.kernel_ms / kernel_launches                  */
 #define FH_K_OPERATOR 0   /* q = K p (+ p.q partials)                       */
@@ -130,6 +135,9 @@ typedef struct fh_stats {
   int guess_used[FH_MAX_LOADS];   /* 1 if the initial guess was kept          */
   double guess_res[FH_MAX_LOADS]; /* sqrt(r0.M r0 / b.M b) of the guess       */
   double guess_ms;                /* warm-start inference + judge             */
+  long long kernel_issued[FH_K_NCLASS]; /* launches per class, timed or not
+                                           (kernel_launches counts the timed
+                                           ones, FH_FLAG_TIME_SAMPLED)       */
 } fh_stats;
 
 /* Context on HIP device `device`.  Returns FH_EDEVICE if it cannot be used. */

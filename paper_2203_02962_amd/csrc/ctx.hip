@@ -110,11 +110,14 @@ struct fh_ctx {
   // solve stream around each launch, read back at every poll
   struct KTimer {
     bool on = false;
+    int period = 1;      // time every period-th PCG iteration
+    bool sample = true;  // the current iteration is timed
     std::vector<hipEvent_t> ev;  // 2 per slot
     std::vector<int> cls;
     size_t used = 0;
     double ms[FH_K_NCLASS] = {};
-    long long n[FH_K_NCLASS] = {};
+    long long n[FH_K_NCLASS] = {};       // timed launches
+    long long issued[FH_K_NCLASS] = {};  // all launches while on
   } kt;
 
   // batched solves: nms microstructures of this grid, G = loads each
@@ -859,7 +862,9 @@ int pcg_run(fh_ctx* c, int nload, const PcgBufs<T>& bf, double eta, int itmax, i
       if (exec) {
         HIPCHK(c, hipGraphLaunch(exec, c->stream));
       } else {
+        c->kt.sample = done_iters % c->kt.period == 0;
         const int rc = one_iteration();
+        c->kt.sample = true;
         if (rc) return rc;
       }
     }
@@ -1135,6 +1140,8 @@ int fill_stats(fh_ctx* c, const std::vector<fh::PcgState>& hs, int nload, fh_sta
 int kt_begin(fh_ctx* c, int cls) {
   fh_ctx::KTimer& t = c->kt;
   if (!t.on) return -1;
+  t.issued[cls] += 1;
+  if (!t.sample) return -1;
   if (t.used * 2 + 2 > t.ev.size()) {
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess) return -1;
@@ -1763,11 +1770,14 @@ int fh_solve(fh_ctx* c, const fh_opts* opt, fh_stats* st) {
   auto t0 = std::chrono::steady_clock::now();
   c->solved = false;
   c->kt.on = (o.flags & FH_FLAG_TIME_KERNELS) != 0;
+  c->kt.period = (o.flags & FH_FLAG_TIME_SAMPLED) ? 8 : 1;
+  c->kt.sample = true;
   if (o.flags & FH_FLAG_REBUILD) c->symbol_ok = c->rhs_ok = false;
   c->kt.used = 0;
   for (int k = 0; k < FH_K_NCLASS; ++k) {
     c->kt.ms[k] = 0.0;
     c->kt.n[k] = 0;
+    c->kt.issued[k] = 0;
   }
   int rc = build_symbol(c);
   if (rc) return rc;
@@ -1877,6 +1887,7 @@ int fh_solve(fh_ctx* c, const fh_opts* opt, fh_stats* st) {
   for (int k = 0; k < FH_K_NCLASS; ++k) {
     c->last.kernel_ms[k] = c->kt.ms[k];
     c->last.kernel_launches[k] = c->kt.n[k];
+    c->last.kernel_issued[k] = c->kt.issued[k];
   }
   c->kt.on = false;
   if (st) *st = c->last;

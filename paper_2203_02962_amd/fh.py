@@ -25,6 +25,7 @@ FH_MAX_LOADS = 32
 FH_FLAG_TIME_KERNELS = 1
 FH_FLAG_REBUILD = 2
 FH_FLAG_WARM_START = 4
+FH_FLAG_TIME_SAMPLED = 8
 NET_CLASSES = ["conv", "dgrad", "wgrad", "other"]
 KERNEL_CLASSES = ["operator", "xfwd", "yfwd", "zsolve", "yinv", "xinv", "scalar", "other"]
 
@@ -62,7 +63,8 @@ class fh_stats(ctypes.Structure):
                 ("chom_ms", ctypes.c_double), ("dof", ctypes.c_longlong),
                 ("kernel_ms", ctypes.c_double * 8), ("kernel_launches", ctypes.c_longlong * 8),
                 ("guess_used", ctypes.c_int * FH_MAX_LOADS),
-                ("guess_res", ctypes.c_double * FH_MAX_LOADS), ("guess_ms", ctypes.c_double)]
+                ("guess_res", ctypes.c_double * FH_MAX_LOADS), ("guess_ms", ctypes.c_double),
+                ("kernel_issued", ctypes.c_longlong * 8)]
 
     def as_dict(self):
         n = self.nload
@@ -71,6 +73,7 @@ class fh_stats(ctypes.Structure):
                     setup_ms=self.setup_ms, solve_ms=self.solve_ms, chom_ms=self.chom_ms,
                     dof=self.dof, kernel_ms=list(self.kernel_ms),
                     kernel_launches=list(self.kernel_launches),
+                    kernel_issued=list(self.kernel_issued),
                     guess_used=list(self.guess_used[:n]), guess_res=list(self.guess_res[:n]),
                     guess_ms=self.guess_ms)
 
@@ -293,9 +296,11 @@ class Context:
         return self._check(self.lib.fh_set_warm_start(self.ptr, net.ptr if net else None))
 
     def solve(self, eta=1e-10, itmax=10000, precision=FH_FP64, poll=0, eta_inner=0.0,
-              time_kernels=False, rebuild=False, warm_start=False, guess_dev=None):
+              time_kernels=False, rebuild=False, warm_start=False, guess_dev=None,
+              time_sampled=False):
         flags = (FH_FLAG_TIME_KERNELS if time_kernels else 0) | \
-            (FH_FLAG_REBUILD if rebuild else 0) | (FH_FLAG_WARM_START if warm_start else 0)
+            (FH_FLAG_REBUILD if rebuild else 0) | (FH_FLAG_WARM_START if warm_start else 0) | \
+            (FH_FLAG_TIME_SAMPLED if time_sampled else 0)
         o = self.opts(eta, itmax, precision, poll, eta_inner, flags)
         if guess_dev is not None:
             o.guess_dev = _tptr(guess_dev).value
