@@ -503,6 +503,23 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
   cplx<T>* a = tw + nx;
   cplx<T>* S = a + (kRows / 2) * lsx;  // 16 x nxh raw tile, row stride nxh + 1
   load_twiddles(tw, twx, nx);
+  // PCG mode: the reads of p and x for the first 8 trips of the output loop
+  // are issued here, before the spectrum tile, and land during the FFT
+  constexpr int CH = 8;
+  const int nout = kRows * nx;
+  T pv0[CH], xv0[CH];
+  if (mode == XI_PCG) {
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      const int idx = threadIdx.x + k * kThreads;
+      const int row = idx / nx, xx = idx - row * nx, y = y0 + row;
+      if (idx < nout && y < ny) {
+        const long long o = fbase + (long long)y * nx + xx;
+        pv0[k] = p[o];
+        xv0[k] = x[o];
+      }
+    }
+  }
   const long long abase = (long long)ld * sstride + ((long long)c * g.nz + z) * nxh * ny;
   staged_fill<8, cplx<T>>(
       kRows * nxh,
@@ -538,12 +555,16 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
   cplx<T>* res = fft_lines<T, P3>(a, px, kRows / 2, tw, +1);
   const T alpha = (mode == XI_PCG) ? T(st[ld].alpha) : T(0);
   const T beta = (mode == XI_PCG) ? T(st[ld].beta) : T(0);
-  // PCG mode reads p and x: the reads of 8 trips are issued before their use
-  constexpr int CH = 8;
-  const int nout = kRows * nx;
+  // later trips: the reads of 8 trips are issued before their use
   for (int base = threadIdx.x; base < nout; base += CH * kThreads) {
     T pv[CH], xv[CH];
-    if (mode == XI_PCG) {
+    if (mode == XI_PCG && base == (int)threadIdx.x) {
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        pv[k] = pv0[k];
+        xv[k] = xv0[k];
+      }
+    } else if (mode == XI_PCG) {
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         const int idx = base + k * kThreads;
