@@ -27,7 +27,7 @@
 using fh::cplx;
 
 // chunks of the load-pair dot products behind C_hom
-constexpr int kPairChunks = 256;
+constexpr int kPairChunks = 1024;
 
 struct fh_ctx {
   int device = 0;

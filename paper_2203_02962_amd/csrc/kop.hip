@@ -763,10 +763,11 @@ hipError_t launch_kop_generic(const Grid& g, int elem, const T* u, T* q, const u
 // b[alpha][I] = -sum_a fe[t(e)][load][a*nd + alpha] (* k(e)), e = I - c_a.
 // Corner contributions are added in antipodal pairs (a, NC-1-a): in a
 // homogeneous medium each pair cancels exactly, so b = 0 exactly there.
+// The phases (or conductivities) of the nc pixels around node I are read
+// once and serve every load case and component.
 __global__ void k_rhs(Grid g, int nc, const uint8_t* __restrict__ phase,
                       const double* __restrict__ kfield, const double* __restrict__ fe,
                       int nload, double* __restrict__ b, long long bstride) {
-  const int ld = blockIdx.y;
   const int nx = g.nx, ny = g.ny, nz = g.nz, nd = g.nd;
   const long long N = g.N;
   const int nk = nc * nd;
@@ -775,22 +776,30 @@ __global__ void k_rhs(Grid g, int nc, const uint8_t* __restrict__ phase,
     const int x = (int)(I % nx);
     const int y = (int)((I / nx) % ny);
     const int z = (int)(I / ((long long)nx * ny));
-    for (int al = 0; al < nd; ++al) {
-      double acc = 0.0;
-      for (int a = 0; a < nc / 2; ++a) {
-        double pair = 0.0;
-        for (int side = 0; side < 2; ++side) {
-          const int aa = side ? nc - 1 - a : a;
-          const int ax = aa & 1, ay = (aa >> 1) & 1, az = (aa >> 2) & 1;
-          const long long e = ((long long)wrapi(z - az, nz) * ny + wrapi(y - ay, ny)) * nx +
-                              wrapi(x - ax, nx);
-          const int t = phase ? phase[e] : 0;
-          const double sc = kfield ? kfield[e] : 1.0;
-          pair += sc * fe[((size_t)t * nload + ld) * nk + aa * nd + al];
+    int t[8];
+    double sc[8];
+#pragma unroll
+    for (int aa = 0; aa < 8; ++aa) {
+      if (aa >= nc) break;
+      const int ax = aa & 1, ay = (aa >> 1) & 1, az = (aa >> 2) & 1;
+      const long long e = ((long long)wrapi(z - az, nz) * ny + wrapi(y - ay, ny)) * nx +
+                          wrapi(x - ax, nx);
+      t[aa] = phase ? phase[e] : 0;
+      sc[aa] = kfield ? kfield[e] : 1.0;
+    }
+    for (int ld = 0; ld < nload; ++ld) {
+      for (int al = 0; al < nd; ++al) {
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          if (a >= nc / 2) break;
+          const int a2 = nc - 1 - a;
+          const double pair = sc[a] * fe[((size_t)t[a] * nload + ld) * nk + a * nd + al] +
+                              sc[a2] * fe[((size_t)t[a2] * nload + ld) * nk + a2 * nd + al];
+          acc += pair;
         }
-        acc += pair;
+        b[(long long)ld * bstride + al * N + I] = -acc;
       }
-      b[(long long)ld * bstride + al * N + I] = -acc;
     }
   }
 }
@@ -802,9 +811,9 @@ hipError_t launch_rhs(const Grid& g, int elem, const uint8_t* phase, const doubl
   (void)elem;
   const int nc = g.dim == 3 ? 8 : 4;
   long long blocks = (g.N + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_rhs, dim3((unsigned)blocks, nload), dim3(256), 0, s, g, nc, phase, kfield,
-                     fe, nload, b, bstride);
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_rhs, dim3((unsigned)blocks), dim3(256), 0, s, g, nc, phase, kfield, fe,
+                     nload, b, bstride);
   return hipGetLastError();
 }
 

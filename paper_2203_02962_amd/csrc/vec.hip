@@ -183,12 +183,13 @@ hipError_t launch_field_sum(const double* x, long long n, double* part, int nb, 
 
 // All load-pair products within every microstructure of a batch:
 // out[ms][i][j] = sum_k A[ms*G+i][k] * B[ms*G+j][k], G <= 8.  Each block
-// reads its chunk of the 2G fields once; chunks are summed in a fixed order
-// by k_pair_dots_sum.
+// reads its chunk of the 2G fields once and reduces its G^2 sums with wave
+// shuffles and one barrier (a fixed tree, so the result is deterministic);
+// chunks are summed in a fixed order by k_pair_dots_sum.
 constexpr int kPairMax = 8;
-__global__ void k_pair_dots(const double* A, const double* B, long long F, int G, int nchunk,
-                            double* part) {
-  __shared__ double sh[256];
+__global__ void __launch_bounds__(256) k_pair_dots(const double* A, const double* B, long long F,
+                                                   int G, int nchunk, double* part) {
+  __shared__ double sh[4][kPairMax * kPairMax];
   const int ms = blockIdx.y, chunk = blockIdx.x;
   const long long len = (F + nchunk - 1) / nchunk;
   const long long k0 = chunk * len, k1 = k0 + len < F ? k0 + len : F;
@@ -203,11 +204,16 @@ __global__ void k_pair_dots(const double* A, const double* B, long long F, int G
     for (int i = 0; i < G; ++i)
       for (int j = 0; j < G; ++j) acc[i * G + j] += a[i] * b[j];
   }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int t = 0; t < G * G; ++t) {
-    const double v = block_sum_fixed(acc[t], sh);
-    if (threadIdx.x == 0) part[((long long)ms * nchunk + chunk) * G * G + t] = v;
-    __syncthreads();
+    double v = acc[t];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) sh[wave][t] = v;
   }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < G * G)
+    part[((long long)ms * nchunk + chunk) * G * G + t] = ((sh[0][t] + sh[1][t]) + sh[2][t]) + sh[3][t];
 }
 __global__ void k_pair_dots_sum(const double* part, int nchunk, int GG, double* out) {
   const int ms = blockIdx.x;
