@@ -1217,9 +1217,11 @@ double time_launches(fh_ctx* c, const std::function<int()>& launch, int reps) {
 
 // Choose the operator z-chunk and the FFT lines per block for this grid by
 // timing the FP32 kernels (the refinement's inner loop) on the group's own
-// buffers.
-int autotune(fh_ctx* c, int nload_total, double* tune_ms) {
+// buffers.  The candidates are timed on at most 24 load cases: enough blocks
+// to fill the GPU at these grid sizes, at a fraction of the cost.
+int autotune(fh_ctx* c, int nload_all, double* tune_ms) {
   auto t0 = std::chrono::steady_clock::now();
+  const int nload_total = std::min(nload_all, 24);
   fh::Grid& g = c->g;
   const long long F = (long long)g.nd * g.N;
   const long long S = (long long)g.nd * g.nxh * g.ny * g.nz;
