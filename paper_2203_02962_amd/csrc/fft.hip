@@ -171,19 +171,28 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int n, int ls, int 
 // P3: the length has a factor 3 (radix-3 stages compiled in).  Lengths are
 // products of 2 and 3 only.
 
+// Stages [first, last) of the plan, with the radices in plan order or in
+// reverse order (a Stockham FFT sorts itself for any order of radices); L0 is
+// the product of the radices of the stages before `first`.
 template <typename T, bool P3>
-__device__ cplx<T>* fft_lines(cplx<T>* a, const AxisPlan& plan, int nlines, const cplx<T>* tw,
-                              int sign) {
-  int L = 1;
+__device__ void fft_stages(cplx<T>* a, const AxisPlan& plan, bool reversed, int first, int last,
+                           int L0, int nlines, const cplx<T>* tw, int sign) {
+  int L = L0;
   const int n = plan.n, ls = lds_stride<T>(n);
-  for (int st = 0; st < plan.nstage; ++st) {
-    const int R = (plan.code >> (4 * st)) & 15u;
+  for (int st = first; st < last; ++st) {
+    const int R = (plan.code >> (4 * (reversed ? plan.nstage - 1 - st : st))) & 15u;
     if (R == 8) stockham_stage<T, 8>(a, n, ls, nlines, L, tw, sign);
     else if (R == 4) stockham_stage<T, 4>(a, n, ls, nlines, L, tw, sign);
     else if (R == 2) stockham_stage<T, 2>(a, n, ls, nlines, L, tw, sign);
     else if constexpr (P3) stockham_stage<T, 3>(a, n, ls, nlines, L, tw, sign);
     L *= R;
   }
+}
+
+template <typename T, bool P3>
+__device__ cplx<T>* fft_lines(cplx<T>* a, const AxisPlan& plan, int nlines, const cplx<T>* tw,
+                              int sign) {
+  fft_stages<T, P3>(a, plan, false, 0, plan.nstage, 1, nlines, tw, sign);
   return a;
 }
 
@@ -330,10 +339,89 @@ __global__ void __launch_bounds__(kThreads) k_yfwd(Grid g, AxisPlan py, const cp
   }
 }
 
+// z pass, 3 components, plans ending in radix 2 (lengths 16, 128, ...): the
+// last forward stage, the per-frequency K^+ solve with its Parseval sum and
+// the first stage of the inverse (run with the radices in reverse order, so
+// that it starts with radix 2) in one pass through registers.  The forward
+// stage leaves X(j) and X(j + n/2) with the thread whose inverse butterfly
+// needs exactly those two, so only the three components of a frequency pair
+// have to meet in one thread: one LDS round trip and the solve pass are
+// saved.
+template <typename T>
+__device__ double zpass_fused_mid(cplx<T>* a, int n, int ls, int cls, int kyb, int ky0, int ny,
+                                  int nz, int kx, const cplx<T>* tw, const T* kplus,
+                                  long long nfreq, double wgt) {
+  constexpr int MAXIT = (2048 / 6 + kThreads - 1) / kThreads;  // kyb * n/2 <= 2048 / 6
+  const int m = n / 2;
+  const int items = kyb * m;
+  cplx<T> v[MAXIT][3][2];
+  int jj[MAXIT], kyl_[MAXIT];
+#pragma unroll
+  for (int k = 0; k < MAXIT; ++k) {
+    const int it = threadIdx.x + k * kThreads;
+    kyl_[k] = -1;
+    if (it < items) {
+      const int kyl = it / m, j = it - kyl * m;
+      const cplx<T> w = tw[j];  // forward twiddle of the last stage: L = n/2, t = 1
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const cplx<T>* src = a + c * cls + kyl * ls;
+        const cplx<T> x0 = src[sw<T>(j)];
+        const cplx<T> x1 = cmul(src[sw<T>(j + m)], w);
+        v[k][c][0] = cadd(x0, x1);
+        v[k][c][1] = csub(x0, x1);
+      }
+      jj[k] = j;
+      kyl_[k] = kyl;
+    }
+  }
+  __syncthreads();
+  double part = 0.0;
+#pragma unroll
+  for (int k = 0; k < MAXIT; ++k) {
+    if (kyl_[k] < 0) continue;
+    const int j = jj[k], kyl = kyl_[k], ky = ky0 + kyl;
+    if (ky < ny) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const long long f = ((long long)kx * ny + ky) * nz + j + t * m;
+        const T k00 = kplus[f], k11 = kplus[nfreq + f], k22 = kplus[2 * nfreq + f];
+        const T k12 = kplus[3 * nfreq + f], k02 = kplus[4 * nfreq + f],
+                k01 = kplus[5 * nfreq + f];
+        const cplx<T> r0 = v[k][0][t], r1 = v[k][1][t], r2 = v[k][2][t];
+        const cplx<T> z0v = {k00 * r0.re + k01 * r1.re + k02 * r2.re,
+                             k00 * r0.im + k01 * r1.im + k02 * r2.im};
+        const cplx<T> z1v = {k01 * r0.re + k11 * r1.re + k12 * r2.re,
+                             k01 * r0.im + k11 * r1.im + k12 * r2.im};
+        const cplx<T> z2v = {k02 * r0.re + k12 * r1.re + k22 * r2.re,
+                             k02 * r0.im + k12 * r1.im + k22 * r2.im};
+        part += wgt * ((double)r0.re * z0v.re + (double)r0.im * z0v.im +
+                       (double)r1.re * z1v.re + (double)r1.im * z1v.im +
+                       (double)r2.re * z2v.re + (double)r2.im * z2v.im);
+        v[k][0][t] = z0v;
+        v[k][1][t] = z1v;
+        v[k][2][t] = z2v;
+      }
+    }
+    // first inverse stage (radix 2, no twiddle): outputs at 2j and 2j + 1
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      cplx<T>* dst = a + c * cls + kyl * ls;
+      dst[sw<T>(2 * j)] = cadd(v[k][c][0], v[k][c][1]);
+      dst[sw<T>(2 * j + 1)] = csub(v[k][c][0], v[k][c][1]);
+    }
+  }
+  __syncthreads();
+  return part;
+}
+
 // ------------------------------------------------ z forward (+ solve + inverse)
 // grid (ceil(ny/kyb), nxh, nload).  Dynamic LDS: tw[nz], a/b[nd*kyb*nz].
+// Power-of-two lengths run four waves per SIMD (at most 128 VGPRs, 7 spilled
+// in FP64): 212 -> 192 us per 6-load launch at 128^3; with radix-3 stages
+// that budget would spill 44 registers, so those keep the compiler's choice.
 template <typename T, bool P3>
-__global__ void __launch_bounds__(kThreads) k_zpass(Grid g, AxisPlan pz, const cplx<double>* twz,
+__global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan pz, const cplx<double>* twz,
                                                    int mode, int kyb, cplx<T>* B,
                                                    long long sstride, const T* kplus,
                                                    const PcgState* st, double* rz_part) {
@@ -378,9 +466,21 @@ __global__ void __launch_bounds__(kThreads) k_zpass(Grid g, AxisPlan pz, const c
         a[c * cls + kyl * ls + sw<T>(z)] = v;
       });
   __syncthreads();
-  cplx<T>* res = fft_lines<T, P3>(a, pz, nd * kyb, tw, -1);
   double part = 0.0;
-  if (mode == Z_SOLVE) {
+  const int last_radix = (pz.code >> (4 * (pz.nstage - 1))) & 15u;
+  const bool fused = mode == Z_SOLVE && nd == 3 && last_radix == 2 && pz.nstage >= 2 &&
+                     kyb * nz <= 2048 / 3;
+  cplx<T>* res = a;
+  if (fused) {
+    const long long nfreq = (long long)nxh * ny * nz;
+    const double wgt = (kx == 0 || (2 * kx == g.nx)) ? 1.0 : 2.0;
+    fft_stages<T, P3>(a, pz, false, 0, pz.nstage - 1, 1, nd * kyb, tw, -1);
+    part = zpass_fused_mid<T>(a, nz, ls, cls, kyb, ky0, ny, nz, kx, tw, kplus, nfreq, wgt);
+    fft_stages<T, P3>(a, pz, true, 1, pz.nstage, 2, nd * kyb, tw, +1);
+  } else {
+    res = fft_lines<T, P3>(a, pz, nd * kyb, tw, -1);
+  }
+  if (mode == Z_SOLVE && !fused) {
     const long long nfreq = (long long)nxh * ny * nz;
     const double wgt = (kx == 0 || (2 * kx == g.nx)) ? 1.0 : 2.0;
     for (int idx0 = threadIdx.x; idx0 < per; idx0 += blockDim.x) {
