@@ -121,9 +121,13 @@ __host__ __device__ __forceinline__ int lds_stride(int n) {
 // thread owns at most kMaxPts / (R * 256) butterflies.
 constexpr int kMaxPts = 2048;
 
-template <typename T, int R>
-__device__ __forceinline__ void stockham_stage(cplx<T>* buf, int n, int ls, int nlines, int L,
-                                               const cplx<T>* tw, int sign) {
+// src(line, e) gives element e of a line; with in_place false the inputs
+// come from another buffer and the barrier between reads and writes is
+// skipped.
+template <typename T, int R, typename Src>
+__device__ __forceinline__ void stockham_stage_from(const Src& src, bool in_place, cplx<T>* buf,
+                                                    int n, int ls, int nlines, int L,
+                                                    const cplx<T>* tw, int sign) {
   constexpr int MAXIT = (kMaxPts / R + kThreads - 1) / kThreads;
   const int m = n / R;
   const int items = nlines * m;
@@ -138,10 +142,9 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int n, int ls, int 
       const int line = it / m;
       const int j = it - line * m;
       const int kk = j % L;
-      const cplx<T>* src = buf + line * ls;
 #pragma unroll
       for (int t = 0; t < R; ++t) {
-        cplx<T> a = src[sw<T>(j + t * m)];
+        cplx<T> a = src(line, j + t * m);
         if (t > 0) {
           // t*kk < R*L, so the index stays below n
           cplx<T> w = tw[t * kk * twstep];
@@ -154,7 +157,7 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int n, int ls, int 
       de[k] = (j / L) * L * R + kk;
     }
   }
-  __syncthreads();
+  if (in_place) __syncthreads();
 #pragma unroll
   for (int k = 0; k < MAXIT; ++k) {
     if (dst[k] >= 0) {
@@ -164,6 +167,14 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int n, int ls, int 
     }
   }
   __syncthreads();
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void stockham_stage(cplx<T>* buf, int n, int ls, int nlines, int L,
+                                               const cplx<T>* tw, int sign) {
+  stockham_stage_from<T, R>(
+      [&](int line, int e) { return buf[line * ls + sw<T>(e)]; }, true, buf, n, ls, nlines, L,
+      tw, sign);
 }
 
 // Runs all stages in place on `a` (caller synchronised after filling it);
@@ -635,9 +646,11 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
         S[yl * (nxh + 1) + kx] = v;
       });
   __syncthreads();
+  // Complex line j carries real rows 2j and 2j+1: X_a + i X_b, with the
+  // spectra extended by Hermitian symmetry.  The first Stockham stage reads
+  // its inputs this way straight from the tile S (no separate unpack pass).
   const int half = nx / 2;
-  for (int idx = threadIdx.x; idx < (kRows / 2) * nx; idx += blockDim.x) {
-    const int j = idx / nx, k = idx - j * nx;
+  auto packed = [&](int j, int k) -> cplx<T> {
     cplx<T> xa, xb;
     if (k <= half) {
       xa = S[(2 * j) * (nxh + 1) + k];
@@ -650,10 +663,15 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
       xa = conjg(S[(2 * j) * (nxh + 1) + (nx - k)]);
       xb = conjg(S[(2 * j + 1) * (nxh + 1) + (nx - k)]);
     }
-    a[j * lsx + sw<T>(k)] = {xa.re - xb.im, xa.im + xb.re};
-  }
-  __syncthreads();
-  cplx<T>* res = fft_lines<T, P3>(a, px, kRows / 2, tw, +1);
+    return {xa.re - xb.im, xa.im + xb.re};
+  };
+  const int R0 = px.code & 15u;
+  if (R0 == 8) stockham_stage_from<T, 8>(packed, false, a, nx, lsx, kRows / 2, 1, tw, +1);
+  else if (R0 == 4) stockham_stage_from<T, 4>(packed, false, a, nx, lsx, kRows / 2, 1, tw, +1);
+  else if (R0 == 2) stockham_stage_from<T, 2>(packed, false, a, nx, lsx, kRows / 2, 1, tw, +1);
+  else if constexpr (P3) stockham_stage_from<T, 3>(packed, false, a, nx, lsx, kRows / 2, 1, tw, +1);
+  fft_stages<T, P3>(a, px, false, 1, px.nstage, R0, kRows / 2, tw, +1);
+  cplx<T>* res = a;
   const T alpha = (mode == XI_PCG) ? T(st[ld].alpha) : T(0);
   const T beta = (mode == XI_PCG) ? T(st[ld].beta) : T(0);
   // later trips: the reads of 8 trips are issued before their use
