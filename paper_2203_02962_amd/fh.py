@@ -129,6 +129,13 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"libfh.so not found at {path}: run __graft_entry__.build() "
                            "or python paper_2203_02962_amd/build.py")
+    # libfh.so links the HIP runtime.  PyTorch (which provides the device
+    # memory and streams) ships its own copy; load it first so that both use
+    # one runtime.  The other way round, torch then finds no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
     sig = {
