@@ -467,7 +467,11 @@ size_t layout(fh_ctx* c, char* base, fh_ctx::Layout* Lout) {
   L.scal = (double*)take(sizeof(double) * 64);
   L.sysdot = (double*)take(sizeof(double) * nl);
   L.sysdot_part = (double*)take(sizeof(double) * nl * 64);
-  L.pair_part = (double*)take(sizeof(double) * (kPairChunks * 64 + 128));
+  // load-pair dot partials and results: one solve (kPairChunks chunks) or a
+  // batch group (64 chunks per microstructure), up to 8 x 8 pairs each
+  L.pair_part = (double*)take(sizeof(double) *
+                              std::max<size_t>(kPairChunks * 64 + 128,
+                                               (size_t)c->nms * (64 * 64 + 2 * 64)));
   L.mask = (int*)take(sizeof(int) * nl);
   L.phase0 = (uint8_t*)take((size_t)g.N);
   L.bytes = off;
@@ -1405,10 +1409,9 @@ int batch_group(fh_ctx* parent, const std::vector<int>& idx, const fh_system* sy
   // homogenized tensors (energy form, as fh_solve)
   if ((rc = apply_K(c, false, L.x, L.q, c->nload, F, nullptr, nullptr))) return pfail(rc);
   const int nchunk = 64;
-  double* part = nullptr;
-  double* dots = nullptr;
-  HIPCHK(parent, hipMalloc((void**)&part, sizeof(double) * (size_t)nms * nchunk * nload * nload));
-  HIPCHK(parent, hipMalloc((void**)&dots, sizeof(double) * (size_t)2 * nms * nload * nload));
+  // fh_solve_batch admits nload <= 8, the size the buffer is laid out for
+  double* part = L.pair_part;                                // nms x nchunk x nload^2
+  double* dots = part + (size_t)nms * nchunk * nload * nload;  // 2 x nms x nload^2
   hipError_t e1 = fh::launch_pair_dots(L.b, L.x, F, nload, nms, nchunk, part, dots, c->stream);
   hipError_t e2 = fh::launch_pair_dots(L.x, L.q, F, nload, nms, nchunk, part,
                                        dots + (size_t)nms * nload * nload, c->stream);
@@ -1416,8 +1419,6 @@ int batch_group(fh_ctx* parent, const std::vector<int>& idx, const fh_system* sy
   hipError_t e3 = hipMemcpyAsync(hd.data(), dots, hd.size() * sizeof(double),
                                  hipMemcpyDeviceToHost, c->stream);
   hipError_t e4 = hipStreamSynchronize(c->stream);
-  hipFree(part);
-  hipFree(dots);
   if (e1 || e2 || e3 || e4) return fail(parent, FH_EDEVICE, "batched C_hom reduction failed");
   const double solve_ms = ms_since(t1);
   for (int ms = 0; ms < nms; ++ms)

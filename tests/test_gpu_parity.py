@@ -268,6 +268,33 @@ def test_solve_is_bitwise_deterministic(fh):
     assert all(np.array_equal(a, b) for a, b in zip(u1, u2))
 
 
+def test_kernel_timing_counts(fh):
+    """Event timing of every launch, or of every 8th PCG iteration: the
+    launch counts, timed counts and totals are consistent, and timing does
+    not change the result."""
+    say("kernel timing")
+    wl, prob = _spheres_case(16, (2.0, 3.5), 100.0, 3)
+    ctx = _ctx(fh, wl)
+    rc0, st0 = ctx.solve(eta=1e-10)
+    H0 = ctx.get_homogenized()
+    rc1, st1 = ctx.solve(eta=1e-10, time_kernels=True, rebuild=True)
+    rc2, st2 = ctx.solve(eta=1e-10, time_kernels=True, time_sampled=True, rebuild=True)
+    assert rc0 == rc1 == rc2 == 0
+    assert st0["iterations"] == st1["iterations"] == st2["iterations"]
+    assert np.array_equal(ctx.get_homogenized(), H0)
+    assert sum(st0["kernel_launches"]) == 0 and sum(st0["kernel_issued"]) == 0
+    # every launch timed: issued == timed; one operator launch per iteration
+    assert st1["kernel_issued"] == st1["kernel_launches"]
+    n_op = st1["kernel_issued"][0]
+    assert n_op >= max(st1["iterations"])
+    # sampled: same launches issued, about an eighth of them timed
+    assert st2["kernel_issued"] == st1["kernel_issued"]
+    assert st2["kernel_launches"][0] == (n_op + 7) // 8
+    for k in range(7):
+        if st2["kernel_launches"][k]:
+            assert st2["kernel_ms"][k] > 0.0
+
+
 def test_breakdown_and_itmax_statuses(fh):
     say("statuses")
     wl, prob = _spheres_case(12, (1.5, 3.0), 100.0, 2)
