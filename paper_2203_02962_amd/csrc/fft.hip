@@ -121,13 +121,14 @@ __host__ __device__ __forceinline__ int lds_stride(int n) {
 // thread owns at most kMaxPts / (R * 256) butterflies.
 constexpr int kMaxPts = 2048;
 
-// src(line, e) gives element e of a line; with in_place false the inputs
-// come from another buffer and the barrier between reads and writes is
-// skipped.
-template <typename T, int R, typename Src>
-__device__ __forceinline__ void stockham_stage_from(const Src& src, bool in_place, cplx<T>* buf,
-                                                    int n, int ls, int nlines, int L,
-                                                    const cplx<T>* tw, int sign) {
+// src(line, e) gives element e of a line and sink(line, e, v) stores one;
+// with in_place false the inputs come from another buffer and the barrier
+// between reads and writes is skipped.  In the first stage (L = 1) every
+// twiddle is 1 and the table is not read.
+template <typename T, int R, typename Src, typename Sink>
+__device__ __forceinline__ void stockham_stage_io(const Src& src, const Sink& sink, bool in_place,
+                                                  int n, int nlines, int L, const cplx<T>* tw,
+                                                  int sign) {
   constexpr int MAXIT = (kMaxPts / R + kThreads - 1) / kThreads;
   const int m = n / R;
   const int items = nlines * m;
@@ -145,7 +146,7 @@ __device__ __forceinline__ void stockham_stage_from(const Src& src, bool in_plac
 #pragma unroll
       for (int t = 0; t < R; ++t) {
         cplx<T> a = src(line, j + t * m);
-        if (t > 0) {
+        if (t > 0 && L > 1) {
           // t*kk < R*L, so the index stays below n
           cplx<T> w = tw[t * kk * twstep];
           if (sign > 0) w.im = -w.im;
@@ -153,7 +154,7 @@ __device__ __forceinline__ void stockham_stage_from(const Src& src, bool in_plac
         }
         v[k][t] = a;
       }
-      dst[k] = line * ls;
+      dst[k] = line;
       de[k] = (j / L) * L * R + kk;
     }
   }
@@ -163,10 +164,19 @@ __device__ __forceinline__ void stockham_stage_from(const Src& src, bool in_plac
     if (dst[k] >= 0) {
       dft_small<T, R>(v[k], sign);
 #pragma unroll
-      for (int t = 0; t < R; ++t) buf[dst[k] + sw<T>(de[k] + t * L)] = v[k][t];
+      for (int t = 0; t < R; ++t) sink(dst[k], de[k] + t * L, v[k][t]);
     }
   }
   __syncthreads();
+}
+
+template <typename T, int R, typename Src>
+__device__ __forceinline__ void stockham_stage_from(const Src& src, bool in_place, cplx<T>* buf,
+                                                    int n, int ls, int nlines, int L,
+                                                    const cplx<T>* tw, int sign) {
+  stockham_stage_io<T, R>(
+      src, [&](int line, int e, cplx<T> v) { buf[line * ls + sw<T>(e)] = v; }, in_place, n,
+      nlines, L, tw, sign);
 }
 
 template <typename T, int R>
@@ -175,6 +185,18 @@ __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int n, int ls, int 
   stockham_stage_from<T, R>(
       [&](int line, int e) { return buf[line * ls + sw<T>(e)]; }, true, buf, n, ls, nlines, L,
       tw, sign);
+}
+
+// One stage of radix `R` (2, 3, 4 or 8, chosen at run time) with custom
+// input and output.
+template <typename T, bool P3, typename Src, typename Sink>
+__device__ __forceinline__ void stage_io_any(int R, const Src& src, const Sink& sink,
+                                             bool in_place, int n, int nlines, int L,
+                                             const cplx<T>* tw, int sign) {
+  if (R == 8) stockham_stage_io<T, 8>(src, sink, in_place, n, nlines, L, tw, sign);
+  else if (R == 4) stockham_stage_io<T, 4>(src, sink, in_place, n, nlines, L, tw, sign);
+  else if (R == 2) stockham_stage_io<T, 2>(src, sink, in_place, n, nlines, L, tw, sign);
+  else if constexpr (P3) stockham_stage_io<T, 3>(src, sink, in_place, n, nlines, L, tw, sign);
 }
 
 // Runs all stages in place on `a` (caller synchronised after filling it);
@@ -463,31 +485,49 @@ __global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan
   const int per = kyb * nz;
   const int ls = lds_stride<T>(nz);
   const int cls = kyb * ls;  // LDS stride between components
-  staged_fill<8, cplx<T>>(
-      nd * per,
-      [&](int idx) {
-        const int c = idx / per, rem = idx - c * per, kyl = rem / nz, z = rem - kyl * nz;
-        const int ky = ky0 + kyl;
-        cplx<T> v = {T(0), T(0)};
-        if (ky < ny) v = B[base + c * cstride + (long long)ky * nz + z];
-        return v;
-      },
-      [&](int idx, cplx<T> v) {
-        const int c = idx / per, rem = idx - c * per, kyl = rem / nz, z = rem - kyl * nz;
-        a[c * cls + kyl * ls + sw<T>(z)] = v;
-      });
-  __syncthreads();
-  double part = 0.0;
   const int last_radix = (pz.code >> (4 * (pz.nstage - 1))) & 15u;
   const bool fused = mode == Z_SOLVE && nd == 3 && last_radix == 2 && pz.nstage >= 2 &&
                      kyb * nz <= 2048 / 3;
+  // line l = c * kyb + kyl of the block is component c of frequency line ky0 + kyl
+  auto gsrc = [&](int l, int z) -> cplx<T> {
+    const int c = l / kyb, ky = ky0 + (l - c * kyb);
+    cplx<T> v = {T(0), T(0)};
+    if (ky < ny) v = B[base + c * cstride + (long long)ky * nz + z];
+    return v;
+  };
+  if (!fused) {
+    staged_fill<8, cplx<T>>(
+        nd * per,
+        [&](int idx) {
+          const int c = idx / per, rem = idx - c * per, kyl = rem / nz, z = rem - kyl * nz;
+          return gsrc(c * kyb + kyl, z);
+        },
+        [&](int idx, cplx<T> v) {
+          const int c = idx / per, rem = idx - c * per, kyl = rem / nz, z = rem - kyl * nz;
+          a[c * cls + kyl * ls + sw<T>(z)] = v;
+        });
+    __syncthreads();
+  }
+  double part = 0.0;
   cplx<T>* res = a;
   if (fused) {
+    // The first forward stage reads the lines from global memory and the
+    // last inverse stage writes them back: the butterflies of those stages
+    // touch runs of consecutive elements, so no staging pass is needed.
     const long long nfreq = (long long)nxh * ny * nz;
     const double wgt = (kx == 0 || (2 * kx == g.nx)) ? 1.0 : 2.0;
-    fft_stages<T, P3>(a, pz, false, 0, pz.nstage - 1, 1, nd * kyb, tw, -1);
+    const int R0 = pz.code & 15u;
+    auto lsrc = [&](int l, int z) { return a[l * ls + sw<T>(z)]; };
+    auto lsink = [&](int l, int z, cplx<T> v) { a[l * ls + sw<T>(z)] = v; };
+    auto gsink = [&](int l, int z, cplx<T> v) {
+      const int c = l / kyb, ky = ky0 + (l - c * kyb);
+      if (ky < ny) B[base + c * cstride + (long long)ky * nz + z] = v;
+    };
+    stage_io_any<T, P3>(R0, gsrc, lsink, false, nz, nd * kyb, 1, tw, -1);
+    fft_stages<T, P3>(a, pz, false, 1, pz.nstage - 1, R0, nd * kyb, tw, -1);
     part = zpass_fused_mid<T>(a, nz, ls, cls, kyb, ky0, ny, nz, kx, tw, kplus, nfreq, wgt);
-    fft_stages<T, P3>(a, pz, true, 1, pz.nstage, 2, nd * kyb, tw, +1);
+    fft_stages<T, P3>(a, pz, true, 1, pz.nstage - 1, 2, nd * kyb, tw, +1);
+    stage_io_any<T, P3>(R0, lsrc, gsink, true, nz, nd * kyb, nz / R0, tw, +1);
   } else {
     res = fft_lines<T, P3>(a, pz, nd * kyb, tw, -1);
   }
@@ -536,10 +576,13 @@ __global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan
     __syncthreads();
     res = fft_lines<T, P3>(res, pz, nd * kyb, tw, +1);
   }
-  for (int idx = threadIdx.x; idx < nd * per; idx += blockDim.x) {
-    const int c = idx / per, rem = idx - c * per, kyl = rem / nz, z = rem - kyl * nz;
-    const int ky = ky0 + kyl;
-    if (ky < ny) B[base + c * cstride + (long long)ky * nz + z] = res[c * cls + kyl * ls + sw<T>(z)];
+  if (!fused) {
+    for (int idx = threadIdx.x; idx < nd * per; idx += blockDim.x) {
+      const int c = idx / per, rem = idx - c * per, kyl = rem / nz, z = rem - kyl * nz;
+      const int ky = ky0 + kyl;
+      if (ky < ny)
+        B[base + c * cstride + (long long)ky * nz + z] = res[c * cls + kyl * ls + sw<T>(z)];
+    }
   }
   if (mode == Z_SOLVE && rz_part) {
     const double s = block_sum(part, red);
