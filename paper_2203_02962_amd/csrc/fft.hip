@@ -495,7 +495,18 @@ __global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan
     if (ky < ny) v = B[base + c * cstride + (long long)ky * nz + z];
     return v;
   };
-  if (!fused) {
+  // solve mode: the first forward stage reads the z lines from global memory
+  // and the last inverse stage writes them back (their butterflies touch runs
+  // of consecutive elements), so no staging pass is needed
+  const bool direct = mode == Z_SOLVE && pz.nstage >= 1;  // nz = 1 (2D) has no stage
+  auto lsrc = [&](int l, int z) { return a[l * ls + sw<T>(z)]; };
+  auto lsink = [&](int l, int z, cplx<T> v) { a[l * ls + sw<T>(z)] = v; };
+  auto gsink = [&](int l, int z, cplx<T> v) {
+    const int c = l / kyb, ky = ky0 + (l - c * kyb);
+    if (ky < ny) B[base + c * cstride + (long long)ky * nz + z] = v;
+  };
+  const int R0 = pz.code & 15u;
+  if (!direct) {
     staged_fill<8, cplx<T>>(
         nd * per,
         [&](int idx) {
@@ -511,23 +522,16 @@ __global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan
   double part = 0.0;
   cplx<T>* res = a;
   if (fused) {
-    // The first forward stage reads the lines from global memory and the
-    // last inverse stage writes them back: the butterflies of those stages
-    // touch runs of consecutive elements, so no staging pass is needed.
     const long long nfreq = (long long)nxh * ny * nz;
     const double wgt = (kx == 0 || (2 * kx == g.nx)) ? 1.0 : 2.0;
-    const int R0 = pz.code & 15u;
-    auto lsrc = [&](int l, int z) { return a[l * ls + sw<T>(z)]; };
-    auto lsink = [&](int l, int z, cplx<T> v) { a[l * ls + sw<T>(z)] = v; };
-    auto gsink = [&](int l, int z, cplx<T> v) {
-      const int c = l / kyb, ky = ky0 + (l - c * kyb);
-      if (ky < ny) B[base + c * cstride + (long long)ky * nz + z] = v;
-    };
     stage_io_any<T, P3>(R0, gsrc, lsink, false, nz, nd * kyb, 1, tw, -1);
     fft_stages<T, P3>(a, pz, false, 1, pz.nstage - 1, R0, nd * kyb, tw, -1);
     part = zpass_fused_mid<T>(a, nz, ls, cls, kyb, ky0, ny, nz, kx, tw, kplus, nfreq, wgt);
     fft_stages<T, P3>(a, pz, true, 1, pz.nstage - 1, 2, nd * kyb, tw, +1);
     stage_io_any<T, P3>(R0, lsrc, gsink, true, nz, nd * kyb, nz / R0, tw, +1);
+  } else if (direct) {
+    stage_io_any<T, P3>(R0, gsrc, lsink, false, nz, nd * kyb, 1, tw, -1);
+    fft_stages<T, P3>(a, pz, false, 1, pz.nstage, R0, nd * kyb, tw, -1);
   } else {
     res = fft_lines<T, P3>(a, pz, nd * kyb, tw, -1);
   }
@@ -574,9 +578,11 @@ __global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan
       }
     }
     __syncthreads();
-    res = fft_lines<T, P3>(res, pz, nd * kyb, tw, +1);
+    const int RL = (pz.code >> (4 * (pz.nstage - 1))) & 15u;
+    fft_stages<T, P3>(a, pz, false, 0, pz.nstage - 1, 1, nd * kyb, tw, +1);
+    stage_io_any<T, P3>(RL, lsrc, gsink, true, nz, nd * kyb, nz / RL, tw, +1);
   }
-  if (!fused) {
+  if (!direct) {
     for (int idx = threadIdx.x; idx < nd * per; idx += blockDim.x) {
       const int c = idx / per, rem = idx - c * per, kyl = rem / nz, z = rem - kyl * nz;
       const int ky = ky0 + kyl;
