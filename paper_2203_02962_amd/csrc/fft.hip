@@ -274,11 +274,11 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // ------------------------------------------------------------- x forward
 // grid (ceil(ny/16), nz, nload*nd).  Optionally r -= alpha q first.
-// Five waves per SIMD (at most 96 VGPRs) for power-of-two lengths: measured
-// 255 -> 231 us per 6-load launch at 128^3 in FP64 (the other passes are
-// slower that way); with radix-3 stages that budget would spill 27 registers.
+// Five waves per SIMD (at most 96 VGPRs): measured 255 -> 231 us per 6-load
+// launch at 128^3 in FP64 (the other passes are slower that way).  FP64 with
+// radix-3 stages would spill 27 registers in that budget and keeps four.
 template <typename T, bool P3>
-__global__ void __launch_bounds__(kThreads, P3 ? 4 : 5) k_xfwd(Grid g, AxisPlan px, const cplx<double>* twx,
+__global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && P3) ? 4 : 5) k_xfwd(Grid g, AxisPlan px, const cplx<double>* twx,
                                                   int mode, T* r, long long rstride, const T* q,
                                                   long long qstride, cplx<T>* A,
                                                   long long sstride, const PcgState* st) {
