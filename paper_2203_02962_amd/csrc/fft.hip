@@ -351,20 +351,24 @@ __global__ void __launch_bounds__(kThreads) k_yfwd(Grid g, AxisPlan py, const cp
   const int z0 = blockIdx.x * zb, kx = blockIdx.y;
   const long long base = (long long)ld * sstride;
   const int ls = lds_stride<T>(ny);
-  staged_fill<8, cplx<T>>(
-      zb * ny,
-      [&](int idx) {
-        const int zl = idx / ny, y = idx - zl * ny, z = z0 + zl;
-        cplx<T> v = {T(0), T(0)};
-        if (z < nz) v = A[base + (((long long)c * nz + z) * nxh + kx) * ny + y];
-        return v;
-      },
-      [&](int idx, cplx<T> v) {
-        const int zl = idx / ny, y = idx - zl * ny;
-        a[zl * ls + sw<T>(y)] = v;
-      });
-  __syncthreads();
-  cplx<T>* res = fft_lines<T, P3>(a, py, zb, tw, -1);
+  // the y lines are contiguous in A: the first stage reads them from HBM
+  auto gsrc = [&](int zl, int y) -> cplx<T> {
+    const int z = z0 + zl;
+    cplx<T> v = {T(0), T(0)};
+    if (z < nz) v = A[base + (((long long)c * nz + z) * nxh + kx) * ny + y];
+    return v;
+  };
+  auto lsink = [&](int l, int y, cplx<T> v) { a[l * ls + sw<T>(y)] = v; };
+  cplx<T>* res = a;
+  if (py.nstage >= 1) {
+    const int R0 = py.code & 15u;
+    stage_io_any<T, P3>(R0, gsrc, lsink, false, ny, zb, 1, tw, -1);
+    fft_stages<T, P3>(a, py, false, 1, py.nstage, R0, zb, tw, -1);
+  } else {
+    for (int idx = threadIdx.x; idx < zb * ny; idx += blockDim.x)
+      lsink(idx / ny, idx % ny, gsrc(idx / ny, idx % ny));
+    __syncthreads();
+  }
   const long long obase = base + ((long long)c * nxh + kx) * (long long)ny * nz;
   for (int idx = threadIdx.x; idx < zb * ny; idx += blockDim.x) {
     const int zl = idx % zb, ky = idx / zb, z = z0 + zl;
@@ -528,7 +532,7 @@ __global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan
     fft_stages<T, P3>(a, pz, false, 1, pz.nstage - 1, R0, nd * kyb, tw, -1);
     part = zpass_fused_mid<T>(a, nz, ls, cls, kyb, ky0, ny, nz, kx, tw, kplus, nfreq, wgt);
     fft_stages<T, P3>(a, pz, true, 1, pz.nstage - 1, 2, nd * kyb, tw, +1);
-    stage_io_any<T, P3>(R0, lsrc, gsink, true, nz, nd * kyb, nz / R0, tw, +1);
+    stage_io_any<T, P3>(R0, lsrc, gsink, false, nz, nd * kyb, nz / R0, tw, +1);
   } else if (direct) {
     stage_io_any<T, P3>(R0, gsrc, lsink, false, nz, nd * kyb, 1, tw, -1);
     fft_stages<T, P3>(a, pz, false, 1, pz.nstage, R0, nd * kyb, tw, -1);
@@ -580,7 +584,7 @@ __global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan
     __syncthreads();
     const int RL = (pz.code >> (4 * (pz.nstage - 1))) & 15u;
     fft_stages<T, P3>(a, pz, false, 0, pz.nstage - 1, 1, nd * kyb, tw, +1);
-    stage_io_any<T, P3>(RL, lsrc, gsink, true, nz, nd * kyb, nz / RL, tw, +1);
+    stage_io_any<T, P3>(RL, lsrc, gsink, false, nz, nd * kyb, nz / RL, tw, +1);
   }
   if (!direct) {
     for (int idx = threadIdx.x; idx < nd * per; idx += blockDim.x) {
@@ -627,10 +631,19 @@ __global__ void __launch_bounds__(kThreads) k_yinv(Grid g, AxisPlan py, const cp
         a[zl * ls + sw<T>(ky)] = v;
       });
   __syncthreads();
-  cplx<T>* res = fft_lines<T, P3>(a, py, zb, tw, +1);
-  for (int idx = threadIdx.x; idx < zb * ny; idx += blockDim.x) {
-    const int zl = idx / ny, y = idx - zl * ny, z = z0 + zl;
-    if (z < nz) A[base + (((long long)c * nz + z) * nxh + kx) * ny + y] = res[zl * ls + sw<T>(y)];
+  // the y lines are contiguous in A: the last stage writes them to HBM
+  auto lsrc = [&](int l, int y) { return a[l * ls + sw<T>(y)]; };
+  auto gsink = [&](int zl, int y, cplx<T> v) {
+    const int z = z0 + zl;
+    if (z < nz) A[base + (((long long)c * nz + z) * nxh + kx) * ny + y] = v;
+  };
+  if (py.nstage >= 1) {
+    const int RL = (py.code >> (4 * (py.nstage - 1))) & 15u;
+    fft_stages<T, P3>(a, py, false, 0, py.nstage - 1, 1, zb, tw, +1);
+    stage_io_any<T, P3>(RL, lsrc, gsink, false, ny, zb, ny / RL, tw, +1);
+  } else {
+    for (int idx = threadIdx.x; idx < zb * ny; idx += blockDim.x)
+      gsink(idx / ny, idx % ny, lsrc(idx / ny, idx % ny));
   }
 }
 
