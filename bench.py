@@ -165,11 +165,11 @@ def conduction_comparison():
         t0 = time.perf_counter()
         rc, st = c.solve(eta=1e-8, precision=prec, rebuild=True)
         torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
         H[name] = c.get_homogenized()
-        out[name] = {"ms": round((time.perf_counter() - t0) * 1000.0, 1), "rc": rc,
+        out[name] = {"ms": round(secs * 1000.0, 1), "rc": rc,
                      "iterations": st["iterations"], "sweeps": st["outer"],
-                     "dof_iter_per_s": st["dof"] * sum(st["iterations"]) /
-                     ((time.perf_counter() - t0))}
+                     "dof_iter_per_s": st["dof"] * sum(st["iterations"]) / secs}
     c.close()
     out["chom_rel_diff"] = float(np.abs(H["fp32_refined"] - H["fp64"]).max() /
                                  np.abs(H["fp64"]).max())
