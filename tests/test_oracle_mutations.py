@@ -2,7 +2,8 @@
 catch each one: a dropped sqrt(2)/2 on shear rows, Gauss points moved, a
 periodic shift taken the wrong way, a dropped quadrature weight, a sign slip in
 the right-hand side, an unnormalised inverse DFT, a zero-frequency block
-inverted instead of pseudo-inverted."""
+inverted instead of pseudo-inverted, and in the large-grid preconditioner a
+symbol built from the wrong rows or an unnormalised inverse FFT."""
 import sys
 
 import numpy as np
@@ -34,6 +35,7 @@ def _all_pin_checks():
         (pins.test_symbol_hex8_closed_form, ("elastic",)),
         (pins.test_preconditioner_is_dense_pseudo_inverse, ("hex8", "elastic", (4, 4, 3))),
         (pins.test_reference_equals_material_converges_in_one_iteration, ("hex8", "elastic", (5, 4, 4))),
+        (pins.test_stencil_symbol_and_fft_preconditioner_match_dense_forms, ()),
     ]
 
 
@@ -98,6 +100,21 @@ def test_catches_rhs_sign_slip(monkeypatch):
 
 def test_catches_unnormalised_inverse_dft(monkeypatch):
     monkeypatch.setattr(opre, "idft", lambda X, axes=None: odft._apply(X, +1, range(np.ndim(X))))
+    assert _caught()
+
+
+def test_catches_large_grid_symbol_from_wrong_rows(monkeypatch):
+    # the impulse response read at one node only, instead of at every
+    # neighbour of the impulse
+    orig = asm.operator_rows
+    monkeypatch.setattr(opre, "operator_rows",
+                        lambda prob, u, nodes: orig(prob, u, np.repeat(nodes[:1], len(nodes))))
+    assert _caught()
+
+
+def test_catches_large_grid_unnormalised_inverse_fft(monkeypatch):
+    fftn = np.fft.fftn
+    monkeypatch.setattr(np.fft, "ifftn", lambda a: np.conj(fftn(np.conj(a))))
     assert _caught()
 
 
