@@ -246,6 +246,7 @@ typedef struct fh_batch_report {
   int nsys[FH_MAX_GROUPS];
   int kz[FH_MAX_GROUPS], zb[FH_MAX_GROUPS], kyb[FH_MAX_GROUPS]; /* tuned shapes */
   double tune_ms[FH_MAX_GROUPS], setup_ms[FH_MAX_GROUPS], solve_ms[FH_MAX_GROUPS];
+  int xrows[FH_MAX_GROUPS]; /* tuned rows per block of the FP32 x passes     */
 } fh_batch_report;
 
 /* Solve nsys systems (elasticity, FH_HEX8) for the nload strains E (host,

@@ -1232,6 +1232,7 @@ int autotune(fh_ctx* c, int nload_all, double* tune_ms) {
   fh_ctx::Layout& L = c->L;
   HIPCHK(c, fh::launch_fill<float>(L.p32, 0.f, F * nload_total, c->stream));
   HIPCHK(c, fh::launch_fill<float>(L.q32, 0.f, F * nload_total, c->stream));
+  HIPCHK(c, fh::launch_fill<float>(L.r32, 0.f, F * nload_total, c->stream));
   const int reps = 3;
   int best = g.kz;
   double bt = 1e30;
@@ -1270,6 +1271,23 @@ int autotune(fh_ctx* c, int nload_all, double* tune_ms) {
     if (t < bt) { bt = t; best = kyb; }
   }
   g.kyb = best;
+  // rows per block of the FP32 x passes (forward and inverse timed together)
+  best = 16;
+  bt = 1e30;
+  for (int xr : {16, 32}) {
+    if (xr == 32 && g.nx > 128) continue;
+    g.xrows = xr;
+    const double t = time_launches(c, [&] {
+      if (fh::launch_xfwd<float>(g, c->px, c->twx, fh::XF_PLAIN, L.r32, F, nullptr, 0, L.A32, S,
+                                 nload_total, nullptr, c->stream) != hipSuccess)
+        return FH_EDEVICE;
+      return fh::launch_xinv<float>(g, c->px, c->twx, fh::XI_PLAIN, L.A32, S, L.q32, nullptr,
+                                    nullptr, F, nload_total, nullptr,
+                                    c->stream) == hipSuccess ? FH_OK : FH_EDEVICE;
+    }, reps);
+    if (t < bt) { bt = t; best = xr; }
+  }
+  g.xrows = best;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   *tune_ms = ms_since(t0);
   return FH_OK;
@@ -1463,6 +1481,7 @@ int batch_group(fh_ctx* parent, const std::vector<int>& idx, const fh_system* sy
     rep->kz[gi] = c->g.kz;
     rep->zb[gi] = c->g.zb;
     rep->kyb[gi] = c->g.kyb;
+    rep->xrows[gi] = c->g.xrows;
     rep->tune_ms[gi] = tune_ms;
     rep->setup_ms[gi] = setup_ms;
     rep->solve_ms[gi] = solve_ms;

@@ -27,8 +27,15 @@
 
 namespace fh {
 
-constexpr int kRows = 16;   // rows per block in x passes (8 complex lines)
 constexpr int kThreads = 256;
+// x passes: KR real rows per block, two per complex line, so KR/2 * nx <=
+// 2048 points.  16 rows always fit (nx <= 256); FP32 blocks of 16 rows move
+// half the bytes of FP64 ones, and 32 rows (nx <= 128) can be chosen by the
+// autotuner.
+template <typename T>
+static int xpass_rows(const Grid& g) {
+  return (sizeof(T) == 4 && g.xrows == 32 && g.nx <= 128) ? 32 : 16;
+}
 
 template <typename T>
 __device__ __forceinline__ cplx<T> conjg(cplx<T> a) { return {a.re, -a.im}; }
@@ -277,7 +284,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // Five waves per SIMD (at most 96 VGPRs): measured 255 -> 231 us per 6-load
 // launch at 128^3 in FP64 (the other passes are slower that way).  FP64 with
 // radix-3 stages would spill 27 registers in that budget and keeps four.
-template <typename T, bool P3>
+template <typename T, bool P3, int kRows>
 __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && P3) ? 4 : 5) k_xfwd(Grid g, AxisPlan px, const cplx<double>* twx,
                                                   int mode, T* r, long long rstride, const T* q,
                                                   long long qstride, cplx<T>* A,
@@ -649,7 +656,7 @@ __global__ void __launch_bounds__(kThreads) k_yinv(Grid g, AxisPlan py, const cp
 
 // ------------------------------------------------------------- x inverse
 // grid (ceil(ny/16), nz, nload*nd).  LDS: tw[nx], a[8 nx], S[16 nxh].
-template <typename T, bool P3>
+template <typename T, bool P3, int kRows>
 __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cplx<double>* twx,
                                                   int mode, const cplx<T>* A, long long sstride,
                                                   T* out, T* x, T* p, long long fstride,
@@ -675,7 +682,7 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
   const int lsx = lds_stride<T>(nx);
   cplx<T>* a = tw + nx;
-  cplx<T>* S = a + (kRows / 2) * lsx;  // 16 x nxh raw tile, row stride nxh + 1
+  cplx<T>* S = a + (kRows / 2) * lsx;  // kRows x nxh raw tile, row stride nxh + 1
   load_twiddles(tw, twx, nx);
   // PCG mode: the reads of p and x for the first 8 trips of the output loop
   // are issued here, before the spectrum tile, and land during the FFT
@@ -842,17 +849,20 @@ hipError_t launch_xfwd(const Grid& g, const AxisPlan& px, const cplx<double>* tw
                        T* r, long long rstride, const T* q, long long qstride, cplx<T>* A,
                        long long sstride, int nload, const PcgState* st, hipStream_t s) {
   const bool P3K = px.n % 3 == 0;
+  const int kRows = xpass_rows<T>(g);
   dim3 grid((g.ny + kRows - 1) / kRows, g.nz, nload * g.nd);
   size_t lds = sizeof(cplx<T>) * (size_t)(g.nx + (kRows / 2) * lds_stride<T>(g.nx));
-  if (lds > 65536)
-    hipFuncSetAttribute(P3K ? (const void*)k_xfwd<T, true> : (const void*)k_xfwd<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
-  if (P3K)
-    hipLaunchKernelGGL((k_xfwd<T, true>), grid, dim3(kThreads), lds, s, g, px, twx, mode, r, rstride, q,
-                     qstride, A, sstride, st);
-  else
-    hipLaunchKernelGGL((k_xfwd<T, false>), grid, dim3(kThreads), lds, s, g, px, twx, mode, r, rstride, q,
-                     qstride, A, sstride, st);
+  auto go = [&](auto kern) {
+    if (lds > 65536)
+      hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, s, g, px, twx, mode, r, rstride, q,
+                       qstride, A, sstride, st);
+  };
+  if (kRows == 32) {
+    if (P3K) go(k_xfwd<T, true, 32>); else go(k_xfwd<T, false, 32>);
+  } else {
+    if (P3K) go(k_xfwd<T, true, 16>); else go(k_xfwd<T, false, 16>);
+  }
   return hipGetLastError();
 }
 
@@ -945,18 +955,21 @@ hipError_t launch_xinv(const Grid& g, const AxisPlan& px, const cplx<double>* tw
                        const cplx<T>* A, long long sstride, T* out, T* x, T* p,
                        long long fstride, int nload, const PcgState* st, hipStream_t s) {
   const bool P3K = px.n % 3 == 0;
+  const int kRows = xpass_rows<T>(g);
   dim3 grid((g.ny + kRows - 1) / kRows, g.nz, nload * g.nd);
   size_t lds = sizeof(cplx<T>) * (size_t)(g.nx + (kRows / 2) * lds_stride<T>(g.nx) +
                                           kRows * (g.nxh + 1));
-  if (lds > 65536)
-    hipFuncSetAttribute(P3K ? (const void*)k_xinv<T, true> : (const void*)k_xinv<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
-  if (P3K)
-    hipLaunchKernelGGL((k_xinv<T, true>), grid, dim3(kThreads), lds, s, g, px, twx, mode, A, sstride, out,
-                     x, p, fstride, st);
-  else
-    hipLaunchKernelGGL((k_xinv<T, false>), grid, dim3(kThreads), lds, s, g, px, twx, mode, A, sstride, out,
-                     x, p, fstride, st);
+  auto go = [&](auto kern) {
+    if (lds > 65536)
+      hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, s, g, px, twx, mode, A, sstride, out, x,
+                       p, fstride, st);
+  };
+  if (kRows == 32) {
+    if (P3K) go(k_xinv<T, true, 32>); else go(k_xinv<T, false, 32>);
+  } else {
+    if (P3K) go(k_xinv<T, true, 16>); else go(k_xinv<T, false, 16>);
+  }
   return hipGetLastError();
 }
 

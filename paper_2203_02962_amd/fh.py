@@ -109,13 +109,14 @@ class fh_batch_report(ctypes.Structure):
                 ("zb", ctypes.c_int * FH_MAX_GROUPS), ("kyb", ctypes.c_int * FH_MAX_GROUPS),
                 ("tune_ms", ctypes.c_double * FH_MAX_GROUPS),
                 ("setup_ms", ctypes.c_double * FH_MAX_GROUPS),
-                ("solve_ms", ctypes.c_double * FH_MAX_GROUPS)]
+                ("solve_ms", ctypes.c_double * FH_MAX_GROUPS),
+                ("xrows", ctypes.c_int * FH_MAX_GROUPS)]
 
     def as_dict(self):
         g = self.ngroups
         return [dict(n=list(self.n[i]), nsys=self.nsys[i], kz=self.kz[i], zb=self.zb[i],
-                     kyb=self.kyb[i], tune_ms=self.tune_ms[i], setup_ms=self.setup_ms[i],
-                     solve_ms=self.solve_ms[i]) for i in range(g)]
+                     kyb=self.kyb[i], xrows=self.xrows[i], tune_ms=self.tune_ms[i],
+                     setup_ms=self.setup_ms[i], solve_ms=self.solve_ms[i]) for i in range(g)]
 
 
 _lib = None
