@@ -459,6 +459,62 @@ __device__ double zpass_fused_mid(cplx<T>* a, int n, int ls, int cls, int kyb, i
   return part;
 }
 
+// Scalar problems (one component): the same fusion for a last radix R of
+// 2, 4 or 8.  The solve is a multiplication per frequency, so the R outputs
+// of a forward butterfly are exactly the R inputs of the matching inverse
+// butterfly and never leave the thread.
+template <typename T, int R>
+__device__ double zpass_fused_mid_scalar(cplx<T>* a, int n, int ls, int kyb, int ky0, int ny,
+                                         int nz, int kx, const cplx<T>* tw, const T* kplus,
+                                         double wgt) {
+  constexpr int MAXIT = (2048 / R + kThreads - 1) / kThreads;  // kyb * n <= 2048
+  const int m = n / R;
+  const int items = kyb * m;
+  cplx<T> v[MAXIT][R];
+  int jj[MAXIT], kyl_[MAXIT];
+#pragma unroll
+  for (int k = 0; k < MAXIT; ++k) {
+    const int it = threadIdx.x + k * kThreads;
+    kyl_[k] = -1;
+    if (it < items) {
+      const int kyl = it / m, j = it - kyl * m;
+      const cplx<T>* src = a + kyl * ls;
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        cplx<T> x = src[sw<T>(j + t * m)];
+        if (t > 0) x = cmul(x, tw[t * j]);  // last forward stage: L = n/R
+        v[k][t] = x;
+      }
+      dft_small<T, R>(v[k], -1);  // outputs at j + t m
+      jj[k] = j;
+      kyl_[k] = kyl;
+    }
+  }
+  __syncthreads();
+  double part = 0.0;
+#pragma unroll
+  for (int k = 0; k < MAXIT; ++k) {
+    if (kyl_[k] < 0) continue;
+    const int j = jj[k], kyl = kyl_[k], ky = ky0 + kyl;
+    if (ky < ny) {
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const T kp = kplus[((long long)kx * ny + ky) * nz + j + t * m];
+        const cplx<T> r = v[k][t];
+        part += wgt * (double)kp * ((double)r.re * r.re + (double)r.im * r.im);
+        v[k][t] = {kp * r.re, kp * r.im};
+      }
+    }
+    // first inverse stage (radix R, L = 1, no twiddles): outputs at jR + t
+    dft_small<T, R>(v[k], +1);
+    cplx<T>* dst = a + kyl * ls;
+#pragma unroll
+    for (int t = 0; t < R; ++t) dst[sw<T>(j * R + t)] = v[k][t];
+  }
+  __syncthreads();
+  return part;
+}
+
 // ------------------------------------------------ z forward (+ solve + inverse)
 // grid (ceil(ny/kyb), nxh, nload).  Dynamic LDS: tw[nz], a/b[nd*kyb*nz].
 // Power-of-two lengths run four waves per SIMD (at most 128 VGPRs, 7 spilled
@@ -497,8 +553,9 @@ __global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan
   const int ls = lds_stride<T>(nz);
   const int cls = kyb * ls;  // LDS stride between components
   const int last_radix = (pz.code >> (4 * (pz.nstage - 1))) & 15u;
-  const bool fused = mode == Z_SOLVE && nd == 3 && last_radix == 2 && pz.nstage >= 2 &&
-                     kyb * nz <= 2048 / 3;
+  const bool fused = mode == Z_SOLVE && pz.nstage >= 2 &&
+                     ((nd == 3 && last_radix == 2 && kyb * nz <= 2048 / 3) ||
+                      (nd == 1 && (last_radix == 2 || last_radix == 4 || last_radix == 8)));
   // line l = c * kyb + kyl of the block is component c of frequency line ky0 + kyl
   auto gsrc = [&](int l, int z) -> cplx<T> {
     const int c = l / kyb, ky = ky0 + (l - c * kyb);
@@ -537,8 +594,15 @@ __global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan
     const double wgt = (kx == 0 || (2 * kx == g.nx)) ? 1.0 : 2.0;
     stage_io_any<T, P3>(R0, gsrc, lsink, false, nz, nd * kyb, 1, tw, -1);
     fft_stages<T, P3>(a, pz, false, 1, pz.nstage - 1, R0, nd * kyb, tw, -1);
-    part = zpass_fused_mid<T>(a, nz, ls, cls, kyb, ky0, ny, nz, kx, tw, kplus, nfreq, wgt);
-    fft_stages<T, P3>(a, pz, true, 1, pz.nstage - 1, 2, nd * kyb, tw, +1);
+    if (nd == 3)
+      part = zpass_fused_mid<T>(a, nz, ls, cls, kyb, ky0, ny, nz, kx, tw, kplus, nfreq, wgt);
+    else if (last_radix == 2)
+      part = zpass_fused_mid_scalar<T, 2>(a, nz, ls, kyb, ky0, ny, nz, kx, tw, kplus, wgt);
+    else if (last_radix == 4)
+      part = zpass_fused_mid_scalar<T, 4>(a, nz, ls, kyb, ky0, ny, nz, kx, tw, kplus, wgt);
+    else
+      part = zpass_fused_mid_scalar<T, 8>(a, nz, ls, kyb, ky0, ny, nz, kx, tw, kplus, wgt);
+    fft_stages<T, P3>(a, pz, true, 1, pz.nstage - 1, last_radix, nd * kyb, tw, +1);
     stage_io_any<T, P3>(R0, lsrc, gsink, false, nz, nd * kyb, nz / R0, tw, +1);
   } else if (direct) {
     stage_io_any<T, P3>(R0, gsrc, lsink, false, nz, nd * kyb, 1, tw, -1);

@@ -69,6 +69,9 @@ CASES = [
     ("hex8", "scalar", (12, 18, 6), "iso", (1.0, 0.8, 1.2)),
     ("hex8", "scalar", (24, 12, 18), "iso", None),
     ("hex8", "scalar", (36, 18, 24), "field", None),
+    # z lengths whose plans end in radix 8 and 4 (fused scalar z pass)
+    ("hex8", "scalar", (6, 4, 64), "field", None),
+    ("hex8", "scalar", (4, 6, 32), "iso", (1.0, 0.8, 1.2)),
     ("tri2", "scalar", (12, 18), "phase", None),
     ("tri2", "elastic", (12, 6), "phase", None),
     ("quad4", "elastic", (12, 8), "phase", (1.0, 0.7)),
