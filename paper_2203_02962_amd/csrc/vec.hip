@@ -187,24 +187,32 @@ hipError_t launch_field_sum(const double* x, long long n, double* part, int nb, 
 // shuffles and one barrier (a fixed tree, so the result is deterministic);
 // chunks are summed in a fixed order by k_pair_dots_sum.
 constexpr int kPairMax = 8;
+// G is a template argument so that the G x G accumulators stay in registers
+// (with a run-time G the array is indexed dynamically and lives in scratch).
+template <int G>
 __global__ void __launch_bounds__(256) k_pair_dots(const double* A, const double* B, long long F,
-                                                   int G, int nchunk, double* part) {
-  __shared__ double sh[4][kPairMax * kPairMax];
+                                                   int nchunk, double* part) {
+  __shared__ double sh[4][G * G];
   const int ms = blockIdx.y, chunk = blockIdx.x;
   const long long len = (F + nchunk - 1) / nchunk;
   const long long k0 = chunk * len, k1 = k0 + len < F ? k0 + len : F;
-  double acc[kPairMax * kPairMax];
+  double acc[G * G];
+#pragma unroll
   for (int t = 0; t < G * G; ++t) acc[t] = 0.0;
   for (long long k = k0 + threadIdx.x; k < k1; k += 256) {
-    double a[kPairMax], b[kPairMax];
+    double a[G], b[G];
+#pragma unroll
     for (int i = 0; i < G; ++i) {
       a[i] = A[((long long)ms * G + i) * F + k];
       b[i] = B[((long long)ms * G + i) * F + k];
     }
+#pragma unroll
     for (int i = 0; i < G; ++i)
+#pragma unroll
       for (int j = 0; j < G; ++j) acc[i * G + j] += a[i] * b[j];
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
   for (int t = 0; t < G * G; ++t) {
     double v = acc[t];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -215,19 +223,31 @@ __global__ void __launch_bounds__(256) k_pair_dots(const double* A, const double
   if (t < G * G)
     part[((long long)ms * nchunk + chunk) * G * G + t] = ((sh[0][t] + sh[1][t]) + sh[2][t]) + sh[3][t];
 }
+// Chunk sums in a fixed order: thread i of a block adds chunks i, i + 256, ...
+// of one entry, then the 256 partial sums are added pairwise (fixed tree).
 __global__ void k_pair_dots_sum(const double* part, int nchunk, int GG, double* out) {
-  const int ms = blockIdx.x;
-  for (int t = threadIdx.x; t < GG; t += blockDim.x) {
-    double v = 0.0;
-    for (int c = 0; c < nchunk; ++c) v += part[((long long)ms * nchunk + c) * GG + t];
-    out[(long long)ms * GG + t] = v;
-  }
+  __shared__ double sh[256];
+  const int ms = blockIdx.y, t = blockIdx.x;
+  double v = 0.0;
+  for (int c = threadIdx.x; c < nchunk; c += 256) v += part[((long long)ms * nchunk + c) * GG + t];
+  const double tot = block_sum_fixed(v, sh);
+  if (threadIdx.x == 0) out[(long long)ms * GG + t] = tot;
 }
 hipError_t launch_pair_dots(const double* A, const double* B, long long F, int G, int nms,
                             int nchunk, double* part, double* out, hipStream_t s) {
-  if (G > kPairMax) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pair_dots, dim3(nchunk, nms), dim3(256), 0, s, A, B, F, G, nchunk, part);
-  hipLaunchKernelGGL(k_pair_dots_sum, dim3(nms), dim3(64), 0, s, part, nchunk, G * G, out);
+  if (G < 1 || G > kPairMax) return hipErrorInvalidValue;
+  const dim3 grid(nchunk, nms);
+  switch (G) {
+    case 1: hipLaunchKernelGGL(k_pair_dots<1>, grid, dim3(256), 0, s, A, B, F, nchunk, part); break;
+    case 2: hipLaunchKernelGGL(k_pair_dots<2>, grid, dim3(256), 0, s, A, B, F, nchunk, part); break;
+    case 3: hipLaunchKernelGGL(k_pair_dots<3>, grid, dim3(256), 0, s, A, B, F, nchunk, part); break;
+    case 4: hipLaunchKernelGGL(k_pair_dots<4>, grid, dim3(256), 0, s, A, B, F, nchunk, part); break;
+    case 5: hipLaunchKernelGGL(k_pair_dots<5>, grid, dim3(256), 0, s, A, B, F, nchunk, part); break;
+    case 6: hipLaunchKernelGGL(k_pair_dots<6>, grid, dim3(256), 0, s, A, B, F, nchunk, part); break;
+    case 7: hipLaunchKernelGGL(k_pair_dots<7>, grid, dim3(256), 0, s, A, B, F, nchunk, part); break;
+    default: hipLaunchKernelGGL(k_pair_dots<8>, grid, dim3(256), 0, s, A, B, F, nchunk, part); break;
+  }
+  hipLaunchKernelGGL(k_pair_dots_sum, dim3(G * G, nms), dim3(256), 0, s, part, nchunk, G * G, out);
   return hipGetLastError();
 }
 
