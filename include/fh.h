@@ -114,7 +114,7 @@ typedef struct fh_opts {
                        (0 = sqrt(eta) when eta >= 1e-6, else 1e-4)                */
   const double *guess_dev; /* initial fluctuation u_(0) of Alg. 1 for every load
                        case (device, nload x nd x N; NULL = zero).  It is shifted
-                       to zero mean per component and judged: a load case keeps
+                       to zero mean per component and screened: a load case keeps
                        it only if r0.M r0 < b.M b (r0 = b - K u_(0)), else it
                        starts from zero.  The stopping test stays relative to
                        b.M b, so results are comparable with zero starts.       */
@@ -134,7 +134,7 @@ typedef struct fh_stats {
   long long kernel_launches[FH_K_NCLASS];
   int guess_used[FH_MAX_LOADS];   /* 1 if the initial guess was kept          */
   double guess_res[FH_MAX_LOADS]; /* sqrt(r0.M r0 / b.M b) of the guess       */
-  double guess_ms;                /* warm-start inference + judge             */
+  double guess_ms;                /* warm-start inference + screen             */
   long long kernel_issued[FH_K_NCLASS]; /* launches per class, timed or not
                                            (kernel_launches counts the timed
                                            ones, FH_FLAG_TIME_SAMPLED)       */
@@ -188,7 +188,7 @@ int fh_solve(fh_ctx *ctx, const fh_opts *opt, fh_stats *st);
 
 /* Learned warm start (fh_net.h): with FH_FLAG_WARM_START, fh_solve runs the
  * network on the phase field and takes u_(0) = (l/n) sum_j E_j O_j, shifted
- * to zero mean, as initial guess of every load case (judged as guess_dev).
+ * to zero mean, as initial guess of every load case (screened as guess_dev).
  * Needs 3D elasticity with FH_HEX8 on a cubic n^3 grid equal to the
  * network's, cubic cell, two isotropic phases (0 = matrix, 1 = inclusion);
  * gamma = log10(C1[0][0] / C0[0][0]) / 3.  The network must outlive its use;

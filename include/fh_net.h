@@ -6,7 +6,7 @@
  * u_(0) of the Newton scheme (Alg. 1), zero for a linear material.  The
  * warm start replaces that zero by the output of a small 3D convolutional
  * encoder-decoder evaluated on the phase field; PCG from zero stays the
- * fallback and the judge (fh_set_warm_start in fh.h).  Nothing of the
+ * fallback and the screen (fh_set_warm_start in fh.h).  Nothing of the
  * network is in the paper; its definition:
  *
  *   Input features per voxel: chi = [phase == 1], gamma chi, gamma, where

@@ -20,7 +20,7 @@ slow, independent algorithms:
   * the homogenized tensor as the energy (bilinear) form over quadrature
     points, and the stress average as a diagnostic (homog.py);
   * PCG from an initial guess u0 (the starting point of Alg. 1) with the
-    warm-start judge (pcg.py), and the learned warm start's network, loss
+    warm-start screen (pcg.py), and the learned warm start's network, loss
     and Adam step in FP64, optionally rounding stored tensors to BF16 as
     the GPU stores them (convnet.py).
 

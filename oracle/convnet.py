@@ -5,7 +5,7 @@ The paper solves every microstructure from the initial guess u0 = 0 (the
 Newton scheme of Alg. 1 starts from a given u_(0); a linear problem is one
 PCG solve from it).  The warm start replaces that zero by the output of a
 small network evaluated on the phase field; PCG from zero stays the fallback
-and the judge.  Nothing of the network is in the paper, so this module is
+and the screen.  Nothing of the network is in the paper, so this module is
 the definition the GPU path is checked against:
 
   * features per voxel: chi = [phase == 1], gamma * chi, gamma, with

@@ -84,8 +84,8 @@ def pcg(apply_K, apply_M, b: np.ndarray, eta: float, itmax: int = 10000,
     return res
 
 
-def judged_guess(apply_K, apply_M, b: np.ndarray, x0: np.ndarray, nd: int):
-    """Warm-start judge: keep the zero-mean guess only if its residual has a
+def screened_guess(apply_K, apply_M, b: np.ndarray, x0: np.ndarray, nd: int):
+    """Warm-start screen: keep the zero-mean guess only if its residual has a
     smaller M-norm than the zero start's (r.M r < b.M b).  Returns
     (accepted, guess or zeros, b.M b, r0.M r0)."""
     b = np.asarray(b, dtype=float)

@@ -893,7 +893,7 @@ int pcg64(fh_ctx* c, int nload, double eta, int itmax, int poll, std::vector<fh:
   return pcg_run<double>(c, nload, bf, eta, itmax, poll, std::vector<int>(nload, 1), out);
 }
 
-// Plain FP64 solve from the judged initial guess in L.x, whose residual is in
+// Plain FP64 solve from the screened initial guess in L.x, whose residual is in
 // L.r: rr[j] = r0.M r0 of the starting point, rb[j] = b.M b.  The stopping
 // test stays relative to b.M b (rho <= eta^2 rb); load cases that already
 // meet it do no iteration.  Reported residuals are relative to b.
@@ -1056,7 +1056,7 @@ void record_history(fh_ctx* c, const std::vector<fh::PcgState>& hs, int nload,
 }
 
 // Initial guess for fh_solve (opts.guess_dev or the learned warm start) into
-// L.x, shifted to zero mean per component, and the judge: rb = b.M b, rr =
+// L.x, shifted to zero mean per component, and the screen: rb = b.M b, rr =
 // r0.M r0 of the kept starting point (a load case whose guess is not better
 // than zero restarts from zero, rr = rb).  L.r holds the starting residual.
 int prepare_guess(fh_ctx* c, const fh_opts& o, std::vector<double>& rb,

@@ -56,8 +56,9 @@ struct Grid {
   long long phase_stride, kplus_stride;
   int lm_stride;
   // launch shapes (0 = default): operator z-chunk, y-pass lines per block,
-  // z-pass ky lines per block -- set by the autotuner for batched solves
-  int kz, zb, kyb;
+  // z-pass ky lines per block, FP32 x-pass rows per block (16 or 32) -- set
+  // by the autotuner for batched solves
+  int kz, zb, kyb, xrows;
 };
 
 // FFT plan for one axis length: radix of stage i (applied first to last) in

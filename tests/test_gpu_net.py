@@ -38,7 +38,7 @@ import pytest
 import oracle
 from oracle import convnet as cn
 from oracle.assembly import assemble_stiffness, rhs
-from oracle.pcg import judged_guess, pcg
+from oracle.pcg import screened_guess, pcg
 from oracle.precond import Preconditioner
 from synth import batch_workload
 
@@ -246,7 +246,7 @@ def test_initial_guess_solve_matches_oracle(fh, precision):
             g = 50.0 * np.abs(xs).max() * rng.standard_normal(xs.size)
         else:
             g = np.zeros_like(xs)
-        ok, x0, rb, rx = judged_guess(AK, M.apply, b, g, nd)
+        ok, x0, rb, rx = screened_guess(AK, M.apply, b, g, nd)
         res = pcg(AK, M.apply, b, 1e-10, x0=x0, nd=nd, rho_ref=rb)
         guesses.append(g)
         ref.append((ok, np.sqrt(rx / rb), res))
@@ -276,7 +276,7 @@ def test_initial_guess_solve_matches_oracle(fh, precision):
 
 
 def test_warm_start_flag_uses_network_guess(fh):
-    """FH_FLAG_WARM_START takes the network's guess through the judge: the
+    """FH_FLAG_WARM_START takes the network's guess through the screen: the
     result equals an explicit-guess solve with the same guess."""
     from paper_2203_02962_amd.runner import setup_context
     say("warm start flag")

@@ -482,14 +482,14 @@ def test_stencil_symbol_and_fft_preconditioner_match_dense_forms():
         assert np.abs(z1 - z2).max() < 1e-12 * np.abs(z1).max()
 
 
-# ------------------------------------------------ initial guess and judge
+# ------------------------------------------------ initial guess and screen
 
-def test_warm_started_pcg_reaches_dense_solution_and_judge():
+def test_warm_started_pcg_reaches_dense_solution_and_screen():
     """A guess u0 (the initial displacement of the Newton scheme of Alg. 1):
     PCG from it with the test relative to b.M b reaches the minimum-norm
     dense solution; the exact solution as guess needs no iteration; the
-    judge accepts a good guess and rejects a bad one."""
-    from oracle.pcg import judged_guess
+    screen accepts a good guess and rejects a bad one."""
+    from oracle.pcg import screened_guess
     rng = np.random.default_rng(41)
     n = (4, 4, 4)
     phase = rng.integers(0, 2, size=n[::-1])
@@ -502,12 +502,12 @@ def test_warm_started_pcg_reaches_dense_solution_and_judge():
     AK = lambda v: K @ v  # noqa: E731
     nd = prob.ndof_node
     # exact solution shifted by a constant: accepted, zero iterations
-    ok, x0, rb, rx = judged_guess(AK, M.apply, b, x_ls + 3.0, nd)
+    ok, x0, rb, rx = screened_guess(AK, M.apply, b, x_ls + 3.0, nd)
     assert ok and rx < 1e-20 * rb
     res = pcg(AK, M.apply, b, 1e-10, x0=x0, nd=nd, rho_ref=rb)
     assert res.iterations == 0 and np.abs(res.x - x_ls).max() < 1e-12 * np.abs(x_ls).max()
     # perturbed solution: accepted, converges to the same point in fewer steps
-    ok, x0, rb, rx = judged_guess(AK, M.apply, b, x_ls + 0.01 * np.abs(x_ls).max() *
+    ok, x0, rb, rx = screened_guess(AK, M.apply, b, x_ls + 0.01 * np.abs(x_ls).max() *
                                   rng.standard_normal(b.size), nd)
     assert ok and rx < rb
     warm = pcg(AK, M.apply, b, 1e-12, x0=x0, nd=nd, rho_ref=rb)
@@ -516,5 +516,5 @@ def test_warm_started_pcg_reaches_dense_solution_and_judge():
     assert warm.iterations < cold.iterations
     assert warm.history[-1] ** 2 * warm.rho0 <= (1e-12) ** 2 * rb * (1 + 1e-12)
     # a guess far worse than zero is rejected
-    ok, x0, rb, rx = judged_guess(AK, M.apply, b, 1e3 * rng.standard_normal(b.size), nd)
+    ok, x0, rb, rx = screened_guess(AK, M.apply, b, 1e3 * rng.standard_normal(b.size), nd)
     assert not ok and rx >= rb and not x0.any()
