@@ -298,6 +298,42 @@ def test_kernel_timing_counts(fh):
             assert st2["kernel_ms"][k] > 0.0
 
 
+def test_input_validation(fh):
+    """Bad sizes, call order and inputs are rejected with an error code and
+    a message before any kernel reads them; the context stays usable."""
+    say("input validation")
+    ctx = fh.Context(0)
+
+    def rejects(code, fn, *a, **k):
+        with pytest.raises(fh.FHError) as e:
+            fn(*a, **k)
+        assert e.value.code == code, e.value
+        return str(e.value)
+
+    for n in [(5, 4, 4), (512, 4, 4), (3, 4, 4), (4, 4, 1), (0, 4, 4)]:
+        rejects(fh.FH_EINVAL, ctx.set_grid, n, "elastic", "hex8")
+    ctx.set_grid((8, 6, 4), "elastic", "hex8")
+    rejects(fh.FH_ESTATE, ctx.solve, eta=1e-8)          # no material, no loads
+    mat = np.stack([isotropic_mandel(1.0, 0.3), isotropic_mandel(5.0, 0.3)])
+    ph = np.zeros((4, 6, 8), dtype=np.uint8)
+    ph[1, 2, 3] = 2                                       # id 2 with 2 tables
+    ph_dev = torch.from_numpy(ph).cuda()
+    msg = rejects(fh.FH_EINVAL, lambda: (ctx.set_phases(ph_dev, mat), ctx.set_load(np.eye(6)),
+                                         ctx.solve(eta=1e-8)))
+    assert "phase" in msg
+    ph[1, 2, 3] = 1
+    ctx.set_phases(torch.from_numpy(ph).cuda(), mat)
+    rejects(fh.FH_EINVAL, ctx.set_load, np.zeros((0, 6)))
+    rejects(fh.FH_EINVAL, ctx.set_load, np.ones((fh.FH_MAX_LOADS + 1, 6)))
+    rejects(fh.FH_EINVAL, ctx.solve, eta=0.0)
+    rejects(fh.FH_EINVAL, ctx.solve, eta=1e-8, itmax=0)
+    # after the rejections the same context solves normally
+    ctx.set_load(np.eye(6))
+    rc, st = ctx.solve(eta=1e-8)
+    assert rc == 0 and min(st["iterations"]) > 0
+    ctx.close()
+
+
 def test_breakdown_and_itmax_statuses(fh):
     say("statuses")
     wl, prob = _spheres_case(12, (1.5, 3.0), 100.0, 2)
