@@ -2,7 +2,7 @@
 
 Workloads: 128^3 elasticity (spheres, two isotropic phases, 6 unit strains)
 and 256^3 heat conduction (k = exp of a periodic Gaussian random field, 3 unit
-gradients).  These grids are too large for the assembled oracle, so:
+gradients); the operator also at 256^3 elasticity, the largest grid.  These grids are too large for the assembled oracle, so:
 
 - operator outputs are compared at 2000 sampled nodes with the oracle's
   per-node rows (the element sum of eq. lin_system written out node by node),
@@ -62,8 +62,12 @@ def _setup(fh, name):
     if name not in _CACHE:
         from paper_2203_02962_amd.runner import setup_context
         say("generate", name)
-        wl = (workload("elastic3d_spheres", seed=0, n=128) if name == "elastic128"
-              else workload("conduction3d_grf", seed=0))
+        if name == "elastic128":
+            wl = workload("elastic3d_spheres", seed=0, n=128)
+        elif name == "elastic256":  # the largest grid the library accepts
+            wl = workload("elastic3d_spheres", seed=0, n=256)
+        else:
+            wl = workload("conduction3d_grf", seed=0)
         _CACHE[name] = (wl, _problem(wl), setup_context(wl))
     return _CACHE[name]
 
@@ -76,7 +80,7 @@ def _nodes(prob, seed):
     return np.random.default_rng(seed).choice(prob.N, NSAMPLE, replace=False)
 
 
-@pytest.mark.parametrize("name", ["elastic128", "conduction256"])
+@pytest.mark.parametrize("name", ["elastic128", "conduction256", "elastic256"])
 def test_full_size_operator_rows(fh, name):
     wl, prob, ctx = _setup(fh, name)
     say("operator rows", name)
