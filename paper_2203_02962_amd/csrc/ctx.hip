@@ -26,8 +26,10 @@
 
 using fh::cplx;
 
-// chunks of the load-pair dot products behind C_hom
+// chunks of the load-pair dot products behind C_hom, and of the one-dot-per-
+// system reductions (refinement norms, warm-start screen)
 constexpr int kPairChunks = 1024;
+constexpr int kSysChunks = 512;
 
 struct fh_ctx {
   int device = 0;
@@ -466,7 +468,7 @@ size_t layout(fh_ctx* c, char* base, fh_ctx::Layout* Lout) {
   L.dot_part = (double*)take(sizeof(double) * 1024);
   L.scal = (double*)take(sizeof(double) * 64);
   L.sysdot = (double*)take(sizeof(double) * nl);
-  L.sysdot_part = (double*)take(sizeof(double) * nl * 64);
+  L.sysdot_part = (double*)take(sizeof(double) * nl * kSysChunks);
   // load-pair dot partials and results: one solve (kPairChunks chunks) or a
   // batch group (64 chunks per microstructure), up to 8 x 8 pairs each
   L.pair_part = (double*)take(sizeof(double) *
@@ -960,7 +962,7 @@ int pcg_refined(fh_ctx* c, int nload, double eta, double eta_in, int itmax, int 
     int rc = precond_fields(c, L.r, L.q, nload, F);
     if (rc) return rc;
     // r_j . z_j for every system in one launch (fixed-order sums)
-    HIPCHK(c, fh::launch_pair_dots(L.r, L.q, F, 1, nload, 64, L.sysdot_part, L.sysdot,
+    HIPCHK(c, fh::launch_pair_dots(L.r, L.q, F, 1, nload, kSysChunks, L.sysdot_part, L.sysdot,
                                    c->stream));
     std::vector<double> dots(nload, 0.0);
     HIPCHK(c, hipMemcpyAsync(dots.data(), L.sysdot, sizeof(double) * nload,
@@ -1086,7 +1088,8 @@ int prepare_guess(fh_ctx* c, const fh_opts& o, std::vector<double>& rb,
   }
   HIPCHK(c, fh::launch_remove_mean(L.x, nl * g.nd, g.N, L.sysdot_part, 16, c->stream));
   auto dots = [&](const double* a, const double* b, std::vector<double>& out) -> int {
-    HIPCHK(c, fh::launch_pair_dots(a, b, F, 1, nl, 64, L.sysdot_part, L.sysdot, c->stream));
+    HIPCHK(c, fh::launch_pair_dots(a, b, F, 1, nl, kSysChunks, L.sysdot_part, L.sysdot,
+                                   c->stream));
     out.assign(nl, 0.0);
     HIPCHK(c, hipMemcpyAsync(out.data(), L.sysdot, sizeof(double) * nl, hipMemcpyDeviceToHost,
                              c->stream));
