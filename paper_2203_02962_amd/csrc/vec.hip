@@ -21,9 +21,22 @@ __device__ double block_sum_fixed(double v, double* sh) {
   return sh[0];
 }
 
+// Thread t adds part[t], part[t + 256], ... in that order.  The reads of 8
+// trips are issued before their additions, so a long list costs one memory
+// round trip per 8 trips, not one per trip (same sum, same order).
 __device__ double sum_parts(const double* part, int nb, double* sh) {
   double v = 0.0;
-  for (int i = threadIdx.x; i < nb; i += 256) v += part[i];
+  for (int base = threadIdx.x; base < nb; base += 8 * 256) {
+    double x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = base + k * 256;
+      x[k] = i < nb ? part[i] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (base + k * 256 < nb) v += x[k];
+  }
   return block_sum_fixed(v, sh);
 }
 
