@@ -334,6 +334,29 @@ def test_input_validation(fh):
     ctx.close()
 
 
+@pytest.mark.parametrize("nload", [1, 2, 4, 8])
+def test_energy_products_for_any_load_count(fh, nload):
+    """nload arbitrary macroscopic strains E (rows): the nload x nload result
+    is E C_hom E^T with C_hom from the six unit strains (the energy form is
+    bilinear in the loads), for every load count the pair-product kernel is
+    specialised to."""
+    say("energy products, loads", nload)
+    wl, prob = _spheres_case(16, (2.0, 3.5), 50.0, 5)
+    ctx = _ctx(fh, wl)
+    rc, _ = ctx.solve(eta=1e-12)
+    assert rc == 0
+    C6 = ctx.get_homogenized()
+    E = np.random.default_rng(40 + nload).standard_normal((nload, 6))
+    ctx.set_load(E)
+    nbytes = ctx.workspace_size()     # more loads than the bound workspace holds
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    off = (-ws.data_ptr()) % 256
+    ctx.bind_workspace(ws[off:off + nbytes])
+    rc, _ = ctx.solve(eta=1e-12)
+    assert rc == 0
+    assert _rel(ctx.get_homogenized(), E @ C6 @ E.T) < 1e-10
+
+
 def test_breakdown_and_itmax_statuses(fh):
     say("statuses")
     wl, prob = _spheres_case(12, (1.5, 3.0), 100.0, 2)
