@@ -312,8 +312,9 @@ def main():
                     help="also run a plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(DESIGN.md describes how the solve would shard).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path. "
+              "Batches would shard by whole systems; one large grid by z slabs, with "
+              "all-to-all transposes for the FFT.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
