@@ -245,8 +245,9 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT))
 // 2^-(2-|M|) / h_beta, which scale the gradient coefficients on the way in
 // and the modal forces on the way out.  The PCG product p.q is taken at the
 // output nodes (p is still in the LDS plane), so no per-voxel energy is
-// formed.  Node planes are triple-buffered in LDS and the plane after next is
-// prefetched into registers while the current slab is computed.
+// formed.  Two node planes sit in LDS and the next one is prefetched into
+// registers while the current slab is computed; the modal forces of a slab's
+// upper face stay in registers until the next slab adds its own.
 template <typename T, int M>
 __device__ __forceinline__ void iso_term(const T (&w)[3][8], T (&f)[3][8], const T lam,
                                          const T mu2, const T ax, const T ay, const T az) {
@@ -272,7 +273,61 @@ __device__ __forceinline__ void iso_term(const T (&w)[3][8], T (&f)[3][8], const
   if (X) f[1][M | 1] += S5 * sax;
 }
 
-template <typename T, int TX, int TY>
+// The same term for cubic voxels (h_x = h_y = h_z).  With one a for every
+// axis the two factors a of a term fold into its constants: l = V lambda c_M
+// a^2, m = 2 V mu c_M a^2 and mh = m / 2 (the two 1/sqrt2 of a shear pair);
+// lpm = l + m serves the terms with a single normal strain.  Each shear
+// coefficient is then the plain sum of the cross derivatives present, and
+// its stress goes back unscaled to both of them.
+template <typename T, int M>
+__device__ __forceinline__ void iso_term_cube(const T (&w)[3][8], T (&f)[3][8], const T l,
+                                              const T m, const T mh, const T lpm) {
+  constexpr bool X = !(M & 1), Y = !(M & 2), Z = !(M & 4);
+  if constexpr (X + Y + Z == 1) {
+    if constexpr (X) f[0][M | 1] += lpm * w[0][M | 1];
+    if constexpr (Y) f[1][M | 2] += lpm * w[1][M | 2];
+    if constexpr (Z) f[2][M | 4] += lpm * w[2][M | 4];
+  } else {
+    T sd;  // sum of the normal strain coefficients present
+    if constexpr (X && Y && Z) sd = w[0][M | 1] + w[1][M | 2] + w[2][M | 4];
+    else if constexpr (X && Y) sd = w[0][M | 1] + w[1][M | 2];
+    else if constexpr (X && Z) sd = w[0][M | 1] + w[2][M | 4];
+    else sd = w[1][M | 2] + w[2][M | 4];
+    const T lt = l * sd;
+    if constexpr (X) f[0][M | 1] += lt + m * w[0][M | 1];
+    if constexpr (Y) f[1][M | 2] += lt + m * w[1][M | 2];
+    if constexpr (Z) f[2][M | 4] += lt + m * w[2][M | 4];
+  }
+  if constexpr (Y && Z) {  // yz
+    const T g = mh * (w[1][M | 4] + w[2][M | 2]);
+    f[1][M | 4] += g;
+    f[2][M | 2] += g;
+  } else if constexpr (Z) {
+    f[1][M | 4] += mh * w[1][M | 4];
+  } else if constexpr (Y) {
+    f[2][M | 2] += mh * w[2][M | 2];
+  }
+  if constexpr (X && Z) {  // xz
+    const T g = mh * (w[0][M | 4] + w[2][M | 1]);
+    f[0][M | 4] += g;
+    f[2][M | 1] += g;
+  } else if constexpr (Z) {
+    f[0][M | 4] += mh * w[0][M | 4];
+  } else if constexpr (X) {
+    f[2][M | 1] += mh * w[2][M | 1];
+  }
+  if constexpr (X && Y) {  // xy
+    const T g = mh * (w[0][M | 2] + w[1][M | 1]);
+    f[0][M | 2] += g;
+    f[1][M | 1] += g;
+  } else if constexpr (Y) {
+    f[0][M | 2] += mh * w[0][M | 2];
+  } else if constexpr (X) {
+    f[1][M | 1] += mh * w[1][M | 1];
+  }
+}
+
+template <typename T, int TX, int TY, bool CUBE>
 __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
     k_kop_hex8_iso(Grid g, int kz, const T* __restrict__ u, T* __restrict__ q,
                    const uint8_t* __restrict__ phase, const T* __restrict__ lm,
@@ -283,7 +338,6 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
   __shared__ T plane[2][3][NP];
   __shared__ uint8_t phl[2][NP];  // voxel phases of the slab above each plane
   __shared__ T force[12][NEL];  // lower-face totals of the current slab
-  __shared__ T carry[12][NEL];  // upper-face forces of the previous slab (own slot)
   __shared__ double red[32];
   // per-phase {V lambda, 2 V mu}, sized by the launch (2 nphase_max)
   extern __shared__ __align__(16) unsigned char kop_dyn[];
@@ -319,6 +373,9 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
   const int ei = tid % PX, ej = tid / PX;
   const bool is_elem = tid < NEL && ei < EX;
   const T ihx = T(1.0 / g.h[0]), ihy = T(1.0 / g.h[1]), ihz = T(1.0 / g.h[2]);
+  const double ih2 = 1.0 / (g.h[0] * g.h[0]);
+  const T k0 = T(ih2 / 16.0), k1 = T(ih2 / 48.0), k2 = T(ih2 / 144.0);
+  const T k0h = T(ih2 / 32.0), k1h = T(ih2 / 96.0), k2h = T(ih2 / 288.0);
 
   int poff[NPF];
 #pragma unroll
@@ -355,6 +412,9 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
   };
 
   for (int i = tid; i < 2 * g.nphase_max; i += NT) lmt[i] = lm[i];
+  T carry[12];  // upper-face modes of the previous slab
+#pragma unroll
+  for (int r = 0; r < 12; ++r) carry[r] = T(0);
   double dot = 0.0;
   fetch(z0 - 1);
   store(0);
@@ -391,11 +451,26 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
           }
       const int ph = phl[blo][ej * PX + ei];
       const T lam = lmt[2 * ph], mu2 = lmt[2 * ph + 1];
+      // -0 is the identity of addition, so the first sum into a mode and the
+      // inverse butterflies of the never-written mode 0 fold away exactly
       T f[3][8];
 #pragma unroll
       for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int a = 0; a < 8; ++a) f[c][a] = T(0);
+        for (int a = 0; a < 8; ++a) f[c][a] = T(-0.0);
+      if constexpr (CUBE) {
+        // c_M a^2 = h^-2 / 16, / 48, / 144 for |M| = 0, 1, 2
+        const T l0 = lam * k0, m0 = mu2 * k0, h0 = mu2 * k0h;
+        iso_term_cube<T, 0>(w, f, l0, m0, h0, T(0));
+        const T l1 = lam * k1, m1 = mu2 * k1, h1 = mu2 * k1h;
+        iso_term_cube<T, 1>(w, f, l1, m1, h1, T(0));
+        iso_term_cube<T, 2>(w, f, l1, m1, h1, T(0));
+        iso_term_cube<T, 4>(w, f, l1, m1, h1, T(0));
+        const T p2 = (lam + mu2) * k2, h2 = mu2 * k2h;
+        iso_term_cube<T, 3>(w, f, T(0), T(0), h2, p2);
+        iso_term_cube<T, 5>(w, f, T(0), T(0), h2, p2);
+        iso_term_cube<T, 6>(w, f, T(0), T(0), h2, p2);
+      } else {
       {  // |M| = 0: c_M = 1, a = h^-1 / 4
         const T qx = T(0.25) * ihx, qy = T(0.25) * ihy, qz = T(0.25) * ihz;
         iso_term<T, 0>(w, f, lam, mu2, qx, qy, qz);
@@ -413,25 +488,37 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
         iso_term<T, 5>(w, f, l2, m2, ihx, ihy, ihz);
         iso_term<T, 6>(w, f, l2, m2, ihx, ihy, ihz);
       }
+      }
+      // Transpose transform, z first: (fm, fd) -> (fm - fd, fm + fd) gives
+      // the modes of the lower and upper faces.  The upper face of this slab
+      // is the lower face of the next, so its modes are carried and added to
+      // the next slab's before the in-plane transform, which thus runs once
+      // per face.
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int bit = 1; bit < 8; bit <<= 1)
-#pragma unroll
-          for (int a = 0; a < 8; ++a) {
-            if (a & bit) continue;
-            const T fm = f[c][a], fd = f[c][a | bit];
-            f[c][a] = fm - fd;
-            f[c][a | bit] = fm + fd;
-          }
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
+      for (int c = 0; c < 3; ++c) {
+        T fl[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const int r = c * 4 + k;
-          if (s > 0) force[r][tid] = f[c][k] + carry[r][tid];
-          carry[r][tid] = f[c][k + 4];
+          const T fm = f[c][k], fd = f[c][k | 4];
+          fl[k] = fm - fd;
+          if (s > 0) fl[k] += carry[r];
+          carry[r] = fm + fd;
         }
+        if (s > 0) {
+#pragma unroll
+          for (int bit = 1; bit < 4; bit <<= 1)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              if (k & bit) continue;
+              const T fm = fl[k], fd = fl[k | bit];
+              fl[k] = fm - fd;
+              fl[k | bit] = fm + fd;
+            }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) force[c * 4 + k][tid] = fl[k];
+        }
+      }
     }
     // p at this step's output node (plane zs, still in LDS) for p.q
     T pd0 = T(0), pd1 = T(0), pd2 = T(0);
@@ -477,7 +564,7 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
 // V k sum_beta c_M(m, beta) a_beta^2, with c_M = (1/12)^|M| and a_beta =
 // 2^-(2-|M|) / h_beta as in the isotropic elastic kernel (M = the other
 // difference bits of m).  Same z march as that kernel: node planes in LDS,
-// lower-face forces exchanged, upper-face forces carried to the next slab.
+// lower-face forces exchanged, upper-face modes carried to the next slab.
 template <typename T, int TX, int TY>
 __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 4)
     k_kop_hex8_scalar(Grid g, int kz, const T* __restrict__ u, T* __restrict__ q,
@@ -490,7 +577,6 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 4)
   __shared__ T plane[2][NP];
   __shared__ T cpl[2][NP];  // coefficients of the slab above each plane
   __shared__ T force[4][NEL];
-  __shared__ T carry[4][NEL];
   __shared__ double red[32];
   extern __shared__ __align__(16) unsigned char kop_dyn[];
   T* skt = reinterpret_cast<T*>(kop_dyn);  // V k per phase (field: V)
@@ -564,6 +650,7 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 4)
       }
   };
   for (int i = tid; i < g.nphase_max; i += NT) skt[i] = sk[i];
+  T carry[4] = {T(0), T(0), T(0), T(0)};  // upper-face modes of the previous slab
   double dot = 0.0;
   fetch(z0 - 1);
   store(0);
@@ -596,22 +683,34 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 4)
           w[a] = u0 + u1;
           w[a | bit] = u1 - u0;
         }
+      // mode 0 (the mean) carries no gradient; -0 keeps its butterflies exact
+      // and lets them fold away
       T f[8];
+      f[0] = T(-0.0);
 #pragma unroll
-      for (int a = 0; a < 8; ++a) f[a] = kk * d[a] * w[a];
-#pragma unroll
-      for (int bit = 1; bit < 8; bit <<= 1)
-#pragma unroll
-        for (int a = 0; a < 8; ++a) {
-          if (a & bit) continue;
-          const T fm = f[a], fd = f[a | bit];
-          f[a] = fm - fd;
-          f[a | bit] = fm + fd;
-        }
+      for (int a = 1; a < 8; ++a) f[a] = kk * d[a] * w[a];
+      // transpose transform, z first; the upper face's modes are carried to
+      // the next slab and added before the in-plane transform
+      T fl[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        if (s > 0) force[k][tid] = f[k] + carry[k][tid];
-        carry[k][tid] = f[k + 4];
+        const T fm = f[k], fd = f[k | 4];
+        fl[k] = fm - fd;
+        if (s > 0) fl[k] += carry[k];
+        carry[k] = fm + fd;
+      }
+      if (s > 0) {
+#pragma unroll
+        for (int bit = 1; bit < 4; bit <<= 1)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            if (k & bit) continue;
+            const T fm = fl[k], fd = fl[k | bit];
+            fl[k] = fm - fd;
+            fl[k | bit] = fm + fd;
+          }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) force[k][tid] = fl[k];
       }
     }
     T pd = T(0);
@@ -637,9 +736,11 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 4)
   }
 }
 
-// 16 x 8 output nodes per block (17 x 9 elements, 3 waves, about 38 KB of
-// LDS in FP64): four blocks fit a CU.  Measured at 128^3, 6 loads, FP64:
-// 32x8 480 us, 32x4 353 us, 16x4 363 us, 16x8 317 us per launch.
+// 16 x 8 output nodes per block (17 x 9 elements, 3 waves; about 25 KB of
+// LDS in FP64 for elasticity, and four blocks per CU at 162 VGPRs).  Tile
+// sweep at 128^3, 6 loads, FP64, with an earlier form of the kernel that
+// kept the carry in LDS: 32x8 480 us, 32x4 353 us, 16x4 363 us, 16x8 317 us
+// per launch.
 constexpr int kHexTX = 16, kHexTY = 8;
 
 // z chunk per block (16 x 8 tiles, 128^3, FP64: kz 16 / 32 / 64 -> 317 /
@@ -829,8 +930,12 @@ hipError_t launch_kop_hex8_iso(const Grid& g, const T* u, T* q, const uint8_t* p
   dim3 grid(ntiles, (g.nz + kz - 1) / kz, nload);
   if (nblocks_out) *nblocks_out = grid.x * grid.y;
   const size_t lds = sizeof(T) * 2 * (size_t)(g.nphase_max > 0 ? g.nphase_max : 1);
-  hipLaunchKernelGGL((k_kop_hex8_iso<T, TX, TY>), grid, dim3(Cfg::NT), lds, s, g, kz, u, q, phase,
-                     lm, ustride, qstride, st, pq_part);
+  if (g.h[0] == g.h[1] && g.h[0] == g.h[2])
+    hipLaunchKernelGGL((k_kop_hex8_iso<T, TX, TY, true>), grid, dim3(Cfg::NT), lds, s, g, kz, u, q,
+                       phase, lm, ustride, qstride, st, pq_part);
+  else
+    hipLaunchKernelGGL((k_kop_hex8_iso<T, TX, TY, false>), grid, dim3(Cfg::NT), lds, s, g, kz, u,
+                       q, phase, lm, ustride, qstride, st, pq_part);
   return hipGetLastError();
 }
 template <typename T>
