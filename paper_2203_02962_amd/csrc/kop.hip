@@ -254,12 +254,14 @@ __device__ __forceinline__ void iso_term(const T (&w)[3][8], T (&f)[3][8], const
   constexpr bool X = !(M & 1), Y = !(M & 2), Z = !(M & 4);
   const T s = T(0.70710678118654752440084436210485);
   const T sax = s * ax, say = s * ay, saz = s * az;
-  const T E0 = X ? w[0][M | 1] * ax : T(0);
-  const T E1 = Y ? w[1][M | 2] * ay : T(0);
-  const T E2 = Z ? w[2][M | 4] * az : T(0);
-  const T E3 = (Z ? w[1][M | 4] * saz : T(0)) + (Y ? w[2][M | 2] * say : T(0));
-  const T E4 = (Z ? w[0][M | 4] * saz : T(0)) + (X ? w[2][M | 1] * sax : T(0));
-  const T E5 = (Y ? w[0][M | 2] * say : T(0)) + (X ? w[1][M | 1] * sax : T(0));
+  // absent strain coefficients are -0, so sums with them fold away exactly
+  const T z = T(-0.0);
+  const T E0 = X ? w[0][M | 1] * ax : z;
+  const T E1 = Y ? w[1][M | 2] * ay : z;
+  const T E2 = Z ? w[2][M | 4] * az : z;
+  const T E3 = (Z ? w[1][M | 4] * saz : z) + (Y ? w[2][M | 2] * say : z);
+  const T E4 = (Z ? w[0][M | 4] * saz : z) + (X ? w[2][M | 1] * sax : z);
+  const T E5 = (Y ? w[0][M | 2] * say : z) + (X ? w[1][M | 1] * sax : z);
   const T lt = lam * (E0 + E1 + E2);
   if (X) f[0][M | 1] += (lt + mu2 * E0) * ax;
   if (Y) f[1][M | 2] += (lt + mu2 * E1) * ay;
@@ -471,23 +473,23 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
         iso_term_cube<T, 5>(w, f, T(0), T(0), h2, p2);
         iso_term_cube<T, 6>(w, f, T(0), T(0), h2, p2);
       } else {
-      {  // |M| = 0: c_M = 1, a = h^-1 / 4
-        const T qx = T(0.25) * ihx, qy = T(0.25) * ihy, qz = T(0.25) * ihz;
-        iso_term<T, 0>(w, f, lam, mu2, qx, qy, qz);
-      }
-      {  // |M| = 1: c_M = 1/12, a = h^-1 / 2
-        const T l1 = lam * T(1.0 / 12.0), m1 = mu2 * T(1.0 / 12.0);
-        const T hx = T(0.5) * ihx, hy = T(0.5) * ihy, hz = T(0.5) * ihz;
-        iso_term<T, 1>(w, f, l1, m1, hx, hy, hz);
-        iso_term<T, 2>(w, f, l1, m1, hx, hy, hz);
-        iso_term<T, 4>(w, f, l1, m1, hx, hy, hz);
-      }
-      {  // |M| = 2: c_M = 1/144, a = h^-1
-        const T l2 = lam * T(1.0 / 144.0), m2 = mu2 * T(1.0 / 144.0);
-        iso_term<T, 3>(w, f, l2, m2, ihx, ihy, ihz);
-        iso_term<T, 5>(w, f, l2, m2, ihx, ihy, ihz);
-        iso_term<T, 6>(w, f, l2, m2, ihx, ihy, ihz);
-      }
+        {  // |M| = 0: c_M = 1, a = h^-1 / 4
+          const T qx = T(0.25) * ihx, qy = T(0.25) * ihy, qz = T(0.25) * ihz;
+          iso_term<T, 0>(w, f, lam, mu2, qx, qy, qz);
+        }
+        {  // |M| = 1: c_M = 1/12, a = h^-1 / 2
+          const T l1 = lam * T(1.0 / 12.0), m1 = mu2 * T(1.0 / 12.0);
+          const T hx = T(0.5) * ihx, hy = T(0.5) * ihy, hz = T(0.5) * ihz;
+          iso_term<T, 1>(w, f, l1, m1, hx, hy, hz);
+          iso_term<T, 2>(w, f, l1, m1, hx, hy, hz);
+          iso_term<T, 4>(w, f, l1, m1, hx, hy, hz);
+        }
+        {  // |M| = 2: c_M = 1/144, a = h^-1
+          const T l2 = lam * T(1.0 / 144.0), m2 = mu2 * T(1.0 / 144.0);
+          iso_term<T, 3>(w, f, l2, m2, ihx, ihy, ihz);
+          iso_term<T, 5>(w, f, l2, m2, ihx, ihy, ihz);
+          iso_term<T, 6>(w, f, l2, m2, ihx, ihy, ihz);
+        }
       }
       // Transpose transform, z first: (fm, fd) -> (fm - fd, fm + fd) gives
       // the modes of the lower and upper faces.  The upper face of this slab
