@@ -661,12 +661,16 @@ int build_symbol(fh_ctx* c) {
     for (double& v : c->cmean) v /= (double)g.N;
   } else {
     const int nb = 1024;
+    HIPCHK(c, fh::launch_flag_nonpositive(c->kfield_dev, g.N, c->flag_dev, c->stream));
     HIPCHK(c, fh::launch_field_sum(c->kfield_dev, g.N, c->L.dot_part, nb, c->stream));
     HIPCHK(c, fh::launch_sum_partials(c->L.dot_part, nb, c->L.scal, c->stream));
     double ks = 0;
+    int badk = 0;
     HIPCHK(c, hipMemcpyAsync(&ks, c->L.scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&badk, c->flag_dev, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (!(ks > 0.0)) return fail(c, FH_EINVAL, "conductivity field must be positive");
+    if (badk || !(ks > 0.0))
+      return fail(c, FH_EINVAL, "conductivity field must be positive and finite in every voxel");
     for (int i = 0; i < m; ++i) c->cmean[i * m + i] = ks / (double)g.N;
   }
   c->cref = c->cref_user ? c->cref_in : c->cmean;
@@ -788,7 +792,8 @@ int apply_KT(fh_ctx* c, const float* u, float* q, int nload, long long F,
 template <typename T>
 int pcg_run(fh_ctx* c, int nload, const PcgBufs<T>& bf, double eta, int itmax, int poll,
             const std::vector<int>& active, std::vector<fh::PcgState>& out,
-            bool zero_x = true, const std::vector<double>* eta2v = nullptr) {
+            bool zero_x = true, const std::vector<double>* eta2v = nullptr,
+            const std::vector<int>* itmaxv = nullptr) {
   const fh::Grid& g = c->g;
   const long long F = (long long)g.nd * g.N;
   const long long S = (long long)g.nd * g.nxh * g.ny * g.nz;
@@ -798,7 +803,7 @@ int pcg_run(fh_ctx* c, int nload, const PcgBufs<T>& bf, double eta, int itmax, i
     hs[j] = fh::PcgState{};
     hs[j].status = active[j] ? fh::ST_ACTIVE : fh::ST_CONVERGED;
     hs[j].eta2 = eta2v ? (*eta2v)[j] : eta * eta;
-    hs[j].itmax = itmax;
+    hs[j].itmax = itmaxv ? std::max(1, (*itmaxv)[j]) : itmax;
   }
   HIPCHK(c, hipMemcpyAsync(L.st, hs.data(), sizeof(fh::PcgState) * nload, hipMemcpyHostToDevice,
                            c->stream));
@@ -1012,8 +1017,13 @@ int pcg_refined(fh_ctx* c, int nload, double eta, double eta_in, int itmax, int 
         const double rel = std::min(0.5, std::max(1e-5, tau * std::sqrt(rho0[j] / rho[j])));
         eta2[j] = rel * rel;
       }
+    // the inner sweeps share the caller's iteration cap (Alg. 1 it_max^CG):
+    // each may run only what the earlier sweeps of its load case left
+    std::vector<int> left(nload, 1);
+    for (int j = 0; j < nload; ++j) left[j] = std::max(1, itmax - total[j]);
     std::vector<fh::PcgState> hs;
-    rc = pcg_run<float>(c, nload, bf, eta_in, std::max(1, itmax), poll, active, hs, true, &eta2);
+    rc = pcg_run<float>(c, nload, bf, eta_in, std::max(1, itmax), poll, active, hs, true, &eta2,
+                        &left);
     if (rc) return rc;
     for (int j = 0; j < nload; ++j)
       if (active[j]) {
@@ -1635,6 +1645,10 @@ int fh_set_grid(fh_ctx* c, int dim, const int n[3], const double l[3], int probl
   c->has_grid = true;
   c->mat_kind = 0;
   c->nload = 0;
+  // a reference set for the previous grid has the previous problem's size
+  c->cref_user = false;
+  c->cref_in.clear();
+  c->cref.clear();
   c->layout_ok = false;
   c->symbol_ok = c->rhs_ok = c->solved = false;
   free_tables(c);
@@ -1946,7 +1960,9 @@ int fh_get_homogenized(fh_ctx* c, double* Chom) {
 int fh_get_reference(fh_ctx* c, double* Cref) {
   if (!c || !Cref) return FH_EINVAL;
   if (!c->symbol_ok) return fail(c, FH_ESTATE, "reference not built yet");
-  std::memcpy(Cref, c->cref.data(), c->cref.size() * sizeof(double));
+  const size_t mm = (size_t)mdim(c) * mdim(c);
+  if (c->cref.size() != mm) return fail(c, FH_ESTATE, "reference does not match the grid");
+  std::memcpy(Cref, c->cref.data(), mm * sizeof(double));
   return FH_OK;
 }
 

@@ -177,6 +177,8 @@ hipError_t launch_add_masked(double* dst, const float* src, long long F, int nlo
 hipError_t launch_impulse(double* f, long long n, long long pos, hipStream_t s);
 hipError_t launch_field_sum(const double* x, long long n, double* out_part, int nb,
                             hipStream_t s);
+// *flag |= 1 if some x[i] is not a positive finite number (flag not cleared)
+hipError_t launch_flag_nonpositive(const double* x, long long n, int* flag, hipStream_t s);
 // x[seg][.] -= its mean for nseg segments of n values (part: nseg x nchunk)
 hipError_t launch_remove_mean(double* x, int nseg, long long n, double* part, int nchunk,
                               hipStream_t s);

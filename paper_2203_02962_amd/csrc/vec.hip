@@ -97,7 +97,10 @@ __global__ void k_finalize_beta(PcgState* st, const double* part, int nb, double
     const double rel = rho_new > 0.0 ? sqrt(rho_new / s.rho0) : 0.0;
     s.last = rel;
     if (hist && s.iter <= hist_len) hist[(long long)ld * hist_len + s.iter - 1] = rel;
-    if (rho_new <= s.eta2 * s.rho0) {
+    if (!(rho_new >= 0.0)) {
+      // r.z < 0 (or NaN): the preconditioned residual norm is not defined
+      s.status = ST_BREAKDOWN;
+    } else if (rho_new <= s.eta2 * s.rho0) {
       s.status = ST_CONVERGED_PENDING;
     } else if (s.iter >= s.itmax) {
       s.status = ST_MAXIT_PENDING;
@@ -186,6 +189,21 @@ hipError_t launch_remove_mean(double* x, int nseg, long long n, double* part, in
                               hipStream_t s) {
   hipLaunchKernelGGL(k_seg_part, dim3(nchunk, nseg), dim3(256), 0, s, x, n, nchunk, part);
   hipLaunchKernelGGL(k_seg_sub, dim3(256, nseg), dim3(256), 0, s, x, n, nchunk, part);
+  return hipGetLastError();
+}
+
+// flag = 1 if any entry is not a positive finite number (App. A: the
+// conductivity of every voxel must be positive)
+__global__ void k_flag_nonpositive(const double* a, long long n, int* flag) {
+  int bad = 0;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    const double v = a[i];
+    bad |= !(v > 0.0 && v <= 1.7976931348623157e308);
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+hipError_t launch_flag_nonpositive(const double* x, long long n, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_flag_nonpositive, dim3(1024), dim3(256), 0, s, x, n, flag);
   return hipGetLastError();
 }
 

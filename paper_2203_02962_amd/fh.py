@@ -203,11 +203,40 @@ def _dptr(arr):
     return arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def _tptr(t):
+def _tptr(t, dtype=None, numel=None, device=None):
+    """Data pointer of a contiguous device tensor, after checking what the
+    library will read or write through it: `dtype` (a torch dtype or a tuple
+    of them), at least `numel` elements and the context's device index.  A
+    mismatch raises TypeError before any library call."""
     import torch  # device memory provider only
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or not t.is_contiguous():
         raise TypeError("expected a contiguous CUDA (HIP) tensor")
+    if dtype is not None:
+        ok = dtype if isinstance(dtype, tuple) else (dtype,)
+        if t.dtype not in ok:
+            raise TypeError(f"expected a tensor of dtype {ok}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise TypeError(f"tensor has {t.numel()} elements, the call needs at least {numel}")
+    if device is not None and t.device.index != device:
+        raise TypeError(f"tensor is on cuda:{t.device.index}, the context on cuda:{device}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _f64():
+    import torch
+    return torch.float64
+
+
+def _U8():
+    import torch
+    return torch.uint8
+
+
+def _BF16_CARRIERS():
+    """16-bit storage the library reads as BF16 bit patterns."""
+    import torch
+    return (torch.int16, torch.bfloat16, torch.uint16) if hasattr(torch, "uint16") else \
+        (torch.int16, torch.bfloat16)
 
 
 class Context:
@@ -261,13 +290,15 @@ class Context:
 
     def set_phases(self, phase_dev, mat):
         mat = np.ascontiguousarray(mat, dtype=np.float64)
+        import torch
+        ptr = _tptr(phase_dev, torch.uint8, self.N, self.device)
         self._keep = [phase_dev]
-        return self._check(self.lib.fh_set_phases(self.ptr, _tptr(phase_dev), int(mat.shape[0]),
-                                                  _dptr(mat)))
+        return self._check(self.lib.fh_set_phases(self.ptr, ptr, int(mat.shape[0]), _dptr(mat)))
 
     def set_conductivity_field(self, k_dev):
+        ptr = _tptr(k_dev, _f64(), self.N, self.device)
         self._keep = [k_dev]
-        return self._check(self.lib.fh_set_conductivity_field(self.ptr, _tptr(k_dev)))
+        return self._check(self.lib.fh_set_conductivity_field(self.ptr, ptr))
 
     def set_reference(self, Cref=None):
         if Cref is None:
@@ -290,8 +321,10 @@ class Context:
         if buf is None:
             self._ws = None
             return self._check(self.lib.fh_bind_workspace(self.ptr, None, 0))
+        import torch
+        ptr = _tptr(buf, torch.uint8, None, self.device)
         self._ws = buf
-        return self._check(self.lib.fh_bind_workspace(self.ptr, _tptr(buf), buf.numel()))
+        return self._check(self.lib.fh_bind_workspace(self.ptr, ptr, buf.numel()))
 
     # ----------------------------------------------------------------- solve
     @staticmethod
@@ -311,14 +344,16 @@ class Context:
             (FH_FLAG_TIME_SAMPLED if time_sampled else 0)
         o = self.opts(eta, itmax, precision, poll, eta_inner, flags)
         if guess_dev is not None:
-            o.guess_dev = _tptr(guess_dev).value
+            o.guess_dev = _tptr(guess_dev, _f64(), self.nload * self.nd * self.N,
+                                self.device).value
         st = fh_stats()
         rc = self._check(self.lib.fh_solve(self.ptr, ctypes.byref(o), ctypes.byref(st)),
                          allow_warning=True)
         return rc, st.as_dict()
 
     def get_fluctuation(self, load, out_dev):
-        return self._check(self.lib.fh_get_fluctuation(self.ptr, load, _tptr(out_dev)))
+        ptr = _tptr(out_dev, _f64(), self.nd * self.N, self.device)
+        return self._check(self.lib.fh_get_fluctuation(self.ptr, load, ptr))
 
     def get_homogenized(self):
         H = np.zeros((self.nload, self.nload))
@@ -339,24 +374,36 @@ class Context:
         return h[:cnt.value]
 
     # ----------------------------------------------------------- step hooks
+    def _field(self, t):
+        return _tptr(t, _f64(), self.nd * self.N, self.device)
+
     def apply_operator(self, u_dev, q_dev):
-        return self._check(self.lib.fh_apply_operator(self.ptr, _tptr(u_dev), _tptr(q_dev)))
+        return self._check(self.lib.fh_apply_operator(self.ptr, self._field(u_dev),
+                                                      self._field(q_dev)))
 
     def apply_preconditioner(self, r_dev, z_dev):
-        return self._check(self.lib.fh_apply_preconditioner(self.ptr, _tptr(r_dev),
-                                                            _tptr(z_dev)))
+        return self._check(self.lib.fh_apply_preconditioner(self.ptr, self._field(r_dev),
+                                                            self._field(z_dev)))
 
     def compute_rhs(self, E, b_dev):
         E = np.ascontiguousarray(E, dtype=np.float64)
-        return self._check(self.lib.fh_compute_rhs(self.ptr, _dptr(E), _tptr(b_dev)))
+        assert E.size == self.m
+        return self._check(self.lib.fh_compute_rhs(self.ptr, _dptr(E), self._field(b_dev)))
+
+    def symbol_size(self):
+        """Doubles written by get_symbol: nd(nd+1)/2 entries per frequency of
+        the half spectrum."""
+        n = list(self.n) + [1] * (3 - len(self.n))
+        return self.nd * (self.nd + 1) // 2 * (n[0] // 2 + 1) * n[1] * n[2]
 
     def get_symbol(self, kplus_dev):
-        return self._check(self.lib.fh_get_symbol(self.ptr, _tptr(kplus_dev)))
+        ptr = _tptr(kplus_dev, _f64(), self.symbol_size(), self.device)
+        return self._check(self.lib.fh_get_symbol(self.ptr, ptr))
 
     def solve_rhs(self, b_dev, u_dev, eta=1e-10, itmax=10000, poll=0):
         o = self.opts(eta, itmax, FH_FP64, poll)
         st = fh_stats()
-        rc = self._check(self.lib.fh_solve_rhs(self.ptr, _tptr(b_dev), _tptr(u_dev),
+        rc = self._check(self.lib.fh_solve_rhs(self.ptr, self._field(b_dev), self._field(u_dev),
                                                ctypes.byref(o), ctypes.byref(st)),
                          allow_warning=True)
         return rc, st.as_dict()
@@ -372,12 +419,14 @@ class Context:
         nload = E.shape[0]
         mats = [np.ascontiguousarray(m, dtype=np.float64) for _, _, m in systems]
         arr = (fh_system * len(systems))()
+        import torch
         for i, ((ph, n, _), m) in enumerate(zip(systems, mats)):
-            arr[i].phase_dev = _tptr(ph)
+            arr[i].phase_dev = _tptr(ph, torch.uint8, int(np.prod(n)), self.device)
             arr[i].n = (ctypes.c_int * 3)(*[int(v) for v in n])
             arr[i].nphase = int(m.shape[0])
             arr[i].mat = _dptr(m)
-            arr[i].u_dev = (_tptr(u_out[i]).value
+            arr[i].u_dev = (_tptr(u_out[i], _f64(), nload * 3 * int(np.prod(n)),
+                                  self.device).value
                             if u_out is not None and u_out[i] is not None else None)
         chom = np.zeros((len(systems), nload, nload))
         sts = (fh_stats * len(systems))()
@@ -448,15 +497,22 @@ class Net:
 
     def forward(self, phase_dev, gamma, out_dev):
         g, gp = self._f32(gamma)
-        return self._check(self.lib.fh_net_forward(self.ptr, int(g.size), _tptr(phase_dev), gp,
-                                                   _tptr(out_dev)))
+        import torch
+        V, b = self.n ** 3, int(g.size)
+        return self._check(self.lib.fh_net_forward(
+            self.ptr, b, _tptr(phase_dev, torch.uint8, b * V, self.device), gp,
+            _tptr(out_dev, torch.float32, b * 18 * V, self.device)))
 
     def gradient(self, phase_dev, gamma, target_dev):
         g, gp = self._f32(gamma)
         loss = ctypes.c_double()
         grad, grp = self._f32(np.zeros(self.P))
-        self._check(self.lib.fh_net_gradient(self.ptr, int(g.size), _tptr(phase_dev), gp,
-                                             _tptr(target_dev), ctypes.byref(loss), grp))
+        import torch
+        V, b = self.n ** 3, int(g.size)
+        self._check(self.lib.fh_net_gradient(
+            self.ptr, b, _tptr(phase_dev, torch.uint8, b * V, self.device), gp,
+            _tptr(target_dev, _BF16_CARRIERS(), b * 18 * V, self.device), ctypes.byref(loss),
+            grp))
         return loss.value, grad
 
     def adam(self, grad=None, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, clip=0.0):
@@ -476,20 +532,26 @@ class Net:
         loss = np.zeros(max(steps, 1))
         o = fh_adam(lr, beta1, beta2, eps, clip)
         self._check(self.lib.fh_net_train(
-            self.ptr, int(g.size), _tptr(phase_dev), gp, _tptr(target_dev), int(batch),
+            self.ptr, int(g.size),
+            _tptr(phase_dev, _U8(), int(g.size) * self.n ** 3, self.device), gp,
+            _tptr(target_dev, _BF16_CARRIERS(), int(g.size) * 18 * self.n ** 3, self.device),
+            int(batch),
             int(steps), order.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(o),
             _dptr_out(loss)))
         return loss[:steps]
 
     def guess(self, phase_dev, gamma, E, length, x_dev):
         E = np.ascontiguousarray(np.atleast_2d(E), dtype=np.float64)
-        return self._check(self.lib.fh_net_guess(self.ptr, _tptr(phase_dev), float(gamma),
-                                                 E.shape[0], _dptr(E), float(length),
-                                                 _tptr(x_dev)))
+        V = self.n ** 3
+        return self._check(self.lib.fh_net_guess(
+            self.ptr, _tptr(phase_dev, _U8(), V, self.device), float(gamma), E.shape[0],
+            _dptr(E), float(length), _tptr(x_dev, _f64(), E.shape[0] * 3 * V, self.device)))
 
     def pack_target(self, u_dev, scale, target_dev):
-        return self._check(self.lib.fh_net_pack_target(self.ptr, _tptr(u_dev), float(scale),
-                                                       _tptr(target_dev)))
+        V = self.n ** 3
+        return self._check(self.lib.fh_net_pack_target(
+            self.ptr, _tptr(u_dev, _f64(), 18 * V, self.device), float(scale),
+            _tptr(target_dev, _BF16_CARRIERS(), 18 * V, self.device)))
 
     def set_timing(self, on=True):
         return self._check(self.lib.fh_net_set_timing(self.ptr, 1 if on else 0))

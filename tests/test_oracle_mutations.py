@@ -2,14 +2,17 @@
 catch each one: a dropped sqrt(2)/2 on shear rows, Gauss points moved, a
 periodic shift taken the wrong way, a dropped quadrature weight, a sign slip in
 the right-hand side, an unnormalised inverse DFT, a zero-frequency block
-inverted instead of pseudo-inverted, and in the large-grid preconditioner a
-symbol built from the wrong rows or an unnormalised inverse FFT."""
+inverted instead of pseudo-inverted, in the large-grid preconditioner a
+symbol built from the wrong rows or an unnormalised inverse FFT, and in the
+homogenization helpers an unweighted or scaled mean material and a stress
+average without the macroscopic strain."""
 import sys
 
 import numpy as np
 import pytest
 
 import oracle.assembly as asm
+import oracle.homog as ohom
 import oracle.naive_dft as odft
 import oracle.elements as oel
 import oracle.precond as opre
@@ -171,3 +174,67 @@ def _conv_taps_transposed(x, W, b):
 def test_net_pins_catch_planted_mistake(monkeypatch, name, mutant):
     monkeypatch.setattr(ocn, name, mutant)
     assert _net_pins_fail()
+
+
+# ------------------------------------------------ mean material and stress
+
+def _mean_pins():
+    return [
+        (pins.test_mean_material_two_phase_closed_form, ("hex8", "elastic", (5, 4, 3),
+                                                         (1.0, 2.0, 0.5))),
+        (pins.test_mean_material_of_a_field_is_the_exact_sum, ()),
+    ]
+
+
+def test_unmutated_mean_and_stress_pins_pass():
+    assert not any(_fails(fn, *a) for fn, a in _mean_pins())
+    assert not _fails(pins.test_stress_average_equals_energy_columns_at_exact_solution,
+                      "hex8", "elastic", (4, 3, 4))
+    assert not _fails(pins.test_stress_average_of_a_laminate_is_the_closed_form)
+
+
+def test_catches_unweighted_mean_material(monkeypatch):
+    """Mean over the distinct phases instead of over the pixels."""
+    def bad(prob):
+        if prob.phase is not None:
+            return np.mean(prob.mat, axis=0)
+        return np.mean(np.asarray(prob.kfield)) * np.eye(prob.dim)
+    monkeypatch.setattr(oracle_mod(), "mean_material", bad)
+    assert any(_fails(fn, *a) for fn, a in _mean_pins())
+
+
+def test_catches_mean_material_not_divided_by_the_volume(monkeypatch):
+    orig = ohom.mean_material
+
+    def bad(prob):
+        return orig(prob) * prob.volume
+    monkeypatch.setattr(oracle_mod(), "mean_material", bad)
+    assert any(_fails(fn, *a) for fn, a in _mean_pins())
+
+
+def test_catches_mean_material_with_one_voxel_dropped(monkeypatch):
+    orig = ohom.mean_material
+
+    def bad(prob):
+        C = prob.voxel_materials()
+        return orig(prob) - C[-1] / prob.N
+    monkeypatch.setattr(oracle_mod(), "mean_material", bad)
+    assert any(_fails(fn, *a) for fn, a in _mean_pins())
+
+
+def test_catches_stress_average_without_macroscopic_strain(monkeypatch):
+    def bad(prob, E, u):
+        w = asm.quadrature_weights(prob)
+        C = prob.voxel_materials()
+        eps = asm.gradient_at_quadrature(prob, u)
+        sig = np.einsum("emn,eqn->eqm", C, eps)
+        return np.einsum("q,eqm->m", w, sig) / prob.volume
+    monkeypatch.setattr(oracle_mod(), "stress_average", bad)
+    assert _fails(pins.test_stress_average_equals_energy_columns_at_exact_solution,
+                  "hex8", "elastic", (4, 3, 4))
+    assert _fails(pins.test_stress_average_of_a_laminate_is_the_closed_form)
+
+
+def oracle_mod():
+    import oracle
+    return oracle

@@ -374,6 +374,82 @@ def test_pcg_matches_dense_least_squares(elem, problem, n):
         assert np.abs(res.x - x_ls).max() < 1e-10 * np.abs(x_ls).max()
 
 
+# ------------------------------------ reference material = mean (Sec. 6.2)
+
+@pytest.mark.parametrize("elem,problem,n,l", [("hex8", "elastic", (5, 4, 3), (1.0, 2.0, 0.5)),
+                                              ("tri2", "scalar", (6, 4), None),
+                                              ("quad4", "elastic", (3, 5), (3.0, 1.0))])
+def test_mean_material_two_phase_closed_form(elem, problem, n, l):
+    """The quadrature-weighted mean of an element-wise constant material is
+    (1 - f) C0 + f C1 with f the inclusion's share of the pixels: every
+    pixel carries the same total weight V_p (the weights of a stencil sum
+    to the pixel volume), so the mean depends only on the counts.  f comes
+    from integer counts here, not from the oracle's weights."""
+    rng = np.random.default_rng(41)
+    dim = len(n)
+    m = 3 * dim - 3 if problem == "elastic" else dim
+    phase = rng.integers(0, 2, size=n[::-1])
+    C0, C1 = random_spd(m, rng), 17.0 * random_spd(m, rng)
+    prob = Problem(n, problem, elem, phase=phase.astype(np.uint8), mat=np.stack([C0, C1]), l=l)
+    n1 = int(np.count_nonzero(phase))
+    N = int(np.prod(n))
+    want = (N - n1) / N * C0 + n1 / N * C1
+    assert np.abs(oracle.mean_material(prob) - want).max() < 1e-14 * np.abs(want).max()
+
+
+def test_mean_material_of_a_field_is_the_exact_sum():
+    """Per-voxel conductivity: the mean is sum(k)/N, checked against
+    math.fsum (exactly rounded) on a field whose entries span six decades."""
+    rng = np.random.default_rng(43)
+    n = (6, 5, 4)
+    k = np.exp(rng.uniform(-7.0, 7.0, size=n[::-1]))
+    prob = Problem(n, "scalar", "hex8", kfield=k, l=(0.5, 1.0, 3.0))
+    want = math.fsum(k.ravel().tolist()) / k.size
+    got = oracle.mean_material(prob)
+    assert np.abs(got - want * np.eye(3)).max() <= 4e-16 * want
+
+
+# ------------------------ stress average vs energy form at the exact solution
+
+@pytest.mark.parametrize("elem,problem,n", [("hex8", "elastic", (4, 3, 4)),
+                                            ("quad4", "scalar", (5, 4)),
+                                            ("tri2", "elastic", (4, 5))])
+def test_stress_average_equals_energy_columns_at_exact_solution(elem, problem, n):
+    """At the exact discrete solution the test function u_i in the
+    equilibrium of u_j makes <D u_i . sigma_j> vanish, so e_i . <sigma_j>
+    equals the energy form C_hom[i, j].  The solutions here come from a dense
+    least-squares solve of the assembled system, not from PCG."""
+    rng = np.random.default_rng(47)
+    dim = len(n)
+    m = 3 * dim - 3 if problem == "elastic" else dim
+    phase = rng.integers(0, 2, size=n[::-1])
+    prob = Problem(n, problem, elem, phase=phase.astype(np.uint8),
+                   mat=np.stack([random_spd(m, rng), 40.0 * random_spd(m, rng)]))
+    Kd = assemble_stiffness(prob).toarray()
+    loads = np.eye(m)
+    sols = [np.linalg.lstsq(Kd, rhs(prob, E), rcond=1e-12)[0] for E in loads]
+    H = oracle.homogenized_energy(prob, loads, sols)
+    S = np.stack([oracle.stress_average(prob, E, u) for E, u in zip(loads, sols)], axis=1)
+    assert np.abs(S - H).max() < 1e-11 * np.abs(H).max()
+
+
+def test_stress_average_of_a_laminate_is_the_closed_form():
+    """Scalar laminate normal to x: the flux average under a unit gradient
+    along the normal is the harmonic mean, across it the arithmetic mean
+    (the FE space holds the exact piecewise-linear solution)."""
+    kvals = np.array([1.0, 1.0, 7.0, 30.0, 7.0, 2.0])
+    n = (6, 4, 3)
+    kf = np.broadcast_to(kvals[None, None, :], n[::-1]).copy()
+    prob = Problem(n, "scalar", "hex8", kfield=kf)
+    Kd = assemble_stiffness(prob).toarray()
+    harm, arit = 1.0 / np.mean(1.0 / kvals), np.mean(kvals)
+    for j, want in ((0, [harm, 0, 0]), (1, [0, arit, 0])):
+        E = np.eye(3)[j]
+        u = np.linalg.lstsq(Kd, rhs(prob, E), rcond=1e-12)[0]
+        got = oracle.stress_average(prob, E, u)
+        assert np.abs(got - np.array(want)).max() < 1e-12 * arit
+
+
 # ------------------------------------------- P5 Voigt / Reuss and symmetry
 
 def test_discrete_bounds_and_symmetry():
