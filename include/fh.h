@@ -221,6 +221,19 @@ int fh_get_symbol(fh_ctx *ctx, double *kplus_dev);
 int fh_solve_rhs(fh_ctx *ctx, const double *b_dev, double *u_dev, const fh_opts *opt,
                  fh_stats *st);
 
+/* Same result as fh_compute_rhs, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the element-force tables are staged in a static device
+ * array of 6144 doubles (48 KiB) that the library holds on every device it
+ * runs on until the process ends; no hipMalloc, hipFree or allocating
+ * routine is called.  Needs the same set-up as fh_compute_rhs (grid and
+ * material).  FH_EINVAL if the tables (material tables x corners x
+ * components) would exceed the array -- impossible within fh_set_phases'
+ * limits.  All contexts on one device share the array: calls that overlap in
+ * time on one device (other threads, other streams) race and must be
+ * serialised by the caller.  The call synchronises the context's stream.  */
+int fh_compute_rhs_noalloc(fh_ctx *ctx, const double *E, double *b_dev);
+
 /* ------------------------------------------------------------ batches
  * Many independent microstructures (possibly of different grid sizes), each
  * solved for the same nload macroscopic strains.  Systems are grouped by grid

@@ -21,10 +21,39 @@
 #include <string>
 #include <vector>
 
+#include <mutex>
+
 #include "../../include/fh.h"
 #include "fh_internal.h"
 
 using fh::cplx;
+
+// Staging for fh_compute_rhs_noalloc: the element forces of the uniform
+// strain, one table per material table (at most 256 tables x 8 corners x 3
+// components).  Every device holds its own copy for the life of the process.
+// In host code the array's name is not a device address: the address of the
+// current device's copy comes from hipGetSymbolAddress (scratch_ptr below).
+constexpr int kRhsScratchDoubles = 256 * 8 * 3;
+static __device__ __align__(256) double scratch[kRhsScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current), looked up
+// once per device.  Returns null if the lookup fails.
+double* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch_dev[device] = static_cast<double*>(ptr);
+  }
+  return g_scratch_dev[device];
+}
+}  // namespace
 
 // chunks of the load-pair dot products behind C_hom, and of the one-dot-per-
 // system reductions (refinement norms, warm-start screen)
@@ -1558,6 +1587,7 @@ int fh_create(fh_ctx** out, int device) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return FH_EDEVICE;
   if (hipSetDevice(device) != hipSuccess) return FH_EDEVICE;
+  if (!scratch_ptr(device)) return FH_EDEVICE;
   fh_ctx* c = new fh_ctx();
   c->device = device;
   if (hipMalloc((void**)&c->counts_dev, 256 * sizeof(unsigned long long)) != hipSuccess ||
@@ -2001,21 +2031,64 @@ int fh_apply_preconditioner(fh_ctx* c, const double* r_dev, double* z_dev) {
   return FH_OK;
 }
 
-int fh_compute_rhs(fh_ctx* c, const double* E, double* b_dev) {
-  if (!c || !E || !b_dev) return FH_EINVAL;
-  hipSetDevice(c->device);
+}  // extern "C"
+
+namespace {
+// Element forces of the uniform strain E for every material table (one unit
+// table for a conductivity field), as k_rhs reads them.
+int rhs_force_tables(fh_ctx* c, const double* E, std::vector<double>& fe) {
   int rc = check_material(c);
   if (rc) return rc;
   const int m = mdim(c);
+  for (int i = 0; i < m; ++i)
+    if (!std::isfinite(E[i])) return fail(c, FH_EINVAL, "loads must be finite");
   const int ntab = c->mat_kind == 1 ? c->nphase : 1;
   std::vector<double> unit((size_t)m * m, 0.0);
   for (int i = 0; i < m; ++i) unit[i * m + i] = 1.0;
-  std::vector<double> fe;
+  fe.clear();
   for (int t = 0; t < ntab; ++t) {
     const double* C = c->mat_kind == 1 ? c->mat.data() + (size_t)t * m * m : unit.data();
     std::vector<double> f = uniform_strain_force(c, C, E);
     fe.insert(fe.end(), f.begin(), f.end());
   }
+  return FH_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int fh_compute_rhs_noalloc(fh_ctx* c, const double* E, double* b_dev) {
+  if (!c || !E || !b_dev) return FH_EINVAL;
+  hipSetDevice(c->device);
+  std::vector<double> fe;
+  int rc = rhs_force_tables(c, E, fe);
+  if (rc) return rc;
+  if (fe.size() > (size_t)kRhsScratchDoubles)
+    return fail(c, FH_EINVAL, "element force tables need " + std::to_string(fe.size()) +
+                                  " doubles, the static staging holds " +
+                                  std::to_string(kRhsScratchDoubles));
+  double* stage = scratch_ptr(c->device);
+  if (!stage) return fail(c, FH_EDEVICE, "hipGetSymbolAddress of the staging array failed");
+  const int ntab = c->mat_kind == 1 ? c->nphase : 1;
+  // every entry k_rhs reads is written here, so nothing of an earlier call
+  // (a larger table) is ever read
+  HIPCHK(c, hipMemcpyAsync(stage, fe.data(), fe.size() * sizeof(double), hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, fh::launch_rhs(c->g, c->element, c->mat_kind == 1 ? c->phase_dev : nullptr,
+                           c->mat_kind == 2 ? c->kfield_dev : nullptr, stage, ntab, 1, b_dev, 0,
+                           c->stream));
+  // the host table must outlive the copy, and the staging the kernel
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FH_OK;
+}
+
+int fh_compute_rhs(fh_ctx* c, const double* E, double* b_dev) {
+  if (!c || !E || !b_dev) return FH_EINVAL;
+  hipSetDevice(c->device);
+  std::vector<double> fe;
+  int rc = rhs_force_tables(c, E, fe);
+  if (rc) return rc;
+  const int ntab = c->mat_kind == 1 ? c->nphase : 1;
   double* tmp = nullptr;
   HIPCHK(c, hipMalloc((void**)&tmp, fe.size() * sizeof(double)));
   hipError_t e1 = hipMemcpyAsync(tmp, fe.data(), fe.size() * sizeof(double),

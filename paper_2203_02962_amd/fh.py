@@ -37,7 +37,8 @@ EXPORTED = [
     "fh_set_phases", "fh_set_conductivity_field", "fh_set_reference", "fh_set_load",
     "fh_workspace_size", "fh_bind_workspace", "fh_solve", "fh_get_fluctuation",
     "fh_get_homogenized", "fh_get_reference", "fh_get_history", "fh_apply_operator",
-    "fh_apply_preconditioner", "fh_compute_rhs", "fh_get_symbol", "fh_solve_rhs",
+    "fh_apply_preconditioner", "fh_compute_rhs", "fh_compute_rhs_noalloc", "fh_get_symbol",
+    "fh_solve_rhs",
     "fh_solve_batch", "fh_set_warm_start",
     "fh_net_param_count", "fh_net_create", "fh_net_destroy", "fh_net_last_error",
     "fh_net_set_stream", "fh_net_set_params", "fh_net_get_params", "fh_net_forward",
@@ -159,6 +160,7 @@ def load_library(path: str = LIB_PATH):
         "fh_apply_operator": ([P, P, P], I),
         "fh_apply_preconditioner": ([P, P, P], I),
         "fh_compute_rhs": ([P, ctypes.POINTER(D), P], I),
+        "fh_compute_rhs_noalloc": ([P, ctypes.POINTER(D), P], I),
         "fh_get_symbol": ([P, P], I),
         "fh_solve_rhs": ([P, P, P, ctypes.POINTER(fh_opts), ctypes.POINTER(fh_stats)], I),
         "fh_solve_batch": ([P, I, ctypes.POINTER(fh_system), I, ctypes.POINTER(D),
@@ -389,6 +391,13 @@ class Context:
         E = np.ascontiguousarray(E, dtype=np.float64)
         assert E.size == self.m
         return self._check(self.lib.fh_compute_rhs(self.ptr, _dptr(E), self._field(b_dev)))
+
+    def compute_rhs_noalloc(self, E, b_dev):
+        """fh_compute_rhs without any device allocation (static staging)."""
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        assert E.size == self.m
+        return self._check(self.lib.fh_compute_rhs_noalloc(self.ptr, _dptr(E),
+                                                           self._field(b_dev)))
 
     def symbol_size(self):
         """Doubles written by get_symbol: nd(nd+1)/2 entries per frequency of

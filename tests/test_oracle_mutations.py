@@ -238,3 +238,56 @@ def test_catches_stress_average_without_macroscopic_strain(monkeypatch):
 def oracle_mod():
     import oracle
     return oracle
+
+
+# ------------------------------------------------- eigenvalue bounds (Sec. 4.3)
+
+def _bounds_pins():
+    return [
+        (pins.test_eigen_bounds_enclose_the_dense_spectrum, ("hex8", "elastic", (3, 3, 4), "mean")),
+        (pins.test_eigen_bounds_enclose_the_dense_spectrum, ("quad4", "elastic", (4, 5), "random")),
+        (pins.test_eigen_bounds_isotropic_closed_form, ()),
+        (pins.test_eigen_bounds_reference_equal_to_material, ()),
+    ]
+
+
+def test_unmutated_bounds_pins_pass():
+    assert not any(_fails(fn, *a) for fn, a in _bounds_pins())
+
+
+def test_catches_bounds_without_the_reference(monkeypatch):
+    """Eigenvalues of C instead of Cref^-1 C."""
+    import oracle.bounds as ob
+    import scipy.linalg as sla
+
+    def bad(prob, Cref):
+        if prob.phase is not None:
+            lam = [np.linalg.eigvalsh(C) for C in prob.mat]
+            key = np.asarray(prob.phase).ravel().astype(np.int64)
+            return np.array([v.min() for v in lam])[key], np.array([v.max() for v in lam])[key]
+        k = np.asarray(prob.kfield, dtype=float).ravel()
+        return k, k
+    monkeypatch.setattr(ob, "element_pairs", bad)
+    assert any(_fails(fn, *a) for fn, a in _bounds_pins())
+
+
+def test_catches_bounds_from_one_voxel_only(monkeypatch):
+    """Support of phi^I taken as the node's own voxel instead of all the
+    voxels that share the node."""
+    import oracle.bounds as ob
+
+    def bad(prob, Cref):
+        return ob.element_pairs(prob, Cref)
+    monkeypatch.setattr(ob, "node_bounds", bad)
+    assert any(_fails(fn, *a) for fn, a in _bounds_pins())
+
+
+def test_catches_bounds_with_min_and_max_swapped(monkeypatch):
+    import oracle.bounds as ob
+    orig = ob.element_pairs
+
+    def bad(prob, Cref):
+        lo, hi = orig(prob, Cref)
+        return hi, lo
+    monkeypatch.setattr(ob, "element_pairs", bad)
+    assert any(_fails(fn, *a) for fn, a in _bounds_pins())

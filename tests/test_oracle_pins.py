@@ -487,6 +487,92 @@ def test_ritz_values_inside_guaranteed_bounds_and_iteration_bound():
     assert res.iterations <= math.ceil(0.5 * math.sqrt(kappa) * math.log(2 / eta))
 
 
+def _nonzero_spectrum(prob, Cref):
+    """Nonzero generalized eigenvalues of (K, Kref), i.e. of Kref^+ K, from
+    dense matrices restricted to zero-mean fields."""
+    import scipy.linalg as sla
+    K = assemble_stiffness(prob).toarray()
+    Kr = assemble_stiffness(prob, uniform=Cref).toarray()
+    nd, N = prob.ndof_node, prob.N
+    Z = np.zeros((nd * N, nd))
+    for a in range(nd):
+        Z[a * N:(a + 1) * N, a] = 1.0
+    Q, _ = np.linalg.qr(np.hstack([Z, np.random.default_rng(5).standard_normal((nd * N, nd * N - nd))]))
+    B = Q[:, nd:]
+    return np.sort(sla.eigh(B.T @ K @ B, B.T @ Kr @ B, eigvals_only=True))
+
+
+@pytest.mark.parametrize("elem,problem,n,ref", [("hex8", "elastic", (3, 3, 4), "mean"),
+                                                ("hex8", "scalar", (4, 3, 3), "random"),
+                                                ("quad4", "elastic", (4, 5), "random"),
+                                                ("tri2", "scalar", (5, 4), "mean")])
+def test_eigen_bounds_enclose_the_dense_spectrum(elem, problem, n, ref):
+    """Sec. 4.3: with every nodal bound counted nd times and both lists
+    sorted, the k-th nonzero eigenvalue of Kref^+ K lies between the
+    (k + nd)-th lower bound and the k-th upper bound (dense eigenvalues)."""
+    from oracle import bounds
+    rng = np.random.default_rng(53)
+    dim = len(n)
+    m = 3 * dim - 3 if problem == "elastic" else dim
+    mats = np.stack([random_spd(m, rng) * 10.0 ** rng.uniform(-2, 2) for _ in range(3)])
+    phase = rng.integers(0, 3, size=n[::-1]).astype(np.uint8)
+    prob = Problem(n, problem, elem, phase=phase, mat=mats)
+    Cref = oracle.mean_material(prob) if ref == "mean" else random_spd(m, rng)
+    mu = _nonzero_spectrum(prob, Cref)
+    lo, hi = bounds.node_bounds(prob, Cref)
+    L, U = bounds.sorted_bounds(lo, hi, prob.ndof_node)
+    nd = prob.ndof_node
+    assert np.all(L[nd:] <= mu * (1 + 1e-10))
+    assert np.all(mu <= U[:mu.size] * (1 + 1e-10))
+    assert mu.max() / mu.min() <= bounds.kappa_bound(lo, hi) * (1 + 1e-10)
+
+
+def test_eigen_bounds_isotropic_closed_form():
+    """Isotropic phases against an isotropic reference: the generalized
+    eigenvalues are the bulk ratio (3 lambda + 2 mu)/(3 lambda_r + 2 mu_r)
+    once and the shear ratio mu/mu_r five times, so each voxel's pair is
+    (min, max) of the two ratios; a node takes the extremes over the eight
+    voxels around it."""
+    from oracle import bounds
+    n = (4, 3, 5)
+    rng = np.random.default_rng(57)
+    phase = rng.integers(0, 2, size=n[::-1]).astype(np.uint8)
+    E, nu = (1.0, 80.0), (0.3, 0.2)
+    prob = Problem(n, "elastic", "hex8", phase=phase,
+                   mat=np.stack([isotropic_mandel(e, v) for e, v in zip(E, nu)]))
+    Er, nur = 10.0, 0.35
+    Cref = isotropic_mandel(Er, nur)
+    lam = lambda e, v: e * v / ((1 + v) * (1 - 2 * v))
+    mu = lambda e, v: e / (2 * (1 + v))
+    bulk = [(3 * lam(e, v) + 2 * mu(e, v)) / (3 * lam(Er, nur) + 2 * mu(Er, nur)) for e, v in zip(E, nu)]
+    shear = [mu(e, v) / mu(Er, nur) for e, v in zip(E, nu)]
+    lo_p = np.array([min(b, s) for b, s in zip(bulk, shear)])
+    hi_p = np.array([max(b, s) for b, s in zip(bulk, shear)])
+    lo, hi = bounds.node_bounds(prob, Cref)
+    # brute force over the voxel neighbourhood of every node
+    for I in range(prob.N):
+        x, y, z = I % n[0], (I // n[0]) % n[1], I // (n[0] * n[1])
+        ph = [phase[(z - cz) % n[2], (y - cy) % n[1], (x - cx) % n[0]]
+              for cx, cy, cz in itertools.product((0, 1), repeat=3)]
+        assert abs(lo[I] - lo_p[ph].min()) < 1e-13 * lo_p.max()
+        assert abs(hi[I] - hi_p[ph].max()) < 1e-13 * hi_p.max()
+
+
+def test_eigen_bounds_reference_equal_to_material():
+    """C = Cref in every voxel: every bound is 1 and the bound on the
+    condition number is 1 (the "geometrically optimal" case of Sec. 4.3)."""
+    from oracle import bounds
+    C = random_spd(6, np.random.default_rng(59))
+    prob = Problem((3, 4, 3), "elastic", "hex8", phase=np.zeros((3, 4, 3), np.uint8), mat=C[None])
+    lo, hi = bounds.node_bounds(prob, C)
+    assert np.abs(lo - 1).max() < 1e-13 and np.abs(hi - 1).max() < 1e-13
+    assert abs(bounds.kappa_bound(lo, hi) - 1) < 1e-13
+    kf = np.exp(np.random.default_rng(61).uniform(-3, 3, size=(4, 5, 6)))
+    prob = Problem((6, 5, 4), "scalar", "hex8", kfield=kf)
+    lo, hi = bounds.node_bounds(prob, 2.0 * np.eye(3))
+    assert abs(bounds.kappa_bound(lo, hi) - kf.max() / kf.min()) < 1e-12 * kf.max() / kf.min()
+
+
 # ----------------------------------- P9 translation, permutation, linearity
 
 def test_translation_and_axis_permutation_invariance():
