@@ -291,3 +291,80 @@ def test_catches_bounds_with_min_and_max_swapped(monkeypatch):
         return hi, lo
     monkeypatch.setattr(ob, "element_pairs", bad)
     assert any(_fails(fn, *a) for fn, a in _bounds_pins())
+
+
+# ------------------------------------------------ elasto-plastic Newton oracle
+import oracle.plasticity as opl  # noqa: E402
+from tests import test_oracle_plasticity as ppins  # noqa: E402
+
+
+def _plastic_checks():
+    return [
+        (ppins.test_pure_shear_closed_form, ()),
+        (ppins.test_consistent_tangent_is_the_derivative_of_the_stress_update, ()),
+        (ppins.test_oracle_internal_force_matches_brute_force, ()),
+        (ppins.test_homogeneous_cell_returns_the_point_response, ()),
+        (ppins.test_newton_converges_quadratically, ()),
+    ]
+
+
+def _plastic_caught():
+    return any(_fails(fn, *args) for fn, args in _plastic_checks())
+
+
+def _radial_return(eps, eps_p_n, alpha_n, K, G, sy0, H, hard=2.0 / 3.0, sq=None,
+                   thb_full=True):
+    """The oracle's stress update with knobs for planted mistakes."""
+    sq = opl.SQ23 if sq is None else sq
+    ONE, P = opl.ONE, opl.P_DEV
+    eps = np.asarray(eps, dtype=float)
+    tr = eps[..., 0] + eps[..., 1] + eps[..., 2]
+    s_tr = 2.0 * G[..., None] * (eps - (tr / 3.0)[..., None] * ONE - eps_p_n)
+    ns = np.sqrt(np.sum(s_tr * s_tr, axis=-1))
+    f = ns - sq * (sy0 + H * alpha_n)
+    pl = f > 0.0
+    dg = np.where(pl, f / (2.0 * G + hard * H), 0.0)
+    n = np.where(pl[..., None], s_tr / np.where(ns > 0, ns, 1.0)[..., None], 0.0)
+    sigma = (K * tr)[..., None] * ONE + s_tr - (2.0 * G * dg)[..., None] * n
+    th = np.where(pl, 1.0 - 2.0 * G * dg / np.where(ns > 0, ns, 1.0), 1.0)
+    thb = np.where(pl, 1.0 / (1.0 + H / (3.0 * G)) - ((1.0 - th) if thb_full else 0.0), 0.0)
+    C = (K[..., None, None] * np.outer(ONE, ONE) + (2.0 * G * th)[..., None, None] * P
+         - (2.0 * G * thb)[..., None, None] * n[..., :, None] * n[..., None, :])
+    return sigma, C, eps_p_n + dg[..., None] * n, alpha_n + sq * dg, pl
+
+
+def test_unmutated_plasticity_pins_pass(monkeypatch):
+    monkeypatch.setattr(opl, "return_mapping", _radial_return)  # same arithmetic
+    assert not _plastic_caught()
+
+
+@pytest.mark.parametrize("name,kw", [
+    ("yield radius without sqrt(2/3)", dict(sq=1.0)),
+    ("hardening denominator 2G + H", dict(hard=1.0)),
+    ("tangent without the (1 - theta) term", dict(thb_full=False)),
+])
+def test_plasticity_pins_catch_stress_update_mistakes(monkeypatch, name, kw):
+    monkeypatch.setattr(opl, "return_mapping",
+                        lambda *a: _radial_return(*a, **kw))
+    assert _plastic_caught(), name
+
+
+def test_plasticity_pins_catch_residual_sign_slip(monkeypatch):
+    orig = opl.internal_force
+
+    def bad(pp, sigma, with_scale=False):
+        out = orig(pp, sigma, with_scale)
+        return (-out[0], out[1]) if with_scale else -out
+    monkeypatch.setattr(opl, "internal_force", bad)
+    assert _plastic_caught()
+
+
+def test_plasticity_pins_catch_uncommitted_state(monkeypatch):
+    """Internal variables never carried to the next increment."""
+    orig = opl.return_mapping
+
+    def bad(eps, eps_p_n, alpha_n, *rest):
+        s, C, _, _, pl = orig(eps, eps_p_n, alpha_n, *rest)
+        return s, C, eps_p_n, alpha_n, pl
+    monkeypatch.setattr(opl, "return_mapping", bad)
+    assert _fails(ppins.test_newton_matches_dense_newton_on_brute_residual) or _plastic_caught()
