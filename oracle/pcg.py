@@ -44,10 +44,11 @@ def zero_mean(x: np.ndarray, nd: int) -> np.ndarray:
 
 def pcg(apply_K, apply_M, b: np.ndarray, eta: float, itmax: int = 10000,
         x0: np.ndarray | None = None, nd: int = 1,
-        rho_ref: float | None = None) -> PCGResult:
+        rho_ref: float | None = None, callback=None) -> PCGResult:
     """rho_ref: the squared norm the stopping test is relative to (default
     r0.z0; a warm start passes b.M b so that the test keeps measuring the
-    residual against the zero-start one)."""
+    residual against the zero-start one).  callback(x), if given, sees every
+    iterate x_k, k >= 1 (a copy)."""
     b = np.asarray(b, dtype=float)
     x = np.zeros_like(b) if x0 is None else zero_mean(x0, nd)
     r = b - apply_K(x) if x0 is not None else b.copy()
@@ -68,6 +69,8 @@ def pcg(apply_K, apply_M, b: np.ndarray, eta: float, itmax: int = 10000,
         alpha = rho / pq
         x += alpha * p
         r -= alpha * q
+        if callback is not None:
+            callback(x.copy())
         z = apply_M(r)
         rho_new = float(np.dot(r, z))
         res.alphas.append(alpha)

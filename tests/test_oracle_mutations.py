@@ -368,3 +368,44 @@ def test_plasticity_pins_catch_uncommitted_state(monkeypatch):
         return s, C, eps_p_n, alpha_n, pl
     monkeypatch.setattr(opl, "return_mapping", bad)
     assert _fails(ppins.test_newton_matches_dense_newton_on_brute_residual) or _plastic_caught()
+
+
+# ------------------------------------------------- strain-based scheme oracle
+import oracle.strain_based as osbm  # noqa: E402
+from tests import test_oracle_strain_based as sbpins  # noqa: E402
+
+
+def _sb_caught():
+    checks = [
+        (sbpins.test_green_operator_projects_onto_compatible_fields, (True,)),
+        (sbpins.test_identity_reference_gives_least_squares_compatible_part, ()),
+        (sbpins.test_strain_iterates_equal_gradients_of_displacement_iterates, (True,)),
+    ]
+    return any(_fails(fn, *args) for fn, args in checks)
+
+
+def test_unmutated_strain_based_pins_pass():
+    assert not _sb_caught()
+
+
+def test_sb_pins_catch_divergence_without_weights(monkeypatch):
+    orig = osbm.divergence
+    monkeypatch.setattr(osbm, "divergence",
+                        lambda prob, tau: orig(prob, tau) / prob.voxel_volume * 8.0)
+    assert _sb_caught()
+
+
+def test_sb_pins_catch_green_operator_without_the_reference(monkeypatch):
+    orig = osbm.GreenOperator.__init__
+
+    def bad(self, prob, Cref):
+        orig(self, prob, np.eye(np.asarray(Cref).shape[0]) * np.trace(Cref) / len(Cref))
+        self.Cref = np.asarray(Cref, dtype=float)
+    monkeypatch.setattr(osbm.GreenOperator, "__init__", bad)
+    assert _sb_caught()
+
+
+def test_sb_pins_catch_inner_product_without_the_reference(monkeypatch):
+    orig = osbm.inner
+    monkeypatch.setattr(osbm, "inner", lambda prob, Cref, a, b: orig(prob, np.eye(6), a, b))
+    assert _sb_caught()
