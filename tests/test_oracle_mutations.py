@@ -409,3 +409,53 @@ def test_sb_pins_catch_inner_product_without_the_reference(monkeypatch):
     orig = osbm.inner
     monkeypatch.setattr(osbm, "inner", lambda prob, Cref, a, b: orig(prob, np.eye(6), a, b))
     assert _sb_caught()
+
+
+# ------------------------------------------------- two-node stencil oracle
+import oracle.two_node as otn  # noqa: E402
+from tests import test_oracle_two_node as tnpins  # noqa: E402
+
+
+def _tn_caught():
+    checks = [
+        (tnpins.test_scalar_symbol_closed_form, ()),
+        (tnpins.test_fourier_pseudo_inverse_is_dense_pseudo_inverse, ("scalar", True)),
+        (tnpins.test_fourier_pseudo_inverse_is_dense_pseudo_inverse, ("elastic", True)),
+        (tnpins.test_laminate_closed_form, ("elastic", 0)),
+    ]
+    return any(_fails(fn, *args) for fn, args in checks)
+
+
+def test_unmutated_two_node_pins_pass():
+    assert not _tn_caught()
+
+
+def test_two_node_pins_catch_zero_frequency_block_set_to_zero(monkeypatch):
+    """The one-node rule K^+(0) = 0 applied to the rank-deficient (not zero)
+    two-node block."""
+    orig = otn.pseudo_inverse_blocks
+
+    def bad(Khat, rtol=1e-10):
+        P = orig(Khat, rtol)
+        P[0] = 0.0
+        return P
+    monkeypatch.setattr(otn, "pseudo_inverse_blocks", bad)
+    assert _tn_caught()
+
+
+def test_two_node_pins_catch_centre_in_the_wrong_place(monkeypatch):
+    monkeypatch.setattr(otn, "_position", lambda node: (np.array([0.5, 0.4]) if node[0] == 1
+                                                        else np.array(node[1:], dtype=float)))
+    assert _tn_caught()
+
+
+def test_two_node_pins_catch_transposed_symbol(monkeypatch):
+    orig = otn.reference_symbol
+    monkeypatch.setattr(otn, "reference_symbol",
+                        lambda tp, Cref: np.transpose(orig(tp, Cref), (0, 2, 1)))
+    assert _tn_caught()
+
+
+def test_two_node_pins_catch_half_pixel_weight(monkeypatch):
+    monkeypatch.setattr(otn.TwoNodeProblem, "weight", lambda self: 0.5 * float(np.prod(self.h)))
+    assert _tn_caught()
