@@ -36,7 +36,8 @@ def algorithmic_bytes(n, nd=3, dtype_bytes=8):
     """Bytes each kernel class must move per load case per PCG iteration
     (compulsory traffic of this design: every field read or written once).
     V = one nodal field, Sb = one half spectrum, Kb = stored K^+ / N,
-    Pb = phase grid."""
+    Pb = phase grid.  The phase grid and K^+ are shared by the load cases of
+    a launch and read once per launch (`per_launch`)."""
     nx = ny = nz = n
     N = nx * ny * nz
     nxh = nx // 2 + 1
@@ -44,14 +45,29 @@ def algorithmic_bytes(n, nd=3, dtype_bytes=8):
     Sb = 2 * dtype_bytes * nd * nxh * ny * nz
     Kb = 8 * (nd * (nd + 1) // 2) * nxh * ny * nz
     Pb = N
-    return {
-        "operator": 2 * V + Pb,          # read p, write q, read phase
+    per_unit = {
+        "operator": 2 * V,               # read p, write q
         "xfwd": 3 * V + Sb,              # read r, q; write r; write spectrum
         "yfwd": 2 * Sb,                  # read + write spectrum
-        "zsolve": 2 * Sb + Kb,           # read + write spectrum, read K^+
+        "zsolve": 2 * Sb,                # read + write spectrum
         "yinv": 2 * Sb,
         "xinv": Sb + 4 * V,              # read spectrum, p, x; write p, x
-    }, dict(V=V, Sb=Sb, Kb=Kb, Pb=Pb)
+    }
+    per_launch = {"operator": Pb, "zsolve": Kb}
+    return per_unit, per_launch, dict(V=V, Sb=Sb, Kb=Kb, Pb=Pb)
+
+
+def launch_bytes(per_unit, per_launch, name, units_per_launch):
+    """Algorithmic bytes of one launch of class `name` that advances
+    `units_per_launch` load cases."""
+    return per_unit[name] * units_per_launch + per_launch.get(name, 0)
+
+
+# The fused floor of one PCG iteration per load case: pass 1 (x/y forward
+# FFT with the r update) 4V, pass 2 (z FFT, K^+ from the closed-form
+# symbol, inverse z FFT, Parseval r.z) 2V, pass 3 (x/y inverse FFT with the
+# x and p updates) 5V, operator 2V.
+FLOOR_V = 13
 
 
 def cpu_baseline(wl, iters: int):
@@ -71,21 +87,31 @@ def cpu_baseline(wl, iters: int):
     M = Preconditioner(prob, oracle.mean_material(prob))
     b = rhs(prob, wl["loads"][0])
     t_setup = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    res = pcg(lambda v: K @ v, M.apply, b, 1e-30, itmax=iters, nd=3)
-    dt = time.perf_counter() - t0
     dof = 3 * prob.N
+
+    def run():
+        ta = time.perf_counter()
+        res = pcg(lambda v: K @ v, M.apply, b, 1e-30, itmax=iters, nd=3)
+        return dof * res.iterations / (time.perf_counter() - ta), res.iterations
+
     blas = [i["num_threads"] for i in threadpoolctl.threadpool_info() if i["user_api"] == "blas"]
     threads = max(blas) if blas else 1
+    # all of the oracle on one thread, then the DFT's BLAS on every thread
+    # (scipy's CSR product runs on one thread either way)
+    with threadpoolctl.threadpool_limits(1):
+        v1, it1 = run()
+    vall, itall = run()
     return {
-        "value": dof * res.iterations / dt,
+        "value": vall,
         "unit": "DOF·PCG-iter/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": (f"{n}^3 elasticity, load case 1, PCG iterations 1..{res.iterations} of the "
-                   f"CPU oracle ({dt:.1f} s timed; setup {t_setup:.1f} s not timed); CSR SpMV "
-                   f"single-threaded (scipy), naive separable DFT on OpenBLAS with {threads} "
-                   f"threads; host has {os.cpu_count()} logical CPUs"),
+        "one_thread_value": v1,
+        "sample": (f"{n}^3 elasticity, load case 1, PCG iterations 1..{itall} of the CPU "
+                   f"oracle (setup {t_setup:.1f} s not timed): CSR SpMV (scipy, one thread) "
+                   f"and the naive separable DFT on OpenBLAS with {threads} threads; "
+                   f"one_thread_value = the same {it1} iterations with every library "
+                   f"limited to one thread; host has {os.cpu_count()} logical CPUs"),
     }
 
 
@@ -310,6 +336,9 @@ def main():
     ap.add_argument("--warm-steps", type=int, default=4000)
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run a plain 512 MiB device copy (counter calibration)")
+    ap.add_argument("--timed-only", action="store_true",
+                    help="run only the warm-up and timed steps (no 1e-6 or refined legs), so "
+                         "that a kernel trace of the run holds the timed launches alone")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path. "
@@ -343,6 +372,8 @@ def main():
     kms = np.zeros(8)
     kn = np.zeros(8)    # timed launches (every 8th PCG iteration)
     kall = np.zeros(8)  # all launches
+    kunits = np.zeros(8)  # load cases advanced by the timed launches
+    pcg_ms = 0.0
     iters_total = 0
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -353,6 +384,8 @@ def main():
         kms += np.array(st["kernel_ms"])
         kn += np.array(st["kernel_launches"])
         kall += np.array(st["kernel_issued"])
+        kunits += np.array(st["kernel_units"])
+        pcg_ms += st["solve_ms"]
         iters_total += sum(st["iterations"])
         print(f"[bench] step {k} done: iterations {st['iterations']}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -369,14 +402,20 @@ def main():
         rcx, stx = ctx.solve(rebuild=True, **kw)
         torch.cuda.synchronize()
         return (time.perf_counter() - ta) * 1000.0, rcx, stx
-    t_1e6, rc6, st6 = timed_solve(eta=1e-6)
     from paper_2203_02962_amd.fh import FH_FP32_REFINED
-    t_1e6_r, rc6r, st6r = timed_solve(eta=1e-6, precision=FH_FP32_REFINED)
-    H6r = ctx.get_homogenized()
-    t_1e10_r, rc10r, st10r = timed_solve(eta=args.eta, precision=FH_FP32_REFINED, eta_inner=1e-4)
-    H10r = ctx.get_homogenized()
+    if args.timed_only:
+        t_1e6 = t_1e6_r = t_1e10_r = float("nan")
+        st6 = st6r = st10r = {"iterations": None, "outer": None}
+        H6r = H10r = H
+    else:
+        t_1e6, rc6, st6 = timed_solve(eta=1e-6)
+        t_1e6_r, rc6r, st6r = timed_solve(eta=1e-6, precision=FH_FP32_REFINED)
+        H6r = ctx.get_homogenized()
+        t_1e10_r, rc10r, st10r = timed_solve(eta=args.eta, precision=FH_FP32_REFINED,
+                                             eta_inner=1e-4)
+        H10r = ctx.get_homogenized()
 
-    per_iter, parts = algorithmic_bytes(args.n)
+    per_iter, per_launch, parts = algorithmic_bytes(args.n)
     kernels = {}
     for i, name in enumerate(CLASSES):
         if kn[i] == 0:
@@ -386,12 +425,30 @@ def main():
                "launches": int(kall[i]), "avg_us": round(avg_us, 2),
                "est_ms_total": round(avg_us * kall[i] / 1000.0, 3)}
         if name in per_iter:
-            # load cases advanced per launch, averaged over all launches
-            bpl = per_iter[name] * iters_total / kall[i]
+            # load cases advanced by the timed launches themselves (a launch
+            # after some load cases stopped does less work)
+            upl = kunits[i] / kn[i]
+            bpl = launch_bytes(per_iter, per_launch, name, upl)
             ent["bytes_per_load_iter"] = per_iter[name]
+            ent["bytes_per_launch_shared"] = per_launch.get(name, 0)
+            ent["load_cases_per_timed_launch"] = round(float(upl), 4)
             ent["bytes_per_launch"] = bpl
             ent["achieved_GBs"] = round(bpl / (avg_us * 1e-6) / 1e9, 1)
         kernels[name] = ent
+    # whole PCG loop against the fused floor of 13 nodal fields per load case
+    # and iteration, and against this design's own compulsory bytes
+    design_bytes = sum(per_iter.values()) * iters_total + sum(per_launch.values()) * kall[0]
+    floor_bytes = FLOOR_V * parts["V"] * iters_total
+    pcg_s = pcg_ms / 1000.0
+    iteration_roofline = {
+        "pcg_ms_per_step": round(pcg_ms / args.steps, 3),
+        "floor_bytes_per_load_iter": FLOOR_V * parts["V"],
+        "floor_GBs": round(floor_bytes / pcg_s / 1e9, 1),
+        "floor_frac": round(floor_bytes / pcg_s / 1e9 / HBM_PEAK_GBS, 4),
+        "design_bytes_per_load_iter": round(design_bytes / iters_total),
+        "design_GBs": round(design_bytes / pcg_s / 1e9, 1),
+        "design_frac": round(design_bytes / pcg_s / 1e9 / HBM_PEAK_GBS, 4),
+    }
     roof = None
     timed = {k: v for k, v in kernels.items() if k in per_iter}
     if timed:
@@ -458,6 +515,7 @@ def main():
         },
         "kernels": kernels,
         "roofline": roof,
+        "iteration_roofline": iteration_roofline,
     }
     if not args.no_batch:
         out["config"]["batched_vs_plain_1e-6"] = batch_comparison(args.batch_count)

@@ -66,6 +66,16 @@ extern "C" {
 #define FH_QUAD4 1 /* 2D bilinear quadrilateral, 2x2 Gauss points, w = V_p/4 (Fig. tiling a.2) */
 #define FH_TRI2 2  /* 2D two linear triangles per pixel, split along (0,0)-(1,1),
                       one centroid point each, w = V_p/2 (Fig. tiling b.2) */
+#define FH_TRI4 3  /* 2D two-node stencil (N_n = 2, Fig. tiling c.2): every pixel
+                      carries its lowest corner node and its centre node and
+                      is cut into four linear triangles (centre + one pixel
+                      edge), one centroid point each, w = V_p/4.  Scalar
+                      problems only.  A nodal field holds two node sets,
+                      u[0][y][x] at the corners and u[1][y][x] at the centres
+                      (2 N doubles), and the symbol is a Hermitian 2 x 2
+                      block per frequency whose zero-frequency block has rank
+                      1 (fh_get_symbol: {k00, k11, Re k01, Im k01} of K^+ / N
+                      per frequency, each as a separate [kx][ky] plane).      */
 
 #define FH_FP64 0          /* every kernel in FP64                                 */
 #define FH_FP32_REFINED 1  /* FP32 operator/FFT/solve inside FP64 refinement       */
@@ -82,7 +92,7 @@ extern "C" {
  * network attached with fh_set_warm_start instead of from zero (see there) */
 #define FH_FLAG_WARM_START 4
 /* fh_opts.flags, with FH_FLAG_TIME_KERNELS: record the event pairs only in
- * every 8th PCG iteration.  Each timed launch leaves the GPU idle for a few
+ * every 8th PCG iteration (loop iterations 4, 12, 20, ...).  Each timed launch leaves the GPU idle for a few
  * microseconds around its events, so timing every launch slows the loop;
  * the per-class totals then cover the sampled iterations only.             */
 #define FH_FLAG_TIME_SAMPLED 8
@@ -138,6 +148,11 @@ typedef struct fh_stats {
   long long kernel_issued[FH_K_NCLASS]; /* launches per class, timed or not
                                            (kernel_launches counts the timed
                                            ones, FH_FLAG_TIME_SAMPLED)       */
+  double kernel_units[FH_K_NCLASS]; /* load cases processed by the timed
+                                       launches of each class (a launch skips
+                                       load cases that have stopped), so bytes
+                                       per timed launch = bytes per load case
+                                       x kernel_units / kernel_launches     */
 } fh_stats;
 
 /* Context on HIP device `device`.  Returns FH_EDEVICE if it cannot be used. */
@@ -233,6 +248,140 @@ int fh_solve_rhs(fh_ctx *ctx, const double *b_dev, double *u_dev, const fh_opts 
  * time on one device (other threads, other streams) race and must be
  * serialised by the caller.  The call synchronises the context's stream.  */
 int fh_compute_rhs_noalloc(fh_ctx *ctx, const double *E, double *b_dev);
+
+/* ----------------------------------------- eigenvalue bounds (Sec. 4.3)
+ * Guaranteed two-sided bounds on the eigenvalues of the preconditioned
+ * operator Kref^+ K.  For every node I, lambda_I^L (lambda_I^U) is the
+ * smallest (largest) generalized eigenvalue of the pair (C, Cref) over the
+ * quadrature points in the support of the node's basis function; with
+ * materials constant per pixel/voxel that is the min (max) over the 2^dim
+ * pixels/voxels that have I as a corner.  Counting every nodal bound nd
+ * times and sorting the two lists gives bounds on all eigenvalues of
+ * Kref^+ K; kappa = lambda_max / lambda_min bounds its condition number
+ * (Sec. 4.3), and ceil(sqrt(kappa)/2 ln(2/eta)) bounds the PCG iterations
+ * to reduce the energy-norm error by eta (classical CG estimate).         */
+typedef struct fh_bounds {
+  double lambda_min;        /* min over nodes of lambda_I^L                  */
+  double lambda_max;        /* max over nodes of lambda_I^U                  */
+  double kappa;             /* lambda_max / lambda_min                       */
+  int predicted_iterations; /* ceil(sqrt(kappa)/2 ln(2/eta)) (0 if eta bad)  */
+  int pad;
+} fh_bounds;
+
+/* Cref: d_m x d_m (or d x d) reference, or NULL for the context's reference
+ * (the one given to fh_set_reference, else the quadrature-weighted mean of
+ * Sec. 6.2).  lo_dev / hi_dev: device arrays of N doubles (node order of the
+ * grid) that receive lambda_I^L and lambda_I^U, or NULL.  Needs a grid and
+ * a material.  FH_ENOTSPD if Cref is not SPD.                              */
+int fh_eigen_bounds(fh_ctx *ctx, const double *Cref, double eta, double *lo_dev,
+                    double *hi_dev, fh_bounds *out);
+
+/* Reference material choice by the bound on the condition number (Sec. 4.3,
+ * Sec. 6.2): FH_REF_MEAN = quadrature-weighted mean, FH_REF_IDENTITY = I_s
+ * (the identity in Mandel / scalar notation), FH_REF_BEST = the candidate
+ * with the smallest kappa among the mean, I_s and, for 3D elasticity with
+ * isotropic phases, the isotropic reference whose bulk-to-shear ratio
+ * minimises kappa (its shear modulus is the mean's).  The choice becomes
+ * the context's reference (as fh_set_reference); Cref_out (d_m x d_m, may
+ * be NULL) receives it, out (may be NULL) its bounds
+ * (predicted_iterations = 0).                                              */
+#define FH_REF_MEAN 0
+#define FH_REF_IDENTITY 1
+#define FH_REF_BEST 2
+int fh_choose_reference(fh_ctx *ctx, int strategy, double *Cref_out, fh_bounds *out);
+
+/* ------------------------------- elasto-plastic Newton loop (Alg. 1)
+ * Nonlinear equilibrium D^T W sigma(e + D u) = 0 (Sec. 3, eq.
+ * non_lin_system) for 3D hex8 elasticity with small-strain von Mises
+ * plasticity and linear isotropic hardening per phase (the small-strain
+ * counterpart of the Sec. 6.3 material): bulk modulus K, shear modulus G,
+ * initial yield stress sy0, hardening modulus H (yield stress sy0 + H alpha,
+ * alpha the equivalent plastic strain).  The stress update is the radial
+ * return with its consistent tangent (Simo & Hughes, Sec. 3.3); internal
+ * variables (plastic strain, alpha) live at the 8 Gauss points of every
+ * voxel and are committed at the end of each load increment.
+ *
+ * Newton step i (Alg. 1, eq. lin_system): b = -D^T W sigma(e + D u_(i)),
+ * K_(i) = D^T W C_(i) D with the per-point tangent C_(i); the preconditioner
+ * is re-assembled (Alg. 2) every step from the quadrature-weighted mean of
+ * C_(i) (FH_NEWTON_REF_TANGENT) or once from the mean elastic stiffness
+ * (FH_NEWTON_REF_ELASTIC); PCG to eta_cg (Sec. 6 relative Kref^-1-norm);
+ * u_(i+1) = u_(i) + du; stop when ||du|| <= eta_newton ||u_(i+1)||.  A
+ * residual whose 2-norm is at most 1e-12 of the 2-norm of the element forces
+ * it sums is rounding noise (a uniform stress) and ends the loop without a
+ * step.  Increment k applies e = (k / nincrement) E_final and starts from
+ * the previous increment's u.                                             */
+#define FH_MAX_INCREMENTS 64
+#define FH_MAX_NEWTON 64
+#define FH_NEWTON_REF_TANGENT 0
+#define FH_NEWTON_REF_ELASTIC 1
+
+typedef struct fh_newton_opts {
+  double eta_newton; /* Newton tolerance on ||du|| / ||u||                 */
+  double eta_cg;     /* PCG tolerance per Newton step                      */
+  int itmax_newton;  /* Newton steps per increment (<= FH_MAX_NEWTON)      */
+  int itmax_cg;      /* PCG iterations per Newton step                     */
+  int nincrement;    /* load increments (<= FH_MAX_INCREMENTS)              */
+  int ref_mode;      /* FH_NEWTON_REF_TANGENT or FH_NEWTON_REF_ELASTIC      */
+} fh_newton_opts;
+
+typedef struct fh_newton_stats {
+  int nincrement;
+  int newton_steps[FH_MAX_INCREMENTS];   /* steps taken per increment          */
+  int converged[FH_MAX_INCREMENTS];      /* 1 if the Newton test was met        */
+  int pcg_iterations[FH_MAX_INCREMENTS][FH_MAX_NEWTON];
+  double du_ratio[FH_MAX_INCREMENTS][FH_MAX_NEWTON]; /* ||du|| / ||u_(i+1)|| */
+  double macro_stress[FH_MAX_INCREMENTS][6]; /* (1/|Y|) sum_Q w_Q sigma_Q,
+                                                Mandel, at the converged u */
+  double plastic_fraction[FH_MAX_INCREMENTS]; /* share of yielding points   */
+  int total_pcg;                         /* PCG iterations of all steps        */
+  double solve_ms;
+} fh_newton_stats;
+
+/* phase_dev: uint8 N_p grid (device, [z][y][x]), read by every later call;
+ * params: nphase x {K, G, sy0, H} (host, copied), K, G, H > 0, sy0 >= 0.
+ * Sets the phases' elastic stiffnesses as fh_set_phases does (so the linear
+ * entry points keep working) and allocates the per-point state: about
+ * 1.1 kB per voxel, library-owned, freed by fh_set_grid, fh_set_phases,
+ * fh_set_conductivity_field or fh_destroy.  Needs a 3D FH_HEX8 FH_ELASTIC
+ * grid.                                                                    */
+int fh_set_plastic_phases(fh_ctx *ctx, const uint8_t *phase_dev, int nphase,
+                          const double *params);
+/* E_final: 6 Mandel components (host).  opt NULL = {1e-8, 1e-10, 50, 10000,
+ * 1, FH_NEWTON_REF_TANGENT}.  Starts from u = 0 and a virgin state.
+ * Returns FH_OK, FH_NOT_CONVERGED (an increment hit itmax_newton or a step
+ * hit itmax_cg; the state is still committed and the loop continues),
+ * FH_ENOTSPD (PCG breakdown), FH_EINVAL / FH_ESTATE.  The caller's
+ * fh_set_reference choice is restored afterwards.                         */
+int fh_newton_solve(fh_ctx *ctx, const double *E_final, const fh_newton_opts *opt,
+                    fh_newton_stats *st);
+/* Device copies (any may be NULL): u_dev 3 x N ([comp][z][y][x]), eps_p_dev
+ * 6 x 8 x N ([Mandel comp][Gauss point][voxel]), alpha_dev 8 x N; Gauss
+ * point q = qx + 2 qy + 4 qz at reference coordinates 1/2 -+ 1/(2 sqrt 3).  */
+int fh_get_plastic_state(fh_ctx *ctx, double *u_dev, double *eps_p_dev, double *alpha_dev);
+
+/* ---------------- strain-based scheme with the FE projection (Sec. 7.1)
+ * The same linear problem as fh_solve, solved with the strain field at the
+ * Gauss points as the unknown (eq. projection_chceme): CG on
+ * Gamma0 C eps = -Gamma0 C e, Gamma0 = D (D^T W Cref D)^+ D^T W, with the
+ * pseudo-inverse applied by the displacement scheme's FFT preconditioner
+ * (same Cref, symbol and zero-frequency rule).  CG runs in the inner
+ * product <a, b> = sum_Q w_Q a_Q^T Cref b_Q and stops when
+ * sqrt(<r, r> / <r0, r0>) <= eta; since r = D z for the displacement
+ * scheme's preconditioned residual z, this is the Sec. 6 stopping test and
+ * the iterates are eps_k = D u_k (the paper's equivalence).  3D hex8
+ * elasticity with a phase field; every load case of fh_set_load, one after
+ * another, FP64 (opt->precision must be FH_FP64; flags and guess are
+ * ignored).  Afterwards fh_get_homogenized returns the energy-form C_hom of
+ * the strain fields, fh_get_history the residual history of each load, and
+ * fh_stats the iterations.  Library-owned device memory: (nload + 3) x 48 N
+ * + 24 N doubles, kept until the grid changes or the context is destroyed. */
+int fh_solve_strain_based(fh_ctx *ctx, const fh_opts *opt, fh_stats *st);
+/* eps_dev: 6 x 8 x N doubles (device): strain fluctuation D u of load
+ * `load` at the Gauss points, [Mandel comp][Gauss point q = qx + 2 qy +
+ * 4 qz][voxel].  FH_ESTATE before fh_solve_strain_based (or after a later
+ * fh_solve).                                                               */
+int fh_get_strain(fh_ctx *ctx, int load, double *eps_dev);
 
 /* ------------------------------------------------------------ batches
  * Many independent microstructures (possibly of different grid sizes), each

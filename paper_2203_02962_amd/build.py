@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfh.so")
-SOURCES = ["ctx.hip", "kop.hip", "fft.hip", "vec.hip", "net.hip"]
+SOURCES = ["ctx.hip", "kop.hip", "fft.hip", "vec.hip", "net.hip", "bounds.hip", "plastic.hip", "sb.hip", "tn.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]

@@ -107,6 +107,25 @@ struct fh_ctx {
   double* ref_sk_dev = nullptr;
   size_t sk_dev_n = 0, ref_sk_dev_n = 0;
   double* lm_dev = nullptr;
+  double* bound_tab_dev = nullptr;  // eigenvalue pairs per material table (Sec. 4.3)
+  size_t bound_tab_n = 0;
+  // elasto-plastic Newton loop (fh_set_plastic_phases, fh_newton_solve):
+  // per-phase {K, G, sy0, H}; per-point committed state and tangent; the
+  // element forces of the material stage; the displacement of the loop
+  bool plastic = false;
+  bool qp_tangent = false;  // apply_K uses the per-point tangent
+  std::vector<double> pl_params;
+  double* pl_params_dev = nullptr;
+  double *pl_eps_p = nullptr, *pl_alpha = nullptr, *pl_ta = nullptr, *pl_tv = nullptr;
+  double *pl_fe = nullptr, *pl_u = nullptr, *pl_part = nullptr;
+  // strain-based scheme (fh_solve_strain_based): strain fields of every load
+  // case, CG vectors, element forces, raw Mandel tables; library-owned
+  double *sb_eps = nullptr, *sb_r = nullptr, *sb_p = nullptr, *sb_q = nullptr;
+  double *sb_fe = nullptr, *sb_C = nullptr;
+  int sb_nload = 0;
+  bool sb_solved = false;
+  int pl_nb = 0;   // blocks of the material-stage launches
+  int pl_nbg = 0;  // blocks of the node gather (p.q partials)
   float* lm_dev_f = nullptr;
   double* ref_lm_dev = nullptr;
   size_t lm_dev_n = 0, ref_lm_dev_n = 0;
@@ -149,6 +168,12 @@ struct fh_ctx {
     double ms[FH_K_NCLASS] = {};
     long long n[FH_K_NCLASS] = {};       // timed launches
     long long issued[FH_K_NCLASS] = {};  // all launches while on
+    // load-case units of the timed launches: the PCG loop index of every
+    // timed launch of the current pcg_run, resolved to the number of load
+    // cases still iterating once their final counts are known
+    int cur_iter = 0;
+    std::vector<std::pair<int, int>> timed_iters;  // (class, loop index)
+    double units[FH_K_NCLASS] = {};
   } kt;
 
   // batched solves: nms microstructures of this grid, G = loads each
@@ -157,6 +182,7 @@ struct fh_ctx {
   bool own_stream = false;
   uint8_t* phase_pack = nullptr;
   std::vector<std::vector<double>> cmean_ms;
+  std::vector<unsigned long long> phase_counts;  // voxels per phase (compute_mean)
 
   bool symbol_ok = false;
   bool rhs_ok = false;
@@ -181,6 +207,10 @@ int fail(fh_ctx* c, int code, const std::string& msg) {
     if (_e != hipSuccess)                                                           \
       return fail(ctx, FH_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
   } while (0)
+
+// stored K^+ entries per frequency: the unique entries of a real symmetric
+// block, or 4 reals of the Hermitian two-node block
+int nsym_of(const fh::Grid& g) { return g.tn ? 4 : g.nd * (g.nd + 1) / 2; }
 
 int mdim(const fh_ctx* c) {
   const int d = c->g.dim;
@@ -240,6 +270,22 @@ struct ElemDef {
 
 ElemDef make_element(int element) {
   ElemDef e{};
+  if (element == FH_TRI4) {
+    // corners 0..3 (bit 0 = x, bit 1 = y offset), centre 4; triangles on the
+    // bottom, right, top and left pixel edges, each with the centre
+    e.dim = 2; e.nc = 5; e.nq = 4;
+    e.grad.assign(4 * 5 * 2, 0.0);
+    auto G = [&](int q, int a, double gx, double gy) {
+      e.grad[(q * 5 + a) * 2 + 0] = gx;
+      e.grad[(q * 5 + a) * 2 + 1] = gy;
+    };
+    G(0, 0, -1, -1); G(0, 1, 1, -1); G(0, 4, 0, 2);   // bottom: 1-x-y, x-y, 2y
+    G(1, 1, 1, -1);  G(1, 3, 1, 1);  G(1, 4, -2, 0);  // right: x-y, x+y-1, 2-2x
+    G(2, 3, 1, 1);   G(2, 2, -1, 1); G(2, 4, 0, -2);  // top: x+y-1, y-x, 2-2y
+    G(3, 2, -1, 1);  G(3, 0, -1, -1); G(3, 4, 2, 0);  // left: y-x, 1-x-y, 2x
+    e.wfrac = {0.25, 0.25, 0.25, 0.25};
+    return e;
+  }
   if (element == FH_TRI2) {
     e.dim = 2; e.nc = 4; e.nq = 2;
     e.grad.assign(2 * 4 * 2, 0.0);
@@ -287,9 +333,12 @@ std::vector<GradRow> grad_rows(int problem, int dim) {
           {4, 0, 2, s}, {4, 2, 0, s}, {5, 0, 1, s}, {5, 1, 0, s}};
 }
 
+// degrees of freedom per node (the two-node stencil's fields are node sets)
+int pnd(const fh_ctx* c) { return c->problem == FH_ELASTIC ? c->g.dim : 1; }
+
 // B_q (m x nc*nd) in physical coordinates
 std::vector<double> bmat(const fh_ctx* c, const ElemDef& e, int q) {
-  const int m = mdim(c), nd = c->g.nd, nk = e.nc * nd;
+  const int m = mdim(c), nd = pnd(c), nk = e.nc * nd;
   std::vector<double> B((size_t)m * nk, 0.0);
   for (const GradRow& r : grad_rows(c->problem, e.dim))
     for (int a = 0; a < e.nc; ++a)
@@ -307,7 +356,7 @@ double voxel_volume(const fh_ctx* c) {
 // K_e = sum_q w_q B_q^T C B_q
 std::vector<double> element_matrix(const fh_ctx* c, const double* C) {
   const ElemDef e = make_element(c->element);
-  const int m = mdim(c), nk = e.nc * c->g.nd;
+  const int m = mdim(c), nk = e.nc * pnd(c);
   const double Vp = voxel_volume(c);
   std::vector<double> K((size_t)nk * nk, 0.0);
   for (int q = 0; q < e.nq; ++q) {
@@ -335,6 +384,21 @@ std::vector<double> element_matrix(const fh_ctx* c, const double* C) {
 // for all three stencils (divergence theorem), so antipodal corners get
 // exactly opposite forces.
 std::vector<double> uniform_strain_force(const fh_ctx* c, const double* C, const double* E) {
+  if (c->element == FH_TRI4) {
+    // f = sum_q w_q B_q^T (C E)
+    const ElemDef el = make_element(FH_TRI4);
+    const int m = mdim(c), nk = el.nc * pnd(c);
+    std::vector<double> sig(m, 0.0), f(nk, 0.0);
+    for (int i = 0; i < m; ++i)
+      for (int k = 0; k < m; ++k) sig[i] += C[i * m + k] * E[k];
+    for (int q = 0; q < el.nq; ++q) {
+      const std::vector<double> B = bmat(c, el, q);
+      const double w = el.wfrac[q] * voxel_volume(c);
+      for (int j = 0; j < nk; ++j)
+        for (int i = 0; i < m; ++i) f[j] += w * B[(size_t)i * nk + j] * sig[i];
+    }
+    return f;
+  }
   const int m = mdim(c), nd = c->g.nd, dim = c->g.dim, nc = 1 << dim;
   const double Vp = voxel_volume(c);
   std::vector<double> sig(m, 0.0);
@@ -386,6 +450,26 @@ double isotropic_k(const double* A, int d) {
       if (i == j && std::fabs(v - A[0]) > 1e-14 * mx) return -1.0;
     }
   return A[0] > 0.0 ? A[0] : -1.0;
+}
+
+void free_plastic(fh_ctx* c) {
+  for (double** p : {&c->pl_params_dev, &c->pl_eps_p, &c->pl_alpha, &c->pl_ta, &c->pl_tv,
+                     &c->pl_fe, &c->pl_u, &c->pl_part}) {
+    hipFree(*p);
+    *p = nullptr;
+  }
+  c->plastic = false;
+  c->qp_tangent = false;
+  c->pl_params.clear();
+}
+
+void free_sb(fh_ctx* c) {
+  for (double** p : {&c->sb_eps, &c->sb_r, &c->sb_p, &c->sb_q, &c->sb_fe, &c->sb_C}) {
+    hipFree(*p);
+    *p = nullptr;
+  }
+  c->sb_nload = 0;
+  c->sb_solved = false;
 }
 
 void free_tables(fh_ctx* c) {
@@ -454,7 +538,7 @@ size_t layout(fh_ctx* c, char* base, fh_ctx::Layout* Lout) {
   const long long F = (long long)g.nd * g.N;
   const long long S = (long long)g.nd * g.nxh * g.ny * g.nz;
   const long long nfreq = (long long)g.nxh * g.ny * g.nz;
-  const int nsym = g.nd * (g.nd + 1) / 2;
+  const int nsym = nsym_of(g);
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
     char* p = base ? base + off : nullptr;
@@ -582,7 +666,19 @@ int apply_K(fh_ctx* c, bool ref, const double* u, double* q, int nload, long lon
   const double* kf = ref ? nullptr : (c->mat_kind == 2 ? c->kfield_dev : nullptr);
   const double* tab = ref ? c->ref_dev : c->mat_dev;
   int nb = 0;
-  if (hex_scalar(c) && (ref ? c->ref_sc : c->sc)) {
+  if (!ref && c->qp_tangent) {
+    // per-point tangent of the Newton step (one load case)
+    if (nload != 1) return fail(c, FH_EINVAL, "the tangent operator takes one field");
+    HIPCHK(c, fh::launch_plastic_stage(1, g, c->phase_dev, c->pl_params_dev, nullptr, u,
+                                       c->pl_fe, nullptr, nullptr, c->pl_ta, c->pl_tv, nullptr,
+                                       c->pl_nb, c->stream));
+    HIPCHK(c, fh::launch_gather_nodes(g, c->pl_fe, 1.0, q, pq ? u : nullptr, pq, c->pl_nbg,
+                                      c->stream));
+  } else if (c->element == FH_TRI4) {
+    if (!ph && !kf) ph = c->L.phase0;
+    HIPCHK(c, fh::launch_kop_tn<double>(g, u, q, ph, kf, tab, nload, stride, stride, st, pq, &nb,
+                                        c->stream));
+  } else if (hex_scalar(c) && (ref ? c->ref_sc : c->sc)) {
     HIPCHK(c, fh::launch_kop_hex8_scalar<double>(g, u, q, kf ? nullptr : (ph ? ph : c->L.phase0),
                                                  kf, ref ? c->ref_sk_dev : c->sk_dev, nload,
                                                  stride, stride, st, pq, &nb, c->stream));
@@ -607,7 +703,11 @@ int apply_K32(fh_ctx* c, const float* u, float* q, int nload, long long stride,
   g.nphase_max = c->mat_kind == 1 ? c->nphase : 1;
   const uint8_t* ph = c->mat_kind == 1 ? c->phase_dev : nullptr;
   int nb = 0;
-  if (hex_scalar(c) && c->sc) {
+  if (c->element == FH_TRI4) {
+    const float* kf = c->mat_kind == 2 ? c->L.kf32 : nullptr;
+    HIPCHK(c, fh::launch_kop_tn<float>(g, u, q, kf ? nullptr : ph, kf, c->mat_dev_f, nload,
+                                       stride, stride, st, pq, &nb, c->stream));
+  } else if (hex_scalar(c) && c->sc) {
     const float* kf = c->mat_kind == 2 ? c->L.kf32 : nullptr;
     HIPCHK(c, fh::launch_kop_hex8_scalar<float>(g, u, q, kf ? nullptr : ph, kf, c->sk_dev_f,
                                                 nload, stride, stride, st, pq, &nb, c->stream));
@@ -661,16 +761,11 @@ int check_material(fh_ctx* c) {
   return FH_OK;
 }
 
-// Reference material, symbol (Alg. 2) and Kref tables.
-int build_symbol(fh_ctx* c) {
-  int rc = check_material(c);
-  if (rc) return rc;
-  rc = ensure_layout(c);
-  if (rc) return rc;
-  if (c->symbol_ok) return FH_OK;
+// Quadrature-weighted mean of the material (Sec. 6.2) into c->cmean; for a
+// phase field also the voxel count of every phase into c->phase_counts.
+int compute_mean(fh_ctx* c) {
   const fh::Grid& g = c->g;
   const int m = mdim(c);
-  // quadrature-weighted mean of the material (Sec. 6.2)
   c->cmean.assign((size_t)m * m, 0.0);
   HIPCHK(c, hipMemsetAsync(c->flag_dev, 0, sizeof(int), c->stream));
   if (c->mat_kind == 1) {
@@ -684,6 +779,7 @@ int build_symbol(fh_ctx* c) {
     HIPCHK(c, hipMemcpyAsync(&bad, c->flag_dev, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (bad) return fail(c, FH_EINVAL, "phase id >= nphase in phase field");
+    c->phase_counts.assign(counts, counts + c->nphase);
     for (int p = 0; p < c->nphase; ++p)
       for (int i = 0; i < m * m; ++i)
         c->cmean[i] += (double)counts[p] * c->mat[(size_t)p * m * m + i];
@@ -702,6 +798,20 @@ int build_symbol(fh_ctx* c) {
       return fail(c, FH_EINVAL, "conductivity field must be positive and finite in every voxel");
     for (int i = 0; i < m; ++i) c->cmean[i * m + i] = ks / (double)g.N;
   }
+  return FH_OK;
+}
+
+// Reference material, symbol (Alg. 2) and Kref tables.
+int build_symbol(fh_ctx* c) {
+  int rc = check_material(c);
+  if (rc) return rc;
+  rc = ensure_layout(c);
+  if (rc) return rc;
+  if (c->symbol_ok) return FH_OK;
+  const fh::Grid& g = c->g;
+  const int m = mdim(c);
+  rc = compute_mean(c);
+  if (rc) return rc;
   c->cref = c->cref_user ? c->cref_in : c->cmean;
   if (!cholesky_ok(c->cref, m)) return fail(c, FH_ENOTSPD, "reference material is not SPD");
   rc = upload(c, &c->ref_dev, &c->ref_dev_n, operator_tables(c, c->cref.data(), 1));
@@ -741,8 +851,12 @@ int build_symbol(fh_ctx* c) {
                                        S, nullptr, 1, nullptr, nullptr, &nb, c->stream));
   }
   HIPCHK(c, hipMemsetAsync(c->flag_dev, 0, sizeof(int), c->stream));
-  HIPCHK(c, fh::launch_symbol(g, c->L.spec, S, c->L.kplus, c->flag_dev, c->stream));
-  const long long nsym_n = (long long)g.nxh * g.ny * g.nz * (g.nd * (g.nd + 1) / 2);
+  if (g.tn)
+    HIPCHK(c, fh::launch_symbol_tn(g, c->L.spec, S, c->L.kplus, c->flag_dev, c->L.dot_part,
+                                   c->stream));
+  else
+    HIPCHK(c, fh::launch_symbol(g, c->L.spec, S, c->L.kplus, c->flag_dev, c->stream));
+  const long long nsym_n = (long long)g.nxh * g.ny * g.nz * nsym_of(g);
   HIPCHK(c, fh::launch_cast_symbol(nsym_n, c->L.kplus, c->L.kplus_f, c->stream));
   if (c->mat_kind == 2) HIPCHK(c, fh::launch_cast_d2f(c->kfield_dev, c->L.kf32, g.N, c->stream));
   int bad = 0;
@@ -848,7 +962,7 @@ int pcg_run(fh_ctx* c, int nload, const PcgBufs<T>& bf, double eta, int itmax, i
   HIPCHK(c, fh::launch_xinv<T>(g, c->px, c->twx, fh::XI_INIT_P, bf.A, S, nullptr, nullptr, bf.p,
                                F, nload, L.st, c->stream));
   HIPCHK(c, fh::launch_finalize_init(L.st, L.rz_part, nbz, nload, c->stream));
-  const int nbk = fh::kop_nblocks(g, hex_tiled(c), (int)sizeof(T));
+  const int nbk = c->qp_tangent ? c->pl_nbg : fh::kop_nblocks(g, hex_tiled(c), (int)sizeof(T));
   auto one_iteration = [&]() -> int {
       int rc = 0;
       KT(FH_K_OPERATOR, rc = apply_KT(c, bf.p, bf.q, nload, F, L.st, L.pq_part));
@@ -897,12 +1011,24 @@ int pcg_run(fh_ctx* c, int nload, const PcgBufs<T>& bf, double eta, int itmax, i
   } guard{exec};
   int done_iters = 0;
   const int cap = itmax + 2;
+  // Iterations until the next status poll.  After the first window the
+  // count follows the observed contraction of sqrt(r.z / r0.z0) since the
+  // previous poll, so that the loop stops close to the last load's
+  // convergence instead of running up to poll - 1 iterations in which every
+  // load case has stopped (those launches only test the status and exit).
+  int window = poll;
+  std::vector<double> prev_last(nload, 1.0);
+  std::vector<int> prev_iter(nload, 0);
   while (true) {
-    for (int k = 0; k < poll && done_iters < cap; ++k, ++done_iters) {
+    for (int k = 0; k < window && done_iters < cap; ++k, ++done_iters) {
       if (exec) {
         HIPCHK(c, hipGraphLaunch(exec, c->stream));
       } else {
-        c->kt.sample = done_iters % c->kt.period == 0;
+        // sampled iterations sit mid-way between the 16-iteration status
+        // polls: the iteration right after a poll starts on an idle GPU, and
+        // its first event pair would include the host's launch latency
+        c->kt.sample = done_iters % c->kt.period == c->kt.period / 2;
+        c->kt.cur_iter = done_iters;
         const int rc = one_iteration();
         c->kt.sample = true;
         if (rc) return rc;
@@ -915,7 +1041,29 @@ int pcg_run(fh_ctx* c, int nload, const PcgBufs<T>& bf, double eta, int itmax, i
     bool any = false;
     for (auto& st : hs) any |= (st.status == fh::ST_ACTIVE);
     if (!any || done_iters >= cap) break;
+    window = poll;
+    for (int j = 0; j < nload; ++j) {
+      const fh::PcgState& sj = hs[j];
+      if (sj.status != fh::ST_ACTIVE) continue;
+      const int di = sj.iter - prev_iter[j];
+      if (di > 0 && sj.last > 0.0 && prev_last[j] > 0.0 && sj.last < prev_last[j]) {
+        const double rate = std::pow(sj.last / prev_last[j], 1.0 / di);
+        const double need = std::log(std::sqrt(sj.eta2) / sj.last) / std::log(rate);
+        if (std::isfinite(need)) window = std::min(window, std::max(1, (int)std::ceil(need)));
+      }
+      prev_last[j] = sj.last;
+      prev_iter[j] = sj.iter;
+    }
   }
+  // A load case takes part in loop iteration k (0-based) of this run if it
+  // started active and its final count exceeds k: its last iteration still
+  // runs every pass (the x update of a converged load is due then).
+  for (const auto& ti : c->kt.timed_iters) {
+    int act = 0;
+    for (int j = 0; j < nload; ++j) act += (active[j] && ti.second < hs[j].iter) ? 1 : 0;
+    c->kt.units[ti.first] += act;
+  }
+  c->kt.timed_iters.clear();
   out = hs;
   return FH_OK;
 }
@@ -1201,6 +1349,7 @@ int kt_begin(fh_ctx* c, int cls) {
   }
   const int slot = (int)t.used++;
   t.cls[slot] = cls;
+  t.timed_iters.emplace_back(cls, t.cur_iter);
   hipEventRecord(t.ev[2 * slot], c->stream);
   return slot;
 }
@@ -1605,6 +1754,9 @@ void fh_destroy(fh_ctx* c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   hipFree(c->ws_own);
   free_tables(c);
+  free_plastic(c);
+  free_sb(c);
+  hipFree(c->bound_tab_dev);
   hipFree(c->counts_dev);
   hipFree(c->flag_dev);
   hipFree(c->twx);
@@ -1632,8 +1784,10 @@ int fh_set_grid(fh_ctx* c, int dim, const int n[3], const double l[3], int probl
   if (dim != 2 && dim != 3) return fail(c, FH_EINVAL, "dim must be 2 or 3");
   if (problem != FH_SCALAR && problem != FH_ELASTIC) return fail(c, FH_EINVAL, "bad problem");
   if ((dim == 3) != (element == FH_HEX8) ||
-      (element != FH_HEX8 && element != FH_QUAD4 && element != FH_TRI2))
+      (element != FH_HEX8 && element != FH_QUAD4 && element != FH_TRI2 && element != FH_TRI4))
     return fail(c, FH_EINVAL, "element does not match dim");
+  if (element == FH_TRI4 && problem != FH_SCALAR)
+    return fail(c, FH_EINVAL, "the two-node stencil is built for scalar problems");
   int nn[3] = {n[0], n[1], dim == 3 ? n[2] : 1};
   for (int k = 0; k < 3; ++k)
     if (nn[k] < 1 || nn[k] > 256 || !factor_ok(nn[k]))
@@ -1647,7 +1801,8 @@ int fh_set_grid(fh_ctx* c, int dim, const int n[3], const double l[3], int probl
   c->g.ny = nn[1];
   c->g.nz = nn[2];
   c->g.dim = dim;
-  c->g.nd = problem == FH_ELASTIC ? dim : 1;
+  c->g.nd = (problem == FH_ELASTIC ? dim : 1) * (element == FH_TRI4 ? 2 : 1);
+  c->g.tn = element == FH_TRI4 ? 1 : 0;
   c->g.nxh = nn[0] / 2 + 1;
   c->g.N = (long long)nn[0] * nn[1] * nn[2];
   c->g.nphase_max = 1;
@@ -1682,6 +1837,8 @@ int fh_set_grid(fh_ctx* c, int dim, const int n[3], const double l[3], int probl
   c->layout_ok = false;
   c->symbol_ok = c->rhs_ok = c->solved = false;
   free_tables(c);
+  free_plastic(c);
+  free_sb(c);
   return FH_OK;
 }
 
@@ -1699,6 +1856,7 @@ int fh_set_phases(fh_ctx* c, const uint8_t* phase_dev, int nphase, const double*
         if (!std::isfinite(a) || std::fabs(a - b) > 1e-12 * (std::fabs(a) + std::fabs(b)))
           return fail(c, FH_EINVAL, "material tables must be finite and symmetric");
       }
+  if (c->plastic) free_plastic(c);
   c->phase_dev = phase_dev;
   c->nphase = nphase;
   c->g.nphase_max = nphase;
@@ -1750,6 +1908,7 @@ int fh_set_conductivity_field(fh_ctx* c, const double* k_dev) {
   if (!c->has_grid) return fail(c, FH_ESTATE, "fh_set_grid not called");
   if (c->problem != FH_SCALAR) return fail(c, FH_EINVAL, "conductivity field needs FH_SCALAR");
   if (!k_dev) return fail(c, FH_EINVAL, "null field");
+  if (c->plastic) free_plastic(c);
   c->kfield_dev = k_dev;
   c->phase_dev = nullptr;
   c->mat_kind = 2;
@@ -1838,15 +1997,18 @@ int fh_solve(fh_ctx* c, const fh_opts* opt, fh_stats* st) {
   const int poll = o.poll > 0 ? o.poll : 16;
   auto t0 = std::chrono::steady_clock::now();
   c->solved = false;
+  c->sb_solved = false;
   c->kt.on = (o.flags & FH_FLAG_TIME_KERNELS) != 0;
   c->kt.period = (o.flags & FH_FLAG_TIME_SAMPLED) ? 8 : 1;
   c->kt.sample = true;
   if (o.flags & FH_FLAG_REBUILD) c->symbol_ok = c->rhs_ok = false;
   c->kt.used = 0;
+  c->kt.timed_iters.clear();
   for (int k = 0; k < FH_K_NCLASS; ++k) {
     c->kt.ms[k] = 0.0;
     c->kt.n[k] = 0;
     c->kt.issued[k] = 0;
+    c->kt.units[k] = 0.0;
   }
   int rc = build_symbol(c);
   if (rc) return rc;
@@ -1957,6 +2119,7 @@ int fh_solve(fh_ctx* c, const fh_opts* opt, fh_stats* st) {
     c->last.kernel_ms[k] = c->kt.ms[k];
     c->last.kernel_launches[k] = c->kt.n[k];
     c->last.kernel_issued[k] = c->kt.issued[k];
+    c->last.kernel_units[k] = c->kt.units[k];
   }
   c->kt.on = false;
   if (st) *st = c->last;
@@ -1982,7 +2145,7 @@ int fh_get_fluctuation(fh_ctx* c, int load, double* u_dev) {
 
 int fh_get_homogenized(fh_ctx* c, double* Chom) {
   if (!c || !Chom) return FH_EINVAL;
-  if (!c->solved) return fail(c, FH_ESTATE, "no solution available");
+  if (!c->solved && !c->sb_solved) return fail(c, FH_ESTATE, "no solution available");
   std::memcpy(Chom, c->chom.data(), c->chom.size() * sizeof(double));
   return FH_OK;
 }
@@ -2109,7 +2272,7 @@ int fh_get_symbol(fh_ctx* c, double* kplus_dev) {
   int rc = build_symbol(c);
   if (rc) return rc;
   const fh::Grid& g = c->g;
-  const long long n = (long long)g.nxh * g.ny * g.nz * (g.nd * (g.nd + 1) / 2);
+  const long long n = (long long)g.nxh * g.ny * g.nz * nsym_of(g);
   HIPCHK(c, hipMemcpyAsync(kplus_dev, c->L.kplus, n * sizeof(double), hipMemcpyDeviceToDevice,
                            c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -2144,6 +2307,656 @@ int fh_solve_rhs(fh_ctx* c, const double* b_dev, double* u_dev, const fh_opts* o
   HIPCHK(c, hipStreamSynchronize(c->stream));
   record_history(c, hs, 1);
   return fill_stats(c, hs, 1, st);
+}
+
+}  // extern "C"
+
+// ============================================ eigenvalue bounds (Sec. 4.3)
+namespace {
+
+// Eigenvalues of a symmetric m x m matrix (cyclic Jacobi rotations).
+std::vector<double> sym_eigvals(std::vector<double> A, int m) {
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) {
+        tot += A[i * m + j] * A[i * m + j];
+        if (i != j) off += A[i * m + j] * A[i * m + j];
+      }
+    if (off <= 1e-32 * tot) break;
+    for (int p = 0; p < m; ++p)
+      for (int q = p + 1; q < m; ++q) {
+        const double apq = A[p * m + q];
+        if (apq == 0.0) continue;
+        const double theta = (A[q * m + q] - A[p * m + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < m; ++k) {  // columns p, q
+          const double akp = A[k * m + p], akq = A[k * m + q];
+          A[k * m + p] = cs * akp - sn * akq;
+          A[k * m + q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < m; ++k) {  // rows p, q
+          const double apk = A[p * m + k], aqk = A[q * m + k];
+          A[p * m + k] = cs * apk - sn * aqk;
+          A[q * m + k] = sn * apk + cs * aqk;
+        }
+      }
+  }
+  std::vector<double> ev(m);
+  for (int i = 0; i < m; ++i) ev[i] = A[i * m + i];
+  return ev;
+}
+
+// Smallest and largest generalized eigenvalue of (C, R), R SPD: the
+// eigenvalues of L^-1 C L^-T with R = L L^T.
+bool gen_eig_range(const double* C, const std::vector<double>& R, int m, double* lo, double* hi) {
+  std::vector<double> L(R);
+  for (int j = 0; j < m; ++j) {
+    double d = L[j * m + j];
+    for (int k = 0; k < j; ++k) d -= L[j * m + k] * L[j * m + k];
+    if (!(d > 0.0)) return false;
+    d = std::sqrt(d);
+    L[j * m + j] = d;
+    for (int i = j + 1; i < m; ++i) {
+      double sm = L[i * m + j];
+      for (int k = 0; k < j; ++k) sm -= L[i * m + k] * L[j * m + k];
+      L[i * m + j] = sm / d;
+    }
+    for (int k = j + 1; k < m; ++k) L[j * m + k] = 0.0;
+  }
+  // Y = L^-1 C (forward substitution per column), then A = L^-1 Y^T
+  std::vector<double> Y((size_t)m * m), A((size_t)m * m);
+  for (int col = 0; col < m; ++col)
+    for (int i = 0; i < m; ++i) {
+      double sm = C[i * m + col];
+      for (int k = 0; k < i; ++k) sm -= L[i * m + k] * Y[k * m + col];
+      Y[i * m + col] = sm / L[i * m + i];
+    }
+  for (int col = 0; col < m; ++col)
+    for (int i = 0; i < m; ++i) {
+      double sm = Y[col * m + i];  // (Y^T)[i][col]
+      for (int k = 0; k < i; ++k) sm -= L[i * m + k] * A[k * m + col];
+      A[i * m + col] = sm / L[i * m + i];
+    }
+  for (int i = 0; i < m; ++i)  // symmetrise the rounding
+    for (int j = i + 1; j < m; ++j) A[i * m + j] = A[j * m + i] = 0.5 * (A[i * m + j] + A[j * m + i]);
+  const std::vector<double> ev = sym_eigvals(A, m);
+  *lo = *std::min_element(ev.begin(), ev.end());
+  *hi = *std::max_element(ev.begin(), ev.end());
+  return true;
+}
+
+// Per material table, the (lo, hi) generalized eigenvalue pair of
+// (C_table, R); for a conductivity field, the pair of the unit conductivity.
+int bound_tables(fh_ctx* c, const std::vector<double>& R, std::vector<double>& tab) {
+  const int m = mdim(c);
+  tab.clear();
+  if (c->mat_kind == 1) {
+    for (int p = 0; p < c->nphase; ++p) {
+      double lo, hi;
+      if (!gen_eig_range(c->mat.data() + (size_t)p * m * m, R, m, &lo, &hi))
+        return fail(c, FH_ENOTSPD, "reference material is not SPD");
+      tab.push_back(lo);
+      tab.push_back(hi);
+    }
+  } else {
+    std::vector<double> I((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i) I[i * m + i] = 1.0;
+    double lo, hi;
+    if (!gen_eig_range(I.data(), R, m, &lo, &hi))
+      return fail(c, FH_ENOTSPD, "reference material is not SPD");
+    tab = {lo, hi};
+  }
+  return FH_OK;
+}
+
+// Classical CG estimate: the energy-norm error falls by eta within
+// ceil(sqrt(kappa)/2 ln(2/eta)) iterations.
+int cg_iteration_bound(double kappa, double eta) {
+  if (!(kappa >= 1.0) || !(eta > 0.0) || eta >= 2.0) return 0;
+  const double v = std::ceil(0.5 * std::sqrt(kappa) * std::log(2.0 / eta));
+  return v > 2e9 ? 2000000000 : (int)v;
+}
+
+// Range of the nodal bounds for reference R over the whole grid: from the
+// phases present (every voxel's pair is some node's extreme), or from the
+// kernel's reduction for a conductivity field.
+int bounds_range(fh_ctx* c, const std::vector<double>& R, double* lo, double* hi,
+                 double* lo_dev, double* hi_dev) {
+  std::vector<double> tab;
+  int rc = bound_tables(c, R, tab);
+  if (rc) return rc;
+  if (c->mat_kind == 1 && !lo_dev && !hi_dev) {
+    double a = HUGE_VAL, b = -HUGE_VAL;
+    for (int p = 0; p < c->nphase; ++p)
+      if (c->phase_counts[p] > 0) {
+        a = std::min(a, tab[2 * p]);
+        b = std::max(b, tab[2 * p + 1]);
+      }
+    *lo = a;
+    *hi = b;
+    return FH_OK;
+  }
+  rc = upload(c, &c->bound_tab_dev, &c->bound_tab_n, tab);
+  if (rc) return rc;
+  const fh::Grid& g = c->g;
+  double* part = c->L.dot_part;  // 1024 doubles: 2 per block
+  if (fh::node_bounds_partials(g) * 2 > 1024) return fail(c, FH_EINVAL, "bounds partials");
+  HIPCHK(c, fh::launch_node_bounds(g, c->mat_kind == 1 ? c->phase_dev : nullptr,
+                                   c->mat_kind == 2 ? c->kfield_dev : nullptr, c->bound_tab_dev,
+                                   lo_dev, hi_dev, part, c->L.scal, c->stream));
+  double r[2];
+  HIPCHK(c, hipMemcpyAsync(r, c->L.scal, sizeof(r), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  *lo = r[0];
+  *hi = r[1];
+  return FH_OK;
+}
+
+// Isotropic Mandel stiffness with bulk modulus K and shear modulus G.
+std::vector<double> iso_mandel(double K, double G) {
+  std::vector<double> C(36, 0.0);
+  const double lam = K - 2.0 * G / 3.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C[i * 6 + j] = lam + (i == j ? 2.0 * G : 0.0);
+  for (int i = 3; i < 6; ++i) C[i * 6 + i] = 2.0 * G;
+  return C;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fh_eigen_bounds(fh_ctx* c, const double* Cref, double eta, double* lo_dev, double* hi_dev,
+                    fh_bounds* out) {
+  if (!c || !out) return FH_EINVAL;
+  hipSetDevice(c->device);
+  int rc = check_material(c);
+  if (rc) return rc;
+  if (c->element == FH_TRI4)
+    return fail(c, FH_EINVAL, "eigenvalue bounds are built for one-node stencils");
+  if ((rc = ensure_layout(c))) return rc;
+  if ((rc = compute_mean(c))) return rc;
+  const int m = mdim(c);
+  std::vector<double> R = Cref ? std::vector<double>(Cref, Cref + (size_t)m * m)
+                               : (c->cref_user ? c->cref_in : c->cmean);
+  double lo = 0, hi = 0;
+  if ((rc = bounds_range(c, R, &lo, &hi, lo_dev, hi_dev))) return rc;
+  fh_bounds b{};
+  b.lambda_min = lo;
+  b.lambda_max = hi;
+  b.kappa = hi / lo;
+  b.predicted_iterations = cg_iteration_bound(b.kappa, eta);
+  *out = b;
+  return FH_OK;
+}
+
+int fh_choose_reference(fh_ctx* c, int strategy, double* Cref_out, fh_bounds* out) {
+  if (!c) return FH_EINVAL;
+  hipSetDevice(c->device);
+  if (strategy < FH_REF_MEAN || strategy > FH_REF_BEST)
+    return fail(c, FH_EINVAL, "unknown reference strategy");
+  int rc = check_material(c);
+  if (rc) return rc;
+  if (c->element == FH_TRI4)
+    return fail(c, FH_EINVAL, "eigenvalue bounds are built for one-node stencils");
+  if ((rc = ensure_layout(c))) return rc;
+  if ((rc = compute_mean(c))) return rc;
+  const int m = mdim(c);
+  std::vector<double> ident((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) ident[i * m + i] = 1.0;
+  auto kappa_of = [&](const std::vector<double>& R, double* kap) -> int {
+    double lo = 0, hi = 0;
+    const int r = bounds_range(c, R, &lo, &hi, nullptr, nullptr);
+    if (r) return r;
+    *kap = hi / lo;
+    return FH_OK;
+  };
+  std::vector<std::vector<double>> cand;
+  if (strategy == FH_REF_MEAN || strategy == FH_REF_BEST) cand.push_back(c->cmean);
+  if (strategy == FH_REF_IDENTITY || strategy == FH_REF_BEST) cand.push_back(ident);
+  if (strategy == FH_REF_BEST && c->mat_kind == 1 && m == 6) {
+    // isotropic phases: the isotropic reference with the smallest bound.  The
+    // generalized eigenvalues of two isotropic stiffnesses are the ratios of
+    // their bulk and shear moduli, so the bound depends only on K_r / G_r;
+    // golden-section search in log(K_r / G_r), with G_r fixed by the mean.
+    bool all_iso = true;
+    for (int p = 0; p < c->nphase && all_iso; ++p) {
+      double lm[2];
+      all_iso = isotropic_lm(c->mat.data() + (size_t)p * 36, 1.0, lm);
+    }
+    double lmm[2];
+    if (all_iso && isotropic_lm(c->cmean.data(), 1.0, lmm)) {
+      const double Gm = 0.5 * lmm[1], Km = lmm[0] + lmm[1] / 3.0;
+      auto f = [&](double s, double* kap) {  // s = log(K_r/G_r) - log(K_m/G_m)
+        return kappa_of(iso_mandel(Km * std::exp(s), Gm), kap);
+      };
+      double a = -12.0, b = 12.0;
+      const double gr = 0.5 * (std::sqrt(5.0) - 1.0);
+      double x1 = b - gr * (b - a), x2 = a + gr * (b - a), f1, f2;
+      if ((rc = f(x1, &f1)) || (rc = f(x2, &f2))) return rc;
+      for (int it = 0; it < 80; ++it) {
+        if (f1 <= f2) {
+          b = x2; x2 = x1; f2 = f1; x1 = b - gr * (b - a);
+          if ((rc = f(x1, &f1))) return rc;
+        } else {
+          a = x1; x1 = x2; f1 = f2; x2 = a + gr * (b - a);
+          if ((rc = f(x2, &f2))) return rc;
+        }
+      }
+      cand.push_back(iso_mandel(Km * std::exp(f1 <= f2 ? x1 : x2), Gm));
+    }
+  }
+  int best = -1;
+  double kbest = HUGE_VAL;
+  for (size_t i = 0; i < cand.size(); ++i) {
+    double k = 0;
+    if ((rc = kappa_of(cand[i], &k))) return rc;
+    if (k < kbest) {  // first of equal bounds wins: mean, then I_s
+      kbest = k;
+      best = (int)i;
+    }
+  }
+  if ((rc = fh_set_reference(c, cand[best].data()))) return rc;
+  if (Cref_out) std::copy(cand[best].begin(), cand[best].end(), Cref_out);
+  if (out) {
+    double lo = 0, hi = 0;
+    if ((rc = bounds_range(c, cand[best], &lo, &hi, nullptr, nullptr))) return rc;
+    out->lambda_min = lo;
+    out->lambda_max = hi;
+    out->kappa = hi / lo;
+    out->predicted_iterations = 0;
+  }
+  return FH_OK;
+}
+
+}  // extern "C"
+
+// ==================================== elasto-plastic Newton loop (Alg. 1)
+namespace {
+
+// Host sums (fixed order) of the material stage's per-block partials.
+int plastic_sums(fh_ctx* c, std::vector<double>& out) {
+  const int np = fh::plastic_parts();
+  std::vector<double> part((size_t)c->pl_nb * np);
+  HIPCHK(c, hipMemcpyAsync(part.data(), c->pl_part, part.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  out.assign(np, 0.0);
+  for (int b = 0; b < c->pl_nb; ++b)
+    for (int k = 0; k < np; ++k) out[k] += part[(size_t)b * np + k];
+  return FH_OK;
+}
+
+// sum of squares of a nodal field (device partials, fixed-order sum)
+int field_dot(fh_ctx* c, const double* a, const double* b, long long n, double* out) {
+  const int nb = 1024;
+  HIPCHK(c, fh::launch_dot_partials(a, b, n, c->L.dot_part, nb, c->stream));
+  HIPCHK(c, fh::launch_sum_partials(c->L.dot_part, nb, c->L.scal, c->stream));
+  HIPCHK(c, hipMemcpyAsync(out, c->L.scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fh_set_plastic_phases(fh_ctx* c, const uint8_t* phase_dev, int nphase, const double* params) {
+  if (!c) return FH_EINVAL;
+  hipSetDevice(c->device);
+  if (!c->has_grid) return fail(c, FH_ESTATE, "fh_set_grid not called");
+  if (!hex_elastic(c) || c->g.dim != 3)
+    return fail(c, FH_EINVAL, "plastic phases need 3D hex8 elasticity");
+  if (!phase_dev || !params || nphase < 1 || nphase > 256)
+    return fail(c, FH_EINVAL, "bad phase arguments");
+  for (int p = 0; p < nphase; ++p) {
+    const double K = params[4 * p], G = params[4 * p + 1], sy = params[4 * p + 2],
+                 H = params[4 * p + 3];
+    if (!(K > 0.0) || !(G > 0.0) || !(sy >= 0.0) || !(H > 0.0) || !std::isfinite(K) ||
+        !std::isfinite(G) || !std::isfinite(sy) || !std::isfinite(H))
+      return fail(c, FH_EINVAL, "plastic phase needs K > 0, G > 0, sy0 >= 0, H > 0 (finite)");
+  }
+  // the elastic stiffness of every phase: the material of the linear problem
+  std::vector<double> mats((size_t)nphase * 36, 0.0);
+  for (int p = 0; p < nphase; ++p) {
+    const double K = params[4 * p], G = params[4 * p + 1];
+    double* C = mats.data() + (size_t)p * 36;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) C[i * 6 + j] = K - 2.0 * G / 3.0 + (i == j ? 2.0 * G : 0.0);
+    for (int i = 3; i < 6; ++i) C[i * 6 + i] = 2.0 * G;
+  }
+  int rc = fh_set_phases(c, phase_dev, nphase, mats.data());
+  if (rc) return rc;
+  const long long N = c->g.N;
+  c->pl_params.assign(params, params + 4 * (size_t)nphase);
+  c->pl_nb = fh::plastic_blocks(c->g, 2048);
+  struct Buf { double** p; size_t n; };
+  const Buf bufs[] = {{&c->pl_params_dev, 4 * (size_t)nphase}, {&c->pl_eps_p, 48 * (size_t)N},
+                      {&c->pl_alpha, 8 * (size_t)N}, {&c->pl_ta, 8 * (size_t)N},
+                      {&c->pl_tv, 48 * (size_t)N}, {&c->pl_fe, 24 * (size_t)N},
+                      {&c->pl_u, 3 * (size_t)N},
+                      {&c->pl_part, (size_t)c->pl_nb * fh::plastic_parts()}};
+  for (const Buf& b : bufs) {
+    if (hipMalloc((void**)b.p, b.n * sizeof(double)) != hipSuccess) {
+      free_plastic(c);
+      return fail(c, FH_ENOMEM, "hipMalloc of the plastic state failed");
+    }
+  }
+  HIPCHK(c, hipMemcpy(c->pl_params_dev, params, 4 * (size_t)nphase * sizeof(double),
+                      hipMemcpyHostToDevice));
+  c->plastic = true;
+  return FH_OK;
+}
+
+int fh_newton_solve(fh_ctx* c, const double* E_final, const fh_newton_opts* opt,
+                    fh_newton_stats* st) {
+  if (!c || !E_final) return FH_EINVAL;
+  hipSetDevice(c->device);
+  if (!c->plastic) return fail(c, FH_ESTATE, "fh_set_plastic_phases not called");
+  fh_newton_opts o{1e-8, 1e-10, 50, 10000, 1, FH_NEWTON_REF_TANGENT};
+  if (opt) o = *opt;
+  if (!(o.eta_newton > 0.0) || !(o.eta_cg > 0.0) || o.itmax_newton < 1 || o.itmax_cg < 1 ||
+      o.nincrement < 1 || o.nincrement > FH_MAX_INCREMENTS ||
+      o.itmax_newton > FH_MAX_NEWTON ||
+      (o.ref_mode != FH_NEWTON_REF_TANGENT && o.ref_mode != FH_NEWTON_REF_ELASTIC))
+    return fail(c, FH_EINVAL, "bad Newton options");
+  for (int m = 0; m < 6; ++m)
+    if (!std::isfinite(E_final[m])) return fail(c, FH_EINVAL, "loads must be finite");
+  int rc = check_material(c);
+  if (rc) return rc;
+  if ((rc = ensure_layout(c))) return rc;
+  c->pl_nbg = fh::plastic_blocks(c->g, c->L.nb_kop);
+  auto t0 = std::chrono::steady_clock::now();
+  const fh::Grid& g = c->g;
+  const long long N = g.N, F = 3 * N;
+  fh_ctx::Layout& L = c->L;
+  fh_newton_stats s{};
+  s.nincrement = o.nincrement;
+  // the caller's reference is restored at the end
+  const bool user_was = c->cref_user;
+  const std::vector<double> user_in = c->cref_in;
+  struct Restore {
+    fh_ctx* c;
+    bool user;
+    const std::vector<double>& in;
+    ~Restore() {
+      c->qp_tangent = false;
+      c->cref_user = user;
+      c->cref_in = in;
+      c->symbol_ok = false;
+      c->solved = false;
+    }
+  } restore{c, user_was, user_in};
+  HIPCHK(c, fh::launch_fill<double>(c->pl_eps_p, 0.0, 48 * N, c->stream));
+  HIPCHK(c, fh::launch_fill<double>(c->pl_alpha, 0.0, 8 * N, c->stream));
+  HIPCHK(c, fh::launch_fill<double>(c->pl_u, 0.0, F, c->stream));
+  const double vol = c->l[0] * c->l[1] * c->l[2];
+  std::vector<double> sums;
+  bool elastic_ref_done = false;
+  int result = FH_OK;
+  for (int k = 1; k <= o.nincrement; ++k) {
+    double E[6];
+    for (int m = 0; m < 6; ++m) E[m] = E_final[m] * ((double)k / o.nincrement);
+    bool conv = false;
+    int steps = 0;
+    for (int i = 0; i < o.itmax_newton; ++i) {
+      // material stage at u_(i): stress, tangent, element forces; b = -D^T W sigma
+      c->qp_tangent = false;
+      HIPCHK(c, fh::launch_plastic_stage(0, g, c->phase_dev, c->pl_params_dev, E, c->pl_u,
+                                         c->pl_fe, c->pl_eps_p, c->pl_alpha, c->pl_ta, c->pl_tv,
+                                         c->pl_part, c->pl_nb, c->stream));
+      HIPCHK(c, fh::launch_gather_nodes(g, c->pl_fe, -1.0, L.b, nullptr, nullptr, c->pl_nbg,
+                                        c->stream));
+      if ((rc = plastic_sums(c, sums))) return rc;
+      double bb = 0.0;
+      if ((rc = field_dot(c, L.b, L.b, F, &bb))) return rc;
+      steps = i + 1;
+      if (std::sqrt(bb) <= 1e-12 * std::sqrt(sums[6])) {
+        // equilibrium to rounding (e.g. a uniform stress): no step
+        s.pcg_iterations[k - 1][i] = 0;
+        s.du_ratio[k - 1][i] = 0.0;
+        conv = true;
+        break;
+      }
+      // reference material: mean of the current tangent (Alg. 1 assembles
+      // the preconditioner every step), or the mean elastic stiffness once
+      if (o.ref_mode == FH_NEWTON_REF_TANGENT || !elastic_ref_done) {
+        std::vector<double> Cr(36, 0.0);
+        if (o.ref_mode == FH_NEWTON_REF_TANGENT) {
+          const double Ks = sums[7] / vol, As = sums[8] / vol;
+          for (int a = 0; a < 6; ++a)
+            for (int b = 0; b < 6; ++b) {
+              const double one = (a < 3 && b < 3) ? 1.0 : 0.0;
+              Cr[a * 6 + b] = Ks * one + As * ((a == b ? 1.0 : 0.0) - one / 3.0);
+            }
+          int t = 9;
+          for (int a = 0; a < 6; ++a)
+            for (int b = a; b < 6; ++b, ++t) {
+              Cr[a * 6 + b] -= sums[t] / vol;
+              if (b != a) Cr[b * 6 + a] -= sums[t] / vol;
+            }
+          c->cref_in = Cr;
+          c->cref_user = true;
+        } else {
+          c->cref_user = false;  // the mean elastic stiffness (Sec. 6.2)
+          elastic_ref_done = true;
+        }
+        c->symbol_ok = false;
+        if ((rc = build_symbol(c))) return rc;
+      }
+      // PCG for K_(i) du = b with the per-point tangent
+      c->qp_tangent = true;
+      HIPCHK(c, fh::launch_copy(L.r, L.b, F, c->stream));
+      PcgBufs<double> bf{L.x, L.r, L.p, L.q, L.A, L.B, L.kplus};
+      std::vector<fh::PcgState> hs;
+      c->kt.on = false;
+      rc = pcg_run<double>(c, 1, bf, o.eta_cg, o.itmax_cg, 16, std::vector<int>(1, 1), hs);
+      c->qp_tangent = false;
+      if (rc) return rc;
+      s.pcg_iterations[k - 1][i] = hs[0].iter;
+      s.total_pcg += hs[0].iter;
+      const int pst = status_code(hs[0].status);
+      if (pst < 0) return fail(c, FH_ENOTSPD, "PCG breakdown in a Newton step");
+      if (pst > 0) result = FH_NOT_CONVERGED;
+      HIPCHK(c, fh::launch_axpy(c->pl_u, 1.0, L.x, F, c->stream));
+      double dd = 0.0, uu = 0.0;
+      if ((rc = field_dot(c, L.x, L.x, F, &dd)) || (rc = field_dot(c, c->pl_u, c->pl_u, F, &uu)))
+        return rc;
+      const double ndu = std::sqrt(dd), nu = std::sqrt(uu);
+      s.du_ratio[k - 1][i] = nu > 0.0 ? ndu / nu : 0.0;
+      if (ndu <= o.eta_newton * nu) {
+        conv = true;
+        break;
+      }
+    }
+    s.newton_steps[k - 1] = steps;
+    s.converged[k - 1] = conv ? 1 : 0;
+    if (!conv) result = FH_NOT_CONVERGED;
+    // commit the internal variables at the converged displacement
+    HIPCHK(c, fh::launch_plastic_stage(2, g, c->phase_dev, c->pl_params_dev, E, c->pl_u, nullptr,
+                                       c->pl_eps_p, c->pl_alpha, nullptr, nullptr, c->pl_part,
+                                       c->pl_nb, c->stream));
+    if ((rc = plastic_sums(c, sums))) return rc;
+    for (int m = 0; m < 6; ++m) s.macro_stress[k - 1][m] = sums[m] / vol;
+    s.plastic_fraction[k - 1] = sums[30] / (8.0 * (double)N);
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  s.solve_ms = ms_since(t0);
+  if (st) *st = s;
+  return result;
+}
+
+int fh_get_plastic_state(fh_ctx* c, double* u_dev, double* eps_p_dev, double* alpha_dev) {
+  if (!c) return FH_EINVAL;
+  hipSetDevice(c->device);
+  if (!c->plastic) return fail(c, FH_ESTATE, "fh_set_plastic_phases not called");
+  const long long N = c->g.N;
+  if (u_dev)
+    HIPCHK(c, hipMemcpyAsync(u_dev, c->pl_u, 3 * N * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
+  if (eps_p_dev)
+    HIPCHK(c, hipMemcpyAsync(eps_p_dev, c->pl_eps_p, 48 * N * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->stream));
+  if (alpha_dev)
+    HIPCHK(c, hipMemcpyAsync(alpha_dev, c->pl_alpha, 8 * N * sizeof(double),
+                             hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FH_OK;
+}
+
+}  // extern "C"
+
+// ============================ strain-based scheme with FE projection (Sec. 7.1)
+namespace {
+
+// Gamma0 tau = D Kref^+ D^T W tau with tau = C (x + E) (x may be null):
+// element forces, nodal sum (sign), FFT pseudo-inverse, gradient.
+int sb_green(fh_ctx* c, const double* x, const double* E, double sign, double* out) {
+  const fh::Grid& g = c->g;
+  const long long F = 3 * g.N;
+  HIPCHK(c, fh::launch_sb_cdiv(g, c->phase_dev, c->sb_C, x, E, c->sb_fe, c->stream));
+  HIPCHK(c, fh::launch_gather_nodes(g, c->sb_fe, sign, c->L.r, nullptr, nullptr,
+                                    fh::plastic_blocks(g, 2048), c->stream));
+  int rc = precond_fields(c, c->L.r, c->L.q, 1, F);
+  if (rc) return rc;
+  HIPCHK(c, fh::launch_sb_grad(g, c->L.q, out, c->stream));
+  return FH_OK;
+}
+
+int sb_dot(fh_ctx* c, const double* C, const double* Mc, const double* a, const double* Ea,
+           const double* b, const double* Eb, double* out) {
+  const fh::Grid& g = c->g;
+  const int nb = fh::sb_dot_partials(g);
+  HIPCHK(c, fh::launch_sb_dot(g, c->phase_dev, C, Mc, a, Ea, b, Eb, c->L.dot_part, c->stream));
+  HIPCHK(c, fh::launch_sum_partials(c->L.dot_part, nb, c->L.scal, c->stream));
+  HIPCHK(c, hipMemcpyAsync(out, c->L.scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fh_solve_strain_based(fh_ctx* c, const fh_opts* opt, fh_stats* st) {
+  if (!c) return FH_EINVAL;
+  hipSetDevice(c->device);
+  fh_opts o{1e-10, 10000, FH_FP64, 0, 0, 0.0};
+  if (opt) o = *opt;
+  if (!(o.eta > 0.0) || o.itmax < 1) return fail(c, FH_EINVAL, "bad eta/itmax");
+  if (o.precision != FH_FP64) return fail(c, FH_EINVAL, "the strain-based scheme runs in FP64");
+  if (!c->has_grid || !hex_elastic(c) || c->g.dim != 3)
+    return fail(c, FH_EINVAL, "the strain-based scheme needs 3D hex8 elasticity");
+  if (c->mat_kind != 1) return fail(c, FH_ESTATE, "fh_set_phases not called");
+  if (c->nload < 1) return fail(c, FH_ESTATE, "fh_set_load not called");
+  c->kt.on = false;
+  auto t0 = std::chrono::steady_clock::now();
+  int rc = build_symbol(c);
+  if (rc) return rc;
+  const double t_setup = ms_since(t0);
+  const fh::Grid& g = c->g;
+  const long long N = g.N, Q = 48 * N;
+  const int nl = c->nload;
+  if (c->sb_nload != nl) {
+    free_sb(c);
+    struct Buf { double** p; size_t n; };
+    const Buf bufs[] = {{&c->sb_eps, (size_t)nl * Q}, {&c->sb_r, (size_t)Q}, {&c->sb_p, (size_t)Q},
+                        {&c->sb_q, (size_t)Q}, {&c->sb_fe, 24 * (size_t)N},
+                        {&c->sb_C, 36 * (size_t)c->nphase}};
+    for (const Buf& b : bufs)
+      if (hipMalloc((void**)b.p, b.n * sizeof(double)) != hipSuccess) {
+        free_sb(c);
+        return fail(c, FH_ENOMEM, "hipMalloc of the strain-based fields failed");
+      }
+    c->sb_nload = nl;
+  }
+  HIPCHK(c, hipMemcpy(c->sb_C, c->mat.data(), 36 * (size_t)c->nphase * sizeof(double),
+                      hipMemcpyHostToDevice));
+  c->sb_solved = false;
+  c->solved = false;
+  const double* Cref = c->cref.data();
+  std::vector<fh::PcgState> hs(nl);
+  c->history.assign(nl, {});
+  t0 = std::chrono::steady_clock::now();
+  for (int j = 0; j < nl; ++j) {
+    const double* E = c->loads.data() + 6 * (size_t)j;
+    double* x = c->sb_eps + (size_t)j * Q;
+    fh::PcgState& s = hs[j];
+    s = fh::PcgState{};
+    HIPCHK(c, fh::launch_fill<double>(x, 0.0, Q, c->stream));
+    // r0 = -Gamma0 C e, p0 = r0
+    if ((rc = sb_green(c, nullptr, E, -1.0, c->sb_r))) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->sb_p, c->sb_r, Q * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
+    double rho = 0.0;
+    if ((rc = sb_dot(c, nullptr, Cref, c->sb_r, nullptr, c->sb_r, nullptr, &rho))) return rc;
+    s.rho0 = rho;
+    s.status = fh::ST_CONVERGED;
+    if (!(rho > 0.0)) continue;
+    s.status = fh::ST_MAXIT;
+    for (int k = 1; k <= o.itmax; ++k) {
+      if ((rc = sb_green(c, c->sb_p, nullptr, 1.0, c->sb_q))) return rc;
+      double pq = 0.0;
+      if ((rc = sb_dot(c, nullptr, Cref, c->sb_p, nullptr, c->sb_q, nullptr, &pq))) return rc;
+      if (!(pq > 0.0)) {
+        s.status = fh::ST_BREAKDOWN;
+        break;
+      }
+      const double alpha = rho / pq;
+      HIPCHK(c, fh::launch_axpy(x, alpha, c->sb_p, Q, c->stream));
+      HIPCHK(c, fh::launch_axpy(c->sb_r, -alpha, c->sb_q, Q, c->stream));
+      double rho_new = 0.0;
+      if ((rc = sb_dot(c, nullptr, Cref, c->sb_r, nullptr, c->sb_r, nullptr, &rho_new)))
+        return rc;
+      s.iter = k;
+      s.last = rho_new > 0.0 ? std::sqrt(rho_new / s.rho0) : 0.0;
+      c->history[j].push_back(s.last);
+      if (!(rho_new >= 0.0)) {
+        s.status = fh::ST_BREAKDOWN;
+        break;
+      }
+      if (rho_new <= o.eta * o.eta * s.rho0) {
+        s.status = fh::ST_CONVERGED;
+        break;
+      }
+      HIPCHK(c, fh::launch_sb_xpby(c->sb_p, c->sb_r, rho_new / rho, Q, c->stream));
+      rho = rho_new;
+    }
+  }
+  const double t_solve = ms_since(t0);
+  // C_hom[i][j] = (1/|Y|) sum_Q w (e_i + eps_i)^T C (e_j + eps_j)
+  t0 = std::chrono::steady_clock::now();
+  const double vol = c->l[0] * c->l[1] * c->l[2];
+  c->chom.assign((size_t)nl * nl, 0.0);
+  for (int i = 0; i < nl; ++i)
+    for (int j = i; j < nl; ++j) {
+      double v = 0.0;
+      if ((rc = sb_dot(c, c->sb_C, nullptr, c->sb_eps + (size_t)i * Q, c->loads.data() + 6 * i,
+                       c->sb_eps + (size_t)j * Q, c->loads.data() + 6 * j, &v)))
+        return rc;
+      c->chom[(size_t)i * nl + j] = c->chom[(size_t)j * nl + i] = v / vol;
+    }
+  c->sb_solved = true;
+  rc = fill_stats(c, hs, nl, nullptr);
+  c->last.setup_ms = t_setup;
+  c->last.solve_ms = t_solve;
+  c->last.chom_ms = ms_since(t0);
+  if (st) *st = c->last;
+  return rc;
+}
+
+int fh_get_strain(fh_ctx* c, int load, double* eps_dev) {
+  if (!c || !eps_dev) return FH_EINVAL;
+  hipSetDevice(c->device);
+  if (!c->sb_solved) return fail(c, FH_ESTATE, "fh_solve_strain_based not called");
+  if (load < 0 || load >= c->sb_nload) return fail(c, FH_EINVAL, "load index out of range");
+  const long long Q = 48 * c->g.N;
+  HIPCHK(c, hipMemcpyAsync(eps_dev, c->sb_eps + (size_t)load * Q, Q * sizeof(double),
+                           hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FH_OK;
 }
 
 }  // extern "C"

@@ -639,6 +639,17 @@ __global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan
         res[idx] = z0v;
         res[cls + idx] = z1v;
         res[2 * cls + idx] = z2v;
+      } else if (nd == 2 && g.tn) {
+        // two-node stencil: Hermitian block, K^+_01 = kr + i ki
+        const T k00 = kplus[f], k11 = kplus[nfreq + f];
+        const T kr = kplus[2 * nfreq + f], ki = kplus[3 * nfreq + f];
+        const cplx<T> r0 = res[idx], r1 = res[cls + idx];
+        cplx<T> z0v = {k00 * r0.re + kr * r1.re - ki * r1.im, k00 * r0.im + kr * r1.im + ki * r1.re};
+        cplx<T> z1v = {kr * r0.re + ki * r0.im + k11 * r1.re, kr * r0.im - ki * r0.re + k11 * r1.im};
+        part += wgt * ((double)r0.re * z0v.re + (double)r0.im * z0v.im +
+                       (double)r1.re * z1v.re + (double)r1.im * z1v.im);
+        res[idx] = z0v;
+        res[cls + idx] = z1v;
       } else if (nd == 2) {
         const T k00 = kplus[f], k11 = kplus[nfreq + f], k01 = kplus[2 * nfreq + f];
         const cplx<T> r0 = res[idx], r1 = res[cls + idx];

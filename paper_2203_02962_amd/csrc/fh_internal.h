@@ -59,6 +59,9 @@ struct Grid {
   // z-pass ky lines per block, FP32 x-pass rows per block (16 or 32) -- set
   // by the autotuner for batched solves
   int kz, zb, kyb, xrows;
+  // two-node stencil (N_n = 2): the nd = 2 fields are the corner and centre
+  // node sets, K^+ is a Hermitian block stored as {k00, k11, Re k01, Im k01}
+  int tn;
 };
 
 // FFT plan for one axis length: radix of stage i (applied first to last) in
@@ -138,6 +141,68 @@ hipError_t launch_xinv(const Grid& g, const AxisPlan& px, const cplx<double>* tw
 hipError_t launch_symbol(const Grid& g, const cplx<double>* spec, long long sstride,
                          double* kplus, int* bad_flag, hipStream_t s);
 hipError_t launch_cast_symbol(long long count, const double* src, float* dst, hipStream_t s);
+
+// Guaranteed eigenvalue bounds (Sec. 4.3): per node the min / max of the
+// per-voxel generalized eigenvalue pairs over the 2^dim voxels sharing the
+// node (tab: lo/hi per phase table, or the unit-conductivity pair scaled by
+// kfield).  lo/hi (N values each) may be null; range[0..1] = global min/max.
+// part holds 2 doubles per block (node_bounds_partials blocks).
+int node_bounds_partials(const Grid& g);
+hipError_t launch_node_bounds(const Grid& g, const uint8_t* phase, const double* kfield,
+                              const double* tab, double* lo, double* hi, double* part,
+                              double* range, hipStream_t s);
+
+// Elasto-plastic material stage (plastic.hip).  mode 0 = residual: stress
+// at e + D u from the committed state, tangent per point, element forces;
+// mode 1 = tangent operator on u (= p); mode 2 = commit the internal
+// variables at e + D u.  part (may be null): plastic_parts() doubles per
+// block (macro stress 6, sum fe^2, sum K, sum a, sum v v^T (21), plastic
+// points).  Launch with plastic_blocks(g, max) blocks.
+int plastic_parts();
+int plastic_blocks(const Grid& g, int max_blocks);
+hipError_t launch_plastic_stage(int mode, const Grid& g, const uint8_t* phase,
+                                const double* params, const double* E, const double* u,
+                                double* fe, double* eps_p, double* alpha, double* ta, double* tv,
+                                double* part, int nblocks, hipStream_t s);
+// out[c][I] = sign * sum of the 8 element forces at node I; part (may be
+// null): one partial per block of sum (dot ? dot : out) * out.
+hipError_t launch_gather_nodes(const Grid& g, const double* fe, double sign, double* out,
+                               const double* dot, double* part, int nblocks, hipStream_t s);
+
+// Two-node stencil (tn.hip), 2D scalar: operator from per-phase 5 x 5
+// element matrices (or a unit matrix scaled by kfield); right-hand side from
+// per-phase x load element forces (5 each); Hermitian K^+ / N from the
+// impulse-response spectra (part: 1024 doubles of scratch).
+template <typename T>
+hipError_t launch_kop_tn(const Grid& g, const T* u, T* q, const uint8_t* phase, const T* kfield,
+                         const T* ke, int nload, long long ustride, long long qstride,
+                         const PcgState* st, double* pq_part, int* nblocks_out, hipStream_t s);
+hipError_t launch_rhs_tn(const Grid& g, const uint8_t* phase, const double* kfield,
+                         const double* fe, int nload, double* b, long long bstride,
+                         hipStream_t s);
+hipError_t launch_symbol_tn(const Grid& g, const cplx<double>* spec, long long sstride,
+                            double* kplus, int* bad_flag, double* part, hipStream_t s);
+
+// Strain-based scheme (sb.hip), 3D hex8, quadrature-point fields [6][8][N].
+// A 6x6 matrix (m, row-major) and a 6-vector (v) passed by value.
+struct Mat6 {
+  double m[36];
+  double v[6];
+};
+// fe = element forces of tau = C_phase (x + E) (x may be null; E 6 values or
+// null); C = nphase x 36 Mandel tables.
+hipError_t launch_sb_cdiv(const Grid& g, const uint8_t* phase, const double* C, const double* x,
+                          const double* E, double* fe, hipStream_t s);
+// out = D z at the Gauss points
+hipError_t launch_sb_grad(const Grid& g, const double* z, double* out, hipStream_t s);
+// part[sb_dot_partials(g)] = per-block sums of w (a + Ea)^T M (b + Eb),
+// M = Mc (36 values) or the voxel's C when C is not null
+int sb_dot_partials(const Grid& g);
+hipError_t launch_sb_dot(const Grid& g, const uint8_t* phase, const double* C, const double* Mc,
+                         const double* a, const double* Ea, const double* b, const double* Eb,
+                         double* part, hipStream_t s);
+// p = r + beta p
+hipError_t launch_sb_xpby(double* p, const double* r, double beta, long long n, hipStream_t s);
 
 // Number of per-load partial sums the operator and z-pass launches write.
 // (tbytes = sizeof of the field type: the default z chunk depends on it)

@@ -912,6 +912,7 @@ hipError_t launch_rhs(const Grid& g, int elem, const uint8_t* phase, const doubl
                       long long bstride, hipStream_t s) {
   (void)nphase_tables;
   (void)elem;
+  if (g.tn) return launch_rhs_tn(g, phase, kfield, fe, nload, b, bstride, s);
   const int nc = g.dim == 3 ? 8 : 4;
   long long blocks = (g.N + 255) / 256;
   if (blocks > 8192) blocks = 8192;

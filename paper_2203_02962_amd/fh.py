@@ -19,17 +19,20 @@ LIB_PATH = os.path.join(_HERE, "libfh.so")
 FH_OK, FH_NOT_CONVERGED = 0, 1
 FH_EINVAL, FH_ENOMEM, FH_EDEVICE, FH_ENOTSPD, FH_ESTATE = -1, -2, -3, -4, -5
 FH_SCALAR, FH_ELASTIC = 0, 1
-FH_HEX8, FH_QUAD4, FH_TRI2 = 0, 1, 2
+FH_HEX8, FH_QUAD4, FH_TRI2, FH_TRI4 = 0, 1, 2, 3
 FH_FP64, FH_FP32_REFINED = 0, 1
 FH_MAX_LOADS = 32
 FH_FLAG_TIME_KERNELS = 1
 FH_FLAG_REBUILD = 2
 FH_FLAG_WARM_START = 4
 FH_FLAG_TIME_SAMPLED = 8
+FH_REF_MEAN, FH_REF_IDENTITY, FH_REF_BEST = 0, 1, 2
+FH_MAX_INCREMENTS, FH_MAX_NEWTON = 64, 64
+FH_NEWTON_REF_TANGENT, FH_NEWTON_REF_ELASTIC = 0, 1
 NET_CLASSES = ["conv", "dgrad", "wgrad", "other"]
 KERNEL_CLASSES = ["operator", "xfwd", "yfwd", "zsolve", "yinv", "xinv", "scalar", "other"]
 
-ELEMENTS = {"hex8": FH_HEX8, "quad4": FH_QUAD4, "tri2": FH_TRI2}
+ELEMENTS = {"hex8": FH_HEX8, "quad4": FH_QUAD4, "tri2": FH_TRI2, "tri4": FH_TRI4}
 PROBLEMS = {"scalar": FH_SCALAR, "elastic": FH_ELASTIC}
 
 EXPORTED = [
@@ -39,7 +42,9 @@ EXPORTED = [
     "fh_get_homogenized", "fh_get_reference", "fh_get_history", "fh_apply_operator",
     "fh_apply_preconditioner", "fh_compute_rhs", "fh_compute_rhs_noalloc", "fh_get_symbol",
     "fh_solve_rhs",
-    "fh_solve_batch", "fh_set_warm_start",
+    "fh_solve_batch", "fh_set_warm_start", "fh_eigen_bounds", "fh_choose_reference",
+    "fh_set_plastic_phases", "fh_newton_solve", "fh_get_plastic_state",
+    "fh_solve_strain_based", "fh_get_strain",
     "fh_net_param_count", "fh_net_create", "fh_net_destroy", "fh_net_last_error",
     "fh_net_set_stream", "fh_net_set_params", "fh_net_get_params", "fh_net_forward",
     "fh_net_gradient", "fh_net_adam", "fh_net_train", "fh_net_pack_target",
@@ -65,7 +70,8 @@ class fh_stats(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double * 8), ("kernel_launches", ctypes.c_longlong * 8),
                 ("guess_used", ctypes.c_int * FH_MAX_LOADS),
                 ("guess_res", ctypes.c_double * FH_MAX_LOADS), ("guess_ms", ctypes.c_double),
-                ("kernel_issued", ctypes.c_longlong * 8)]
+                ("kernel_issued", ctypes.c_longlong * 8),
+                ("kernel_units", ctypes.c_double * 8)]
 
     def as_dict(self):
         n = self.nload
@@ -75,6 +81,7 @@ class fh_stats(ctypes.Structure):
                     dof=self.dof, kernel_ms=list(self.kernel_ms),
                     kernel_launches=list(self.kernel_launches),
                     kernel_issued=list(self.kernel_issued),
+                    kernel_units=list(self.kernel_units),
                     guess_used=list(self.guess_used[:n]), guess_res=list(self.guess_res[:n]),
                     guess_ms=self.guess_ms)
 
@@ -99,6 +106,43 @@ class fh_net_stats(ctypes.Structure):
         return {k: dict(ms=self.kernel_ms[i], launches=self.kernel_launches[i],
                         flops=self.flops[i]) for i, k in enumerate(NET_CLASSES)} | \
             dict(adam_steps=self.adam_steps)
+
+
+class fh_bounds(ctypes.Structure):
+    _fields_ = [("lambda_min", ctypes.c_double), ("lambda_max", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("predicted_iterations", ctypes.c_int),
+                ("pad", ctypes.c_int)]
+
+    def as_dict(self):
+        return dict(lambda_min=self.lambda_min, lambda_max=self.lambda_max, kappa=self.kappa,
+                    predicted_iterations=self.predicted_iterations)
+
+
+class fh_newton_opts(ctypes.Structure):
+    _fields_ = [("eta_newton", ctypes.c_double), ("eta_cg", ctypes.c_double),
+                ("itmax_newton", ctypes.c_int), ("itmax_cg", ctypes.c_int),
+                ("nincrement", ctypes.c_int), ("ref_mode", ctypes.c_int)]
+
+
+class fh_newton_stats(ctypes.Structure):
+    _fields_ = [("nincrement", ctypes.c_int),
+                ("newton_steps", ctypes.c_int * FH_MAX_INCREMENTS),
+                ("converged", ctypes.c_int * FH_MAX_INCREMENTS),
+                ("pcg_iterations", (ctypes.c_int * FH_MAX_NEWTON) * FH_MAX_INCREMENTS),
+                ("du_ratio", (ctypes.c_double * FH_MAX_NEWTON) * FH_MAX_INCREMENTS),
+                ("macro_stress", (ctypes.c_double * 6) * FH_MAX_INCREMENTS),
+                ("plastic_fraction", ctypes.c_double * FH_MAX_INCREMENTS),
+                ("total_pcg", ctypes.c_int), ("solve_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        k = self.nincrement
+        steps = list(self.newton_steps[:k])
+        return dict(nincrement=k, newton_steps=steps, converged=list(self.converged[:k]),
+                    pcg_iterations=[list(self.pcg_iterations[i][:steps[i]]) for i in range(k)],
+                    du_ratio=[list(self.du_ratio[i][:steps[i]]) for i in range(k)],
+                    macro_stress=[list(self.macro_stress[i]) for i in range(k)],
+                    plastic_fraction=list(self.plastic_fraction[:k]),
+                    total_pcg=self.total_pcg, solve_ms=self.solve_ms)
 
 
 FH_MAX_GROUPS = 16
@@ -167,6 +211,14 @@ def load_library(path: str = LIB_PATH):
                             ctypes.POINTER(fh_opts), ctypes.POINTER(D), ctypes.POINTER(fh_stats),
                             ctypes.POINTER(fh_batch_report)], I),
         "fh_set_warm_start": ([P, P], I),
+        "fh_eigen_bounds": ([P, ctypes.POINTER(D), D, P, P, ctypes.POINTER(fh_bounds)], I),
+        "fh_set_plastic_phases": ([P, P, I, ctypes.POINTER(D)], I),
+        "fh_newton_solve": ([P, ctypes.POINTER(D), ctypes.POINTER(fh_newton_opts),
+                             ctypes.POINTER(fh_newton_stats)], I),
+        "fh_get_plastic_state": ([P, P, P, P], I),
+        "fh_solve_strain_based": ([P, ctypes.POINTER(fh_opts), ctypes.POINTER(fh_stats)], I),
+        "fh_get_strain": ([P, I, P], I),
+        "fh_choose_reference": ([P, I, ctypes.POINTER(D), ctypes.POINTER(fh_bounds)], I),
         "fh_net_param_count": ([], ctypes.c_longlong),
         "fh_net_create": ([ctypes.POINTER(P), I, I, I], I),
         "fh_net_destroy": ([P], None),
@@ -282,7 +334,10 @@ class Context:
         dim = 3 if element == "hex8" else 2
         narr = (ctypes.c_int * 3)(*[int(v) for v in n])
         larr = None if l is None else (ctypes.c_double * 3)(*(list(l) + [1.0] * (3 - len(l))))
-        self.nd = (dim if problem == "elastic" else 1)
+        # fields per grid point: node sets x components (two node sets for
+        # the two-node stencil)
+        self.nd = (dim if problem == "elastic" else 1) * (2 if element == "tri4" else 1)
+        self.element = element
         self.N = int(np.prod(n[:dim]))
         self.n = tuple(n[:dim])
         self.dim = dim
@@ -375,6 +430,71 @@ class Context:
                                             ctypes.byref(cnt)))
         return h[:cnt.value]
 
+    # ------------------------------------------------ strain-based scheme
+    def solve_strain_based(self, eta=1e-10, itmax=10000):
+        o = self.opts(eta, itmax, FH_FP64)
+        st = fh_stats()
+        rc = self._check(self.lib.fh_solve_strain_based(self.ptr, ctypes.byref(o),
+                                                        ctypes.byref(st)), allow_warning=True)
+        return rc, st.as_dict()
+
+    def get_strain(self, load, eps_dev):
+        ptr = _tptr(eps_dev, _f64(), 48 * self.N, self.device)
+        return self._check(self.lib.fh_get_strain(self.ptr, int(load), ptr))
+
+    # ------------------------------------------------ elasto-plastic Newton
+    def set_plastic_phases(self, phase_dev, params):
+        """params: (nphase, 4) = K, G, sy0, H per phase (fh_set_plastic_phases)."""
+        import torch
+        params = np.ascontiguousarray(params, dtype=np.float64)
+        assert params.ndim == 2 and params.shape[1] == 4
+        ptr = _tptr(phase_dev, torch.uint8, self.N, self.device)
+        self._keep = [phase_dev]
+        return self._check(self.lib.fh_set_plastic_phases(self.ptr, ptr, params.shape[0],
+                                                          _dptr(params)))
+
+    def newton_solve(self, E_final, nincrement=1, eta_newton=1e-8, eta_cg=1e-10,
+                     itmax_newton=50, itmax_cg=10000, ref_mode=FH_NEWTON_REF_TANGENT):
+        E = np.ascontiguousarray(E_final, dtype=np.float64)
+        assert E.size == 6
+        o = fh_newton_opts(eta_newton, eta_cg, itmax_newton, itmax_cg, nincrement, ref_mode)
+        st = fh_newton_stats()
+        rc = self._check(self.lib.fh_newton_solve(self.ptr, _dptr(E), ctypes.byref(o),
+                                                  ctypes.byref(st)), allow_warning=True)
+        return rc, st.as_dict()
+
+    def get_plastic_state(self, u_dev=None, eps_p_dev=None, alpha_dev=None):
+        N = self.N
+        u = None if u_dev is None else _tptr(u_dev, _f64(), 3 * N, self.device)
+        e = None if eps_p_dev is None else _tptr(eps_p_dev, _f64(), 48 * N, self.device)
+        a = None if alpha_dev is None else _tptr(alpha_dev, _f64(), 8 * N, self.device)
+        return self._check(self.lib.fh_get_plastic_state(self.ptr, u, e, a))
+
+    # ---------------------------------------------------- eigenvalue bounds
+    def eigen_bounds(self, Cref=None, eta=1e-6, lo_dev=None, hi_dev=None):
+        """Guaranteed eigenvalue bounds (fh_eigen_bounds): dict with
+        lambda_min, lambda_max, kappa and the predicted PCG iterations for
+        eta; lo_dev / hi_dev (float64 tensors of N values, optional) receive
+        the nodal bounds."""
+        C = None if Cref is None else np.ascontiguousarray(Cref, dtype=np.float64)
+        if C is not None:
+            assert C.shape == (self.m, self.m)
+        lo = None if lo_dev is None else _tptr(lo_dev, _f64(), self.N, self.device)
+        hi = None if hi_dev is None else _tptr(hi_dev, _f64(), self.N, self.device)
+        b = fh_bounds()
+        self._check(self.lib.fh_eigen_bounds(self.ptr, None if C is None else _dptr(C),
+                                             float(eta), lo, hi, ctypes.byref(b)))
+        return b.as_dict()
+
+    def choose_reference(self, strategy=FH_REF_BEST):
+        """fh_choose_reference: returns (Cref, bounds dict); the choice
+        becomes the context's reference."""
+        C = np.zeros((self.m, self.m))
+        b = fh_bounds()
+        self._check(self.lib.fh_choose_reference(self.ptr, int(strategy), _dptr_out(C),
+                                                 ctypes.byref(b)))
+        return C, b.as_dict()
+
     # ----------------------------------------------------------- step hooks
     def _field(self, t):
         return _tptr(t, _f64(), self.nd * self.N, self.device)
@@ -401,9 +521,10 @@ class Context:
 
     def symbol_size(self):
         """Doubles written by get_symbol: nd(nd+1)/2 entries per frequency of
-        the half spectrum."""
+        the half spectrum (4 for the two-node stencil's Hermitian block)."""
         n = list(self.n) + [1] * (3 - len(self.n))
-        return self.nd * (self.nd + 1) // 2 * (n[0] // 2 + 1) * n[1] * n[2]
+        nsym = 4 if self.element == "tri4" else self.nd * (self.nd + 1) // 2
+        return nsym * (n[0] // 2 + 1) * n[1] * n[2]
 
     def get_symbol(self, kplus_dev):
         ptr = _tptr(kplus_dev, _f64(), self.symbol_size(), self.device)

@@ -1,0 +1,164 @@
+"""GPU parity of the elasto-plastic Newton-PCG loop (Alg. 1 with the
+small-strain J2 material) through the C-ABI, against oracle/plasticity.py
+(pinned in tests/test_oracle_plasticity.py).
+
+Tolerances: both sides take the same Newton and PCG decisions, so Newton
+steps per increment are equal and PCG iterations per step agree to
++-max(1, 1 %) (the two sides sum in different orders); the final
+displacement agrees to 1e-8 relative in l2 (eta_cg = 1e-10 per step,
+eta_newton = 1e-9), the macroscopic stress of every increment to 1e-9 of its
+largest component, the equivalent plastic strain to 1e-8 of its maximum, and
+the set of yielding points exactly.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import plasticity as op
+from synth import spheres
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fh():
+    from paper_2203_02962_amd import fh as fhmod
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    fhmod.load_library()
+    return fhmod
+
+
+def _params(E, nu, sy0, H):
+    return np.array([E / (3.0 * (1.0 - 2.0 * nu)), E / (2.0 * (1.0 + nu)), sy0, H])
+
+
+def _problem(n, seed, contrast):
+    phase, _, _ = spheres(n, (1.5, 2.5), 0.3, seed=seed)
+    phase = phase.astype(np.uint8)
+    # Sec. 6.3 phases: the hard phase has twice the initial yield stress and
+    # hardening modulus of the soft one (sy0 = 0.0015 E, H = 0.005 E)
+    params = np.stack([_params(1.0, 0.3, 0.0015, 0.005),
+                       _params(contrast, 0.3, 0.003, 0.01)])
+    return phase, params
+
+
+def _gpu(fh, n, phase, params, E, nincr, ref, eta_nw=1e-9, eta_cg=1e-10):
+    ctx = fh.Context(0)
+    ctx.set_grid((n, n, n), "elastic", "hex8")
+    ph = torch.from_numpy(phase).cuda()
+    ctx.set_plastic_phases(ph, params)
+    rc, st = ctx.newton_solve(E, nincrement=nincr, eta_newton=eta_nw, eta_cg=eta_cg,
+                              ref_mode=ref)
+    N = n ** 3
+    u = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+    ep = torch.empty(48 * N, dtype=torch.float64, device="cuda")
+    al = torch.empty(8 * N, dtype=torch.float64, device="cuda")
+    ctx.get_plastic_state(u, ep, al)
+    out = (rc, st, u.cpu().numpy(), ep.cpu().numpy().reshape(6, 8, N),
+           al.cpu().numpy().reshape(8, N))
+    ctx.close()
+    return out
+
+
+def _compare(st, u, ep, al, uo, epo, alo, res):
+    for k, r in enumerate(res):
+        assert st["newton_steps"][k] == r.newton_steps, (k, st["newton_steps"], r.newton_steps)
+        assert st["converged"][k] == int(r.converged)
+        for a, b in zip(st["pcg_iterations"][k], r.pcg_iterations):
+            assert abs(a - b) <= max(1, 0.01 * b), (k, st["pcg_iterations"][k], r.pcg_iterations)
+        ms = np.array(st["macro_stress"][k])
+        assert np.abs(ms - r.macro_stress).max() <= 1e-9 * np.abs(r.macro_stress).max()
+        assert abs(st["plastic_fraction"][k] - r.plastic_fraction) <= 1e-12
+    assert np.linalg.norm(u - uo) <= 1e-8 * max(np.linalg.norm(uo), 1e-300)
+    alo_t = alo.T                    # oracle (N, 8) -> (8, N)
+    if alo.max() > 0:
+        assert np.abs(al - alo_t).max() <= 1e-8 * alo.max()
+    assert np.array_equal(al > 0, alo_t > 0)
+    epo_t = np.transpose(epo, (2, 1, 0))  # (N, 8, 6) -> (6, 8, N)
+    if np.abs(epo).max() > 0:
+        assert np.abs(ep - epo_t).max() <= 1e-8 * np.abs(epo).max()
+
+
+@pytest.mark.parametrize("ref", ["tangent", "elastic"])
+def test_newton_matches_oracle(fh, ref):
+    n = 12
+    phase, params = _problem(n, 3, 3.0)
+    E = np.array([0.006, -0.006, 0.0, 0.002, 0.0, 0.0])
+    nincr = 3 if ref == "tangent" else 2
+    say("newton", ref, n, nincr)
+    refc = fh.FH_NEWTON_REF_TANGENT if ref == "tangent" else fh.FH_NEWTON_REF_ELASTIC
+    rc, st, u, ep, al = _gpu(fh, n, phase, params, E, nincr, refc)
+    assert rc == 0, st
+    pp = op.PlasticProblem((n,) * 3, phase, params)
+    uo, epo, alo, res = op.newton_solve(pp, E, nincr, eta_nw=1e-9, eta_cg=1e-10, ref=ref)
+    say("gpu steps", st["newton_steps"], st["pcg_iterations"])
+    say("oracle steps", [r.newton_steps for r in res], [r.pcg_iterations for r in res])
+    assert max(st["plastic_fraction"]) > 0.1
+    _compare(st, u, ep, al, uo, epo, alo, res)
+
+
+def test_newton_with_equal_elastic_phases(fh):
+    """Sec. 6.3 setting: both phases share the elastic constants, so while
+    nothing yields the stress is uniform, the residual is rounding noise and
+    the increment ends without a PCG solve; later increments yield."""
+    n = 12
+    phase, params = _problem(n, 5, 1.0)
+    E = np.array([0.004, -0.004, 0.0, 0.0, 0.0, 0.0])
+    rc, st, u, ep, al = _gpu(fh, n, phase, params, E, 4, fh.FH_NEWTON_REF_TANGENT)
+    assert rc == 0
+    pp = op.PlasticProblem((n,) * 3, phase, params)
+    uo, epo, alo, res = op.newton_solve(pp, E, 4, eta_nw=1e-9, eta_cg=1e-10)
+    say("steps", st["newton_steps"], st["pcg_iterations"], st["plastic_fraction"])
+    assert st["pcg_iterations"][0] == [0] and st["plastic_fraction"][0] == 0.0
+    assert st["plastic_fraction"][-1] > 0.0
+    _compare(st, u, ep, al, uo, epo, alo, res)
+
+
+def test_newton_residual_at_48(fh):
+    """48^3, one increment from the virgin state: the GPU's converged
+    displacement satisfies the oracle's nodal equilibrium to the Newton
+    tolerance (residual against the size of the element forces it sums)."""
+    n = 48
+    phase, params = _problem(n, 7, 3.0)
+    E = np.array([0.005, -0.005, 0.0, 0.0, 0.0, 0.0])
+    rc, st, u, ep, al = _gpu(fh, n, phase, params, E, 1, fh.FH_NEWTON_REF_TANGENT,
+                             eta_nw=1e-9, eta_cg=1e-10)
+    assert rc == 0
+    say("48^3 steps", st["newton_steps"], st["pcg_iterations"], st["solve_ms"])
+    pp = op.PlasticProblem((n,) * 3, phase, params)
+    eps = op.strain_at_qp(pp, u, E)
+    Kq, Gq, syq, Hq = pp.qp_params()
+    sig, _, _, alpha, _ = op.return_mapping(eps, np.zeros(eps.shape), np.zeros(eps.shape[:2]),
+                                            Kq, Gq, syq, Hq)
+    f, fscale = op.internal_force(pp, sig, with_scale=True)
+    assert np.linalg.norm(f) <= 1e-7 * fscale
+    assert np.abs(al - alpha.T).max() <= 1e-12 + 1e-9 * alpha.max()
+
+
+def test_newton_input_errors(fh):
+    ctx = fh.Context(0)
+    ctx.set_grid((8, 8, 8), "elastic", "hex8")
+    with pytest.raises(fh.FHError):
+        ctx.newton_solve(np.zeros(6))                      # no plastic phases
+    ph = torch.zeros(512, dtype=torch.uint8, device="cuda")
+    with pytest.raises(fh.FHError):
+        ctx.set_plastic_phases(ph, np.array([[1.0, 1.0, 0.001, 0.0]]))   # H = 0
+    ctx.set_plastic_phases(ph, _params(1.0, 0.3, 0.001, 0.01)[None])
+    with pytest.raises(fh.FHError):
+        ctx.newton_solve(np.zeros(6), nincrement=0)
+    rc, st = ctx.newton_solve(np.array([0.003, 0, 0, 0, 0, 0]), nincrement=2)
+    assert rc == 0 and st["total_pcg"] == 0                # homogeneous: no solve
+    ctx.close()
+    ctx = fh.Context(0)
+    ctx.set_grid((8, 8), "elastic", "quad4")
+    ph2 = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(fh.FHError):
+        ctx.set_plastic_phases(ph2, _params(1.0, 0.3, 0.001, 0.01)[None])
+    ctx.close()

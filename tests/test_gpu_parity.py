@@ -296,10 +296,19 @@ def test_kernel_timing_counts(fh):
     assert n_op >= max(st1["iterations"])
     # sampled: same launches issued, about an eighth of them timed
     assert st2["kernel_issued"] == st1["kernel_issued"]
-    assert st2["kernel_launches"][0] == (n_op + 7) // 8
+    assert st2["kernel_launches"][0] == (n_op + 3) // 8   # loop iterations 4, 12, ...
     for k in range(7):
         if st2["kernel_launches"][k]:
             assert st2["kernel_ms"][k] > 0.0
+    # load cases advanced by the timed launches: load j takes part in loop
+    # iterations 0 .. iterations[j] - 1 of every pass
+    its = st1["iterations"]
+    for k in (0, 1, 2, 3, 4, 5):
+        assert st1["kernel_units"][k] == sum(its)
+        assert st2["kernel_units"][k] == sum((i + 3) // 8 for i in its)
+    # the adaptive status poll stops within a few iterations of the last
+    # load's convergence
+    assert max(its) <= n_op <= max(its) + 3
 
 
 def test_input_validation(fh):
