@@ -139,6 +139,7 @@ def batch_comparison(count: int):
     inner = sum(sum(s["iterations"]) for s in sts)
     dof_iters = sum(s["dof"] * sum(s["iterations"]) for s in sts)
     t_plain = 0.0
+    t_refined_seq = 0.0
     diffs = []
     plain_iters = 0
     for w, Hi in zip(wls, Hb):
@@ -151,13 +152,21 @@ def batch_comparison(count: int):
         plain_iters += sum(st1["iterations"])
         Hp = c1.get_homogenized()
         diffs.append(float(np.abs(Hi - Hp).max() / np.abs(Hp).max()))
+        # the same FP32-refined solve, system by system: batching's own share
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        c1.solve(eta=1e-6, precision=fh.FH_FP32_REFINED, rebuild=True)
+        torch.cuda.synchronize()
+        t_refined_seq += (time.perf_counter() - ta) * 1000.0
         c1.close()
     return {
         "systems": count, "solves": 6 * count,
         "voxels_total": int(sum(np.prod(w["n"]) for w in wls)),
         "batched_fp32_refined_ms": round(t_batch, 1),
         "plain_fp64_sequential_ms": round(t_plain, 1),
+        "fp32_refined_sequential_ms": round(t_refined_seq, 1),
         "speedup": round(t_plain / t_batch, 3),
+        "batching_speedup_same_precision": round(t_refined_seq / t_batch, 3),
         "batched_inner_iterations_total": int(inner),
         "plain_iterations_total": int(plain_iters),
         "batched_dof_iter_per_s": dof_iters / (t_batch / 1000.0),
@@ -336,6 +345,8 @@ def main():
     ap.add_argument("--warm-steps", type=int, default=4000)
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run a plain 512 MiB device copy (counter calibration)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched comparison (for a kernel trace of it)")
     ap.add_argument("--timed-only", action="store_true",
                     help="run only the warm-up and timed steps (no 1e-6 or refined legs), so "
                          "that a kernel trace of the run holds the timed launches alone")
@@ -354,6 +365,10 @@ def main():
 
     wl = workload("elastic3d_spheres", seed=0, n=args.n)
     torch.cuda.set_device(0)
+    if args.batch_only:
+        print(json.dumps({"batched_vs_plain_1e-6": batch_comparison(args.batch_count)}),
+              flush=True)
+        return
     if args.probe_copy:
         a = torch.ones(64 * 2 ** 20, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)

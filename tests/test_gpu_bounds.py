@@ -146,9 +146,10 @@ def test_reference_choice(fh):
     ctx = _ctx(wl)
     rc, st_mean = ctx.solve(eta=1e-10)
     H_mean = ctx.get_homogenized()
-    kap = {}
+    kap, chosen = {}, {}
     for strat in (fh.FH_REF_MEAN, fh.FH_REF_IDENTITY, fh.FH_REF_BEST):
         C, b = ctx.choose_reference(strat)
+        chosen[strat] = C
         k_o = ob.kappa_bound(*ob.node_bounds(prob, C))
         assert abs(b["kappa"] - k_o) <= 1e-12 * k_o
         kap[strat] = k_o
@@ -161,10 +162,12 @@ def test_reference_choice(fh):
     assert kap[fh.FH_REF_BEST] < 0.9 * kap[fh.FH_REF_MEAN]
     rc, st_best = ctx.solve(eta=1e-10)
     assert rc == 0
-    C_used = ctx.get_reference()
-    C_best, _ = ctx.choose_reference(fh.FH_REF_BEST)
-    assert np.array_equal(C_used, C_best)
+    assert np.array_equal(ctx.get_reference(), chosen[fh.FH_REF_BEST])
     assert _rel(ctx.get_homogenized(), H_mean) <= 1e-9
+    # a new reference makes the previous solution stale
+    ctx.choose_reference(fh.FH_REF_MEAN)
+    with pytest.raises(fh.FHError):
+        ctx.get_homogenized()
     say("iterations mean", st_mean["iterations"], "best", st_best["iterations"])
     ctx.close()
 
