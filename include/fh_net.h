@@ -134,6 +134,27 @@ int fh_net_pack_target(fh_net *net, const double *u_dev, double scale, uint16_t 
 
 /* Kernel timing with HIP events on the network's stream (on != 0 resets
  * the counters), and the accumulated figures. */
+/* One layer of the network on caller-given tensors: a test hook for the
+ * MFMA kernels, with the network's current parameters (weights and biases
+ * rounded to BF16 as in every forward pass).  layer 0..13 in the parameter
+ * order; s = n >> level of the layer; cinp = cin rounded up to 16; tensors
+ * are BF16 (uint16 bit patterns) channels last [batch][s^3][channels].
+ *   FH_NET_OP_FORWARD: out = BF16(leaky(conv(x) + b)), x with cinp
+ *     channels (padding channels zero), out with cout channels;
+ *   FH_NET_OP_DGRAD: out = BF16(conv_input_grad(dz) (x leaky'(mask) when
+ *     mask is not NULL)), dz with cout channels, out and mask with cinp
+ *     channels; the first layer has none (FH_EINVAL);
+ *   FH_NET_OP_WGRAD: out = float[27 cout cin + cout], the gradient of the
+ *     layer's weights [tap][cout][cin] and bias from x and dz (it also
+ *     overwrites that layer's slice of the gradient of the last
+ *     fh_net_gradient call).
+ * batch <= max_batch.  Synchronises the network's stream.                 */
+#define FH_NET_OP_FORWARD 0
+#define FH_NET_OP_DGRAD 1
+#define FH_NET_OP_WGRAD 2
+int fh_net_layer(fh_net *net, int layer, int op, int batch, const uint16_t *x_dev,
+                 const uint16_t *dz_dev, const uint16_t *mask_dev, void *out_dev);
+
 int fh_net_set_timing(fh_net *net, int on);
 int fh_net_get_stats(fh_net *net, fh_net_stats *stats);
 

@@ -1251,6 +1251,43 @@ int fh_net_pack_target(fh_net* N, const double* u_dev, double scale, uint16_t* t
   return FH_OK;
 }
 
+int fh_net_layer(fh_net* N, int layer, int op, int batch, const uint16_t* x_dev,
+                 const uint16_t* dz_dev, const uint16_t* mask_dev, void* out_dev) {
+  if (!N || !out_dev) return FH_EINVAL;
+  hipSetDevice(N->device);
+  if (layer < 0 || layer >= kLayers) return nfail(N, FH_EINVAL, "layer index out of range");
+  int rc = check_batch(N, batch);
+  if (rc) return rc;
+  if (!N->packed && (rc = pack_all(N))) return rc;
+  const int l = layer, s = N->s[kL[l].level];
+  if (op == FH_NET_OP_FORWARD) {
+    if (!x_dev) return nfail(N, FH_EINVAL, "forward needs x");
+    rc = conv(N, x_dev, cinp(l), N->wf[l], N->bias[l], nullptr, (uint16_t*)out_dev, kL[l].cout,
+              s, batch, true, FH_NET_K_CONV, conv_flops(N, l, batch));
+  } else if (op == FH_NET_OP_DGRAD) {
+    if (!dz_dev) return nfail(N, FH_EINVAL, "input gradient needs dz");
+    if (!N->wd[l]) return nfail(N, FH_EINVAL, "the first layer has no input gradient");
+    rc = conv(N, dz_dev, kL[l].cout, N->wd[l], nullptr, mask_dev, (uint16_t*)out_dev, cinp(l), s,
+              batch, false, FH_NET_K_DGRAD, conv_flops(N, l, batch));
+  } else if (op == FH_NET_OP_WGRAD) {
+    if (!x_dev || !dz_dev) return nfail(N, FH_EINVAL, "weight gradient needs x and dz");
+    rc = wgrad(N, l, x_dev, dz_dev, batch);
+    if (!rc) {
+      const long long nw = 27LL * kL[l].cin * kL[l].cout;
+      float* o = (float*)out_dev;
+      NCHK(N, hipMemcpyAsync(o, N->gr + N->offw[l], nw * sizeof(float), hipMemcpyDeviceToDevice,
+                             N->stream));
+      NCHK(N, hipMemcpyAsync(o + nw, N->gr + N->offb[l], kL[l].cout * sizeof(float),
+                             hipMemcpyDeviceToDevice, N->stream));
+    }
+  } else {
+    return nfail(N, FH_EINVAL, "unknown layer operation");
+  }
+  if (rc) return rc;
+  NCHK(N, hipStreamSynchronize(N->stream));
+  return FH_OK;
+}
+
 int fh_net_set_timing(fh_net* N, int on) {
   if (!N) return FH_EINVAL;
   N->time_on = on != 0;

@@ -26,6 +26,7 @@ FH_FLAG_TIME_KERNELS = 1
 FH_FLAG_REBUILD = 2
 FH_FLAG_WARM_START = 4
 FH_FLAG_TIME_SAMPLED = 8
+FH_FLAG_BATCH_SERIAL = 16
 FH_REF_MEAN, FH_REF_IDENTITY, FH_REF_BEST = 0, 1, 2
 FH_MAX_INCREMENTS, FH_MAX_NEWTON = 64, 64
 FH_NEWTON_REF_TANGENT, FH_NEWTON_REF_ELASTIC = 0, 1
@@ -48,7 +49,7 @@ EXPORTED = [
     "fh_net_param_count", "fh_net_create", "fh_net_destroy", "fh_net_last_error",
     "fh_net_set_stream", "fh_net_set_params", "fh_net_get_params", "fh_net_forward",
     "fh_net_gradient", "fh_net_adam", "fh_net_train", "fh_net_pack_target",
-    "fh_net_set_timing", "fh_net_get_stats", "fh_net_guess",
+    "fh_net_set_timing", "fh_net_get_stats", "fh_net_guess", "fh_net_layer",
 ]
 
 
@@ -236,6 +237,7 @@ def load_library(path: str = LIB_PATH):
         "fh_net_set_timing": ([P, I], I),
         "fh_net_get_stats": ([P, ctypes.POINTER(fh_net_stats)], I),
         "fh_net_guess": ([P, P, ctypes.c_float, I, ctypes.POINTER(D), D, P], I),
+        "fh_net_layer": ([P, I, I, I, P, P, P, P], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -540,10 +542,11 @@ class Context:
 
 
     def solve_batch(self, systems, E, eta=1e-6, itmax=10000, precision=FH_FP32_REFINED,
-                    poll=0, eta_inner=0.0, u_out=None):
+                    poll=0, eta_inner=0.0, u_out=None, serial=False):
         """systems: list of (phase_dev uint8 tensor, n (3,), mat (nphase, 6, 6)).
         u_out: optional list of float64 CUDA tensors (nload x 3 x N each) that
-        receive the fluctuation fields.
+        receive the fluctuation fields.  serial: solve the grid-size groups
+        one after another (FH_FLAG_BATCH_SERIAL) instead of concurrently.
         Returns (rc, chom (nsys, nload, nload), [stats dicts], [group reports])."""
         E = np.ascontiguousarray(np.atleast_2d(E), dtype=np.float64)
         nload = E.shape[0]
@@ -561,7 +564,8 @@ class Context:
         chom = np.zeros((len(systems), nload, nload))
         sts = (fh_stats * len(systems))()
         rep = fh_batch_report()
-        o = self.opts(eta, itmax, precision, poll, eta_inner)
+        o = self.opts(eta, itmax, precision, poll, eta_inner,
+                      FH_FLAG_BATCH_SERIAL if serial else 0)
         rc = self._check(self.lib.fh_solve_batch(self.ptr, len(systems), arr, nload, _dptr(E),
                                                  ctypes.byref(o), _dptr_out(chom), sts,
                                                  ctypes.byref(rep)), allow_warning=True)
@@ -682,6 +686,27 @@ class Net:
         return self._check(self.lib.fh_net_pack_target(
             self.ptr, _tptr(u_dev, _f64(), 18 * V, self.device), float(scale),
             _tptr(target_dev, _BF16_CARRIERS(), 18 * V, self.device)))
+
+    LAYERS = [(3, 16, 0), (16, 16, 0), (16, 32, 1), (32, 32, 1), (32, 64, 2), (64, 64, 2),
+              (64, 64, 3), (64, 64, 3), (128, 64, 2), (64, 64, 2), (96, 32, 1), (32, 32, 1),
+              (48, 16, 0), (16, 16, 0)]  # (cin, cout, level), the header's layer order
+
+    def layer(self, layer, op, batch, x=None, dz=None, mask=None, out=None):
+        """fh_net_layer: op 0 forward, 1 input gradient, 2 weight gradient.
+        BF16 tensors are torch int16/uint16 carriers (channels last)."""
+        cin, cout, lev = self.LAYERS[layer]
+        V = (self.n >> lev) ** 3
+        cinp = (cin + 15) // 16 * 16
+        need_out = {0: batch * V * cout, 1: batch * V * cinp, 2: 27 * cin * cout + cout}[op]
+        import torch
+        odt = torch.float32 if op == 2 else _BF16_CARRIERS()
+        xp = None if x is None else _tptr(x, _BF16_CARRIERS(), batch * V * cinp, self.device)
+        dp = None if dz is None else _tptr(dz, _BF16_CARRIERS(), batch * V * cout, self.device)
+        mp = None if mask is None else _tptr(mask, _BF16_CARRIERS(), batch * V * cinp,
+                                             self.device)
+        op_ = _tptr(out, odt, need_out, self.device)
+        return self._check(self.lib.fh_net_layer(self.ptr, int(layer), int(op), int(batch), xp, dp,
+                                                 mp, op_))
 
     def set_timing(self, on=True):
         return self._check(self.lib.fh_net_set_timing(self.ptr, 1 if on else 0))

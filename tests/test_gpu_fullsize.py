@@ -18,6 +18,7 @@ gradients); the operator also at 256^3 elasticity, the largest grid.  These grid
   residual in the preconditioner's norm, not over sampled rows), symmetry of
   C_hom, the Voigt and Reuss bounds, and FP64 against FP32-refined results.
 """
+import os
 import sys
 
 import numpy as np
@@ -167,6 +168,42 @@ def test_conduction_256_solves(fh):
         assert lam.min() > reuss * (1 - 1e-12) and lam.max() < voigt * (1 + 1e-12)
     say("C_hom FP32-refined vs FP64", _rel(H[fh.FH_FP32_REFINED], H[fh.FH_FP64]))
     assert _rel(H[fh.FH_FP32_REFINED], H[fh.FH_FP64]) < 1e-10
+
+
+GOLDEN_256 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                          "conduction3d_grf_256_seed0.json")
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN_256),
+                    reason="stored oracle result for 256^3 conduction not written yet "
+                           "(tests/golden/make_golden.py conduction3d_grf_256)")
+def test_conduction_256_matches_stored_oracle(fh):
+    """256^3 conduction against the CPU oracle's stored result (assembled CSR
+    K, FFT-form preconditioner, PCG to 1e-8; tests/golden/make_golden.py):
+    FP64 and FP32-refined C_hom element by element to 1e-10 of the largest
+    entry, FP64 iteration counts to +-max(1, 1 %), and the fluctuation at
+    the stored sample nodes to 1e-6 relative (both solutions are within
+    about sqrt(kappa) eta = 3e-7 of the exact one at eta = 1e-8)."""
+    import hashlib
+    import json
+    g = json.load(open(GOLDEN_256))
+    wl, prob, ctx = _setup(fh, "conduction256")
+    k = np.ascontiguousarray(np.asarray(wl["kfield"], dtype=np.float64))
+    assert hashlib.sha256(k.tobytes()).hexdigest() == g["kfield_sha256"]
+    Hg = np.array(g["C_hom"])
+    nodes = np.array(g["sample_nodes"])
+    for prec in (fh.FH_FP64, fh.FH_FP32_REFINED):
+        rc, st = ctx.solve(eta=g["eta"], precision=prec, rebuild=True)
+        assert rc == 0
+        H = ctx.get_homogenized()
+        say("C_hom vs stored oracle, precision", prec, _rel(H, Hg))
+        assert _rel(H, Hg) <= 1e-10
+        if prec == fh.FH_FP64:
+            for a, b in zip(st["iterations"][:3], g["iterations"]):
+                assert abs(a - b) <= max(1, 0.01 * b), (st["iterations"], g["iterations"])
+        for j, u in enumerate(_fields(ctx, prob, 3)):
+            us = np.asarray(g["u_samples"][j])
+            assert np.linalg.norm(u[nodes] - us) <= 1e-6 * np.linalg.norm(us), (prec, j)
 
 
 def test_batch_96_benchmark_workload(fh):
