@@ -130,6 +130,13 @@ def batch_comparison(count: int):
     wls = batch_workload(count=count)
     devs = [(torch.from_numpy(w["phase"]).cuda(), w["n"], w["mat"]) for w in wls]
     ctx = fh.Context(0)
+    # the grid-size groups one after another (for comparison) ...
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.solve_batch(devs, np.eye(6), eta=1e-6, precision=fh.FH_FP32_REFINED, serial=True)
+    torch.cuda.synchronize()
+    t_serial = (time.perf_counter() - t0) * 1000.0
+    # ... and concurrently, one stream per group (the timed call)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rc, Hb, sts, rep = ctx.solve_batch(devs, np.eye(6), eta=1e-6, precision=fh.FH_FP32_REFINED)
@@ -163,6 +170,7 @@ def batch_comparison(count: int):
         "systems": count, "solves": 6 * count,
         "voxels_total": int(sum(np.prod(w["n"]) for w in wls)),
         "batched_fp32_refined_ms": round(t_batch, 1),
+        "batched_groups_serial_ms": round(t_serial, 1),
         "plain_fp64_sequential_ms": round(t_plain, 1),
         "fp32_refined_sequential_ms": round(t_refined_seq, 1),
         "speedup": round(t_plain / t_batch, 3),
@@ -323,6 +331,97 @@ def warm_start_comparison(ntrain: int, neval: int, steps: int, batch: int = 8, n
     }
 
 
+def further_rows():
+    """The rows beyond the linear solve, timed on the GPU (parity is in the
+    tests): eigenvalue bounds at 128^3, the elasto-plastic Newton loop at
+    64^3, the strain-based scheme against the displacement-based one at
+    64^3, and the two-node stencil against the one-node triangles on a
+    256^2 conduction grid."""
+    import numpy as np
+    import torch
+
+    from paper_2203_02962_amd import fh
+    from paper_2203_02962_amd.runner import setup_context
+    from synth import circles2d, isotropic_conductivity, isotropic_mandel, spheres, workload
+
+    out = {}
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t0) * 1000.0
+
+    # f3: nodal bounds of the 128^3 sphere workload (17 B per node moved)
+    wl = workload("elastic3d_spheres", seed=0, n=128)
+    c = setup_context(wl)
+    N = 128 ** 3
+    lo = torch.empty(N, dtype=torch.float64, device="cuda")
+    hi = torch.empty_like(lo)
+    c.eigen_bounds(None, 1e-6, lo, hi)
+    b, ms = timed(lambda: c.eigen_bounds(None, 1e-6, lo, hi))
+    rc, st = c.solve(eta=1e-6)
+    out["eigen_bounds_128"] = {"ms": round(ms, 3), "kappa": b["kappa"],
+                               "predicted_iterations_1e-6": b["predicted_iterations"],
+                               "pcg_iterations_1e-6": st["iterations"],
+                               "GBs_of_17B_per_node": round(17 * N / (ms * 1e-3) / 1e9, 1)}
+    c.close()
+    # f4: strain-based vs displacement-based, 64^3 spheres, 6 loads, 1e-6
+    wl = workload("elastic3d_spheres", seed=0, n=64)
+    c = setup_context(wl)
+    c.solve(eta=1e-6)
+    (rc, st_db), ms_db = timed(lambda: c.solve(eta=1e-6, rebuild=True))
+    H_db = c.get_homogenized()
+    (rc, st_sb), ms_sb = timed(lambda: c.solve_strain_based(eta=1e-6))
+    H_sb = c.get_homogenized()
+    out["strain_based_vs_displacement_64_1e-6"] = {
+        "db_ms": round(ms_db, 1), "sb_ms": round(ms_sb, 1),
+        "db_iterations": st_db["iterations"], "sb_iterations": st_sb["iterations"],
+        "chom_rel_diff": float(np.abs(H_sb - H_db).max() / np.abs(H_db).max())}
+    c.close()
+    # f1: Newton loop, 64^3 spheres, Sec. 6.3 phases (equal elastic constants,
+    # hard inclusions with twice the yield stress and hardening), deviatoric
+    # strain 0.005 in 5 increments, eta^NW = eta^CG = 1e-5 as in Sec. 6.3
+    n = 64
+    phase, _, _ = spheres(n, (3.0, 6.0), 0.3, seed=0)
+    Em, nu = 1.0, 0.3
+    K, G = Em / (3 * (1 - 2 * nu)), Em / (2 * (1 + nu))
+    params = np.array([[K, G, 0.0015, 0.005], [K, G, 0.003, 0.01]])
+    c = fh.Context(0)
+    c.set_grid((n, n, n), "elastic", "hex8")
+    ph = torch.from_numpy(phase).cuda()
+    c.set_plastic_phases(ph, params)
+    E = np.array([0.005, -0.005, 0, 0, 0, 0])
+    c.newton_solve(E, nincrement=5, eta_newton=1e-5, eta_cg=1e-5)
+    (rc, st), ms = timed(lambda: c.newton_solve(E, nincrement=5, eta_newton=1e-5, eta_cg=1e-5))
+    out["newton_plasticity_64"] = {
+        "ms": round(ms, 1), "rc": rc, "newton_steps": st["newton_steps"],
+        "pcg_total": st["total_pcg"], "pcg_per_step": st["pcg_iterations"],
+        "plastic_fraction": [round(v, 4) for v in st["plastic_fraction"]],
+        "macro_stress_11": [round(m[0], 8) for m in st["macro_stress"]],
+        "dof_pcg_iter_per_s": 3 * n ** 3 * st["total_pcg"] / (ms * 1e-3)}
+    c.close()
+    # f2: two-node vs one-node triangles, 256^2 conduction (the largest
+    # grid side), 2 loads, 1e-8
+    n = 256
+    phase = circles2d(n, 128, (3.0, 6.0), seed=0)
+    mat = np.stack([isotropic_conductivity(1.0, 2), isotropic_conductivity(10.0, 2)])
+    res = {}
+    for elem in ("tri4", "tri2"):
+        wl2 = dict(dim=2, n=(n, n, 1), problem="scalar", element=elem, phase=phase, mat=mat,
+                   loads=np.eye(2))
+        c = setup_context(wl2)
+        c.solve(eta=1e-8)
+        (rc, st), ms = timed(lambda: c.solve(eta=1e-8, rebuild=True))
+        res[elem] = {"ms": round(ms, 2), "iterations": st["iterations"],
+                     "dof_iter_per_s": st["dof"] * sum(st["iterations"]) / (ms * 1e-3),
+                     "C_hom": c.get_homogenized().tolist()}
+        c.close()
+    out["two_node_vs_tri2_256_1e-8"] = res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -345,6 +444,8 @@ def main():
     ap.add_argument("--warm-steps", type=int, default=4000)
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run a plain 512 MiB device copy (counter calibration)")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="skip the further rows (bounds, Newton, strain-based, two-node)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched comparison (for a kernel trace of it)")
     ap.add_argument("--timed-only", action="store_true",
@@ -532,6 +633,9 @@ def main():
         "roofline": roof,
         "iteration_roofline": iteration_roofline,
     }
+    if not args.no_rows and not args.timed_only:
+        print("[bench] further rows ...", file=sys.stderr, flush=True)
+        out["config"]["further_rows"] = further_rows()
     if not args.no_batch:
         out["config"]["batched_vs_plain_1e-6"] = batch_comparison(args.batch_count)
     if not args.no_conduction:

@@ -96,6 +96,9 @@ extern "C" {
  * microseconds around its events, so timing every launch slows the loop;
  * the per-class totals then cover the sampled iterations only.             */
 #define FH_FLAG_TIME_SAMPLED 8
+/* fh_opts.flags for fh_solve_batch: solve the grid-size groups one after
+ * another instead of concurrently (each group on its own stream)           */
+#define FH_FLAG_BATCH_SERIAL 16
 
 /* kernel classes of fh_stats.kernel_ms / kernel_launches                  */
 #define FH_K_OPERATOR 0   /* q = K p (+ p.q partials)                       */

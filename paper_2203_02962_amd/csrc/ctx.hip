@@ -21,7 +21,9 @@
 #include <string>
 #include <vector>
 
+#include <condition_variable>
 #include <mutex>
+#include <thread>
 
 #include "../../include/fh.h"
 #include "fh_internal.h"
@@ -1484,9 +1486,32 @@ int autotune(fh_ctx* c, int nload_all, double* tune_ms) {
   return FH_OK;
 }
 
+// Start line for the solves of concurrently running groups: every group
+// finishes its set-up and launch-shape tuning (timed on an otherwise idle
+// GPU, one group at a time under `tune_mu`) before any group starts solving.
+struct BatchGate {
+  std::mutex tune_mu, mu;
+  std::condition_variable cv;
+  int waiting = 0, total = 1;
+  void arrive() {
+    std::unique_lock<std::mutex> lk(mu);
+    if (++waiting >= total) cv.notify_all();
+    else cv.wait(lk, [&] { return waiting >= total; });
+  }
+};
+
 int batch_group(fh_ctx* parent, const std::vector<int>& idx, const fh_system* sys, int nload,
                 const double* E, const fh_opts& o, double* chom, fh_stats* st,
-                fh_batch_report* rep, int gi) {
+                fh_batch_report* rep, int gi, BatchGate* gate) {
+  // the gate is passed exactly once, whatever path leaves this function
+  struct Arrive {
+    BatchGate* g;
+    bool done = false;
+    void now() { if (g && !done) { done = true; g->arrive(); } }
+    ~Arrive() { now(); }
+  } arrive{gate};
+  std::unique_lock<std::mutex> tune_lock;
+  if (gate) tune_lock = std::unique_lock<std::mutex>(gate->tune_mu);
   fh_ctx* c = nullptr;
   if (fh_create(&c, parent->device) != FH_OK) return fail(parent, FH_EDEVICE, "fh_create");
   struct Owner {
@@ -1604,6 +1629,8 @@ int batch_group(fh_ctx* parent, const std::vector<int>& idx, const fh_system* sy
   const double setup_ms = ms_since(t0);
   double tune_ms = 0.0;
   if ((rc = autotune(c, c->nload, &tune_ms))) return pfail(rc);
+  if (gate) tune_lock.unlock();
+  arrive.now();
   // solve all microstructures x loads together
   auto t1 = std::chrono::steady_clock::now();
   c->use_graph = true;
@@ -1719,10 +1746,33 @@ extern "C" int fh_solve_batch(fh_ctx* c, int nsys, const fh_system* sys, int nlo
     HIPCHK(c, hipDeviceSynchronize());
   }
   int worst = FH_OK;
-  for (size_t gi = 0; gi < groups.size(); ++gi) {
-    const int rc = batch_group(c, groups[gi], sys, nload, E, o, chom, st, rep, (int)gi);
-    if (rc < 0) return rc;
-    if (rc > 0) worst = rc;
+  const int ng = (int)groups.size();
+  if ((o.flags & FH_FLAG_BATCH_SERIAL) || ng == 1) {
+    for (int gi = 0; gi < ng; ++gi) {
+      const int rc = batch_group(c, groups[gi], sys, nload, E, o, chom, st, rep, gi, nullptr);
+      if (rc < 0) return rc;
+      if (rc > 0) worst = rc;
+    }
+    return worst;
+  }
+  // groups of different grid sizes run concurrently, one host thread and one
+  // stream each; every thread reports into its own error holder
+  BatchGate gate;
+  gate.total = ng;
+  std::vector<fh_ctx> holders(ng);
+  std::vector<int> rcs(ng, FH_OK);
+  std::vector<std::thread> threads;
+  for (int gi = 0; gi < ng; ++gi) {
+    holders[gi].device = c->device;
+    threads.emplace_back([&, gi] {
+      hipSetDevice(c->device);
+      rcs[gi] = batch_group(&holders[gi], groups[gi], sys, nload, E, o, chom, st, rep, gi, &gate);
+    });
+  }
+  for (std::thread& t : threads) t.join();
+  for (int gi = 0; gi < ng; ++gi) {
+    if (rcs[gi] < 0) return fail(c, rcs[gi], holders[gi].err);
+    if (rcs[gi] > 0) worst = rcs[gi];
   }
   return worst;
 }

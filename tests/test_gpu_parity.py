@@ -560,6 +560,11 @@ def test_batch_matches_single_solves_and_oracle(fh, precision):
     rc, H, sts, rep = ctx.solve_batch(devs, np.eye(6), eta=1e-10, precision=prec, eta_inner=1e-4)
     assert rc == 0, sts
     assert len(rep) == 3 and sorted(r["nsys"] for r in rep) == [1, 2, 3]
+    # the groups ran concurrently; one after another they give the same bits
+    rc2, H2, sts2, _ = ctx.solve_batch(devs, np.eye(6), eta=1e-10, precision=prec,
+                                       eta_inner=1e-4, serial=True)
+    assert rc2 == 0 and np.array_equal(H, H2)
+    assert [s["iterations"] for s in sts] == [s["iterations"] for s in sts2]
     for i, (ph, n, m) in enumerate(sysl):
         wl = dict(dim=3, n=n, problem="elastic", element="hex8", phase=ph, mat=m, loads=np.eye(6))
         c1 = setup_context(wl)
