@@ -125,6 +125,25 @@ __host__ __device__ __forceinline__ int lds_stride(int n) {
   return sizeof(T) == 8 ? ((n + (n >> 3) + 1) | 1) : n + 1;
 }
 
+// Quotient by a block-uniform divisor d >= 1 through one 24-bit multiply:
+// with M = ceil(2^21 / d), (x M) >> 21 equals x / d whenever x d <= 2^21 and
+// x M < 2^32.  (Write M d = 2^21 + e with 0 <= e < d; the excess x e /
+// (d 2^21) of x M / 2^21 over x / d is below 1/d, too little to carry the
+// fraction (x mod d) / d <= (d - 1) / d across an integer.)  Every use
+// divides a block-local index below 4096 by a line length or count of at
+// most 256, with quotients below 32 where the index passes 2048, inside both
+// bounds; a generic integer division costs about ten instructions per use.
+struct UDiv {
+  int d;
+  unsigned M;
+  __device__ __forceinline__ explicit UDiv(int d_)
+      : d(d_), M(((1u << 21) + (unsigned)d_ - 1u) / (unsigned)d_) {}
+  __device__ __forceinline__ int q(int x) const {
+    return (int)(__umul24((unsigned)x, M) >> 21);
+  }
+  __device__ __forceinline__ int r(int x, int qq) const { return x - __mul24(qq, d); }
+};
+
 // One in-place Stockham stage on `nlines` lines of length n (line stride n):
 // every thread first reads its butterflies' inputs into registers, the
 // block synchronises, then the results are written back.  L = product of the
@@ -144,6 +163,7 @@ __device__ __forceinline__ void stockham_stage_io(const Src& src, const Sink& si
   const int m = n / R;
   const int items = nlines * m;
   const int twstep = n / (L * R);
+  const UDiv dm(m), dL(L);
   cplx<T> v[MAXIT][R];
   int dst[MAXIT], de[MAXIT];
 #pragma unroll
@@ -151,22 +171,23 @@ __device__ __forceinline__ void stockham_stage_io(const Src& src, const Sink& si
     const int it = threadIdx.x + k * kThreads;
     dst[k] = -1;
     if (it < items) {
-      const int line = it / m;
-      const int j = it - line * m;
-      const int kk = j % L;
+      const int line = dm.q(it);
+      const int j = dm.r(it, line);
+      const int jl = dL.q(j);
+      const int kk = dL.r(j, jl);
 #pragma unroll
       for (int t = 0; t < R; ++t) {
         cplx<T> a = src(line, j + t * m);
         if (t > 0 && L > 1) {
           // t*kk < R*L, so the index stays below n
-          cplx<T> w = tw[t * kk * twstep];
+          cplx<T> w = tw[t * __mul24(kk, twstep)];
           if (sign > 0) w.im = -w.im;
           a = cmul(a, w);
         }
         v[k][t] = a;
       }
       dst[k] = line;
-      de[k] = (j / L) * L * R + kk;
+      de[k] = __mul24(jl, L * R) + kk;
     }
   }
   if (in_place) __syncthreads();
@@ -186,7 +207,7 @@ __device__ __forceinline__ void stockham_stage_from(const Src& src, bool in_plac
                                                     int n, int ls, int nlines, int L,
                                                     const cplx<T>* tw, int sign) {
   stockham_stage_io<T, R>(
-      src, [&](int line, int e, cplx<T> v) { buf[line * ls + sw<T>(e)] = v; }, in_place, n,
+      src, [&](int line, int e, cplx<T> v) { buf[__mul24(line, ls) + sw<T>(e)] = v; }, in_place, n,
       nlines, L, tw, sign);
 }
 
@@ -194,7 +215,7 @@ template <typename T, int R>
 __device__ __forceinline__ void stockham_stage(cplx<T>* buf, int n, int ls, int nlines, int L,
                                                const cplx<T>* tw, int sign) {
   stockham_stage_from<T, R>(
-      [&](int line, int e) { return buf[line * ls + sw<T>(e)]; }, true, buf, n, ls, nlines, L,
+      [&](int line, int e) { return buf[__mul24(line, ls) + sw<T>(e)]; }, true, buf, n, ls, nlines, L,
       tw, sign);
 }
 
@@ -305,10 +326,11 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && P3) ? 4 : 5) k_xf
   const T alpha = (mode == XF_UPDATE_R) ? T(st[ld].alpha) : T(0);
   const int lsx = lds_stride<T>(nx);
   const T* qb = q ? q + (long long)ld * qstride + ((long long)c * g.nz + z) * ny * nx : nullptr;
+  const UDiv dnx(nx);
   staged_fill<8, T>(
       kRows * nx,
       [&](int idx) {
-        const int row = idx / nx, x = idx - row * nx, y = y0 + row;
+        const int row = dnx.q(idx), x = dnx.r(idx, row), y = y0 + row;
         T v = T(0);
         if (y < ny) {
           const long long o = rbase + (long long)y * nx + x;
@@ -321,8 +343,8 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && P3) ? 4 : 5) k_xf
         return v;
       },
       [&](int idx, T v) {
-        const int row = idx / nx, x = idx - row * nx;
-        cplx<T>& d = a[(row >> 1) * lsx + sw<T>(x)];
+        const int row = dnx.q(idx), x = dnx.r(idx, row);
+        cplx<T>& d = a[__mul24(row >> 1, lsx) + sw<T>(x)];
         if (row & 1) d.im = v; else d.re = v;
       });
   __syncthreads();
@@ -331,9 +353,9 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && P3) ? 4 : 5) k_xf
   for (int idx = threadIdx.x; idx < kRows * nxh; idx += blockDim.x) {
     const int yl = idx % kRows, kx = idx / kRows, y = y0 + yl;
     if (y >= ny) continue;
-    const cplx<T>* line = res + (yl >> 1) * lsx;
+    const cplx<T>* line = res + __mul24(yl >> 1, lsx);
     const cplx<T> ck = line[sw<T>(kx)];
-    const cplx<T> cn = line[sw<T>((nx - kx) % nx)];
+    const cplx<T> cn = line[sw<T>(kx == 0 ? 0 : nx - kx)];
     cplx<T> X;
     if ((yl & 1) == 0) {
       X = {T(0.5) * (ck.re + cn.re), T(0.5) * (ck.im - cn.im)};
@@ -369,7 +391,7 @@ __global__ void __launch_bounds__(kThreads) k_yfwd(Grid g, AxisPlan py, const cp
     if (z < nz) v = A[base + (((long long)c * nz + z) * nxh + kx) * ny + y];
     return v;
   };
-  auto lsink = [&](int l, int y, cplx<T> v) { a[l * ls + sw<T>(y)] = v; };
+  auto lsink = [&](int l, int y, cplx<T> v) { a[__mul24(l, ls) + sw<T>(y)] = v; };
   cplx<T>* res = a;
   if (py.nstage >= 1) {
     const int R0 = py.code & 15u;
@@ -381,9 +403,10 @@ __global__ void __launch_bounds__(kThreads) k_yfwd(Grid g, AxisPlan py, const cp
     __syncthreads();
   }
   const long long obase = base + ((long long)c * nxh + kx) * (long long)ny * nz;
+  const UDiv dzb(zb);
   for (int idx = threadIdx.x; idx < zb * ny; idx += blockDim.x) {
-    const int zl = idx % zb, ky = idx / zb, z = z0 + zl;
-    if (z < nz) B[obase + (long long)ky * nz + z] = res[zl * ls + sw<T>(ky)];
+    const int ky = dzb.q(idx), zl = dzb.r(idx, ky), z = z0 + zl;
+    if (z < nz) B[obase + (long long)ky * nz + z] = res[__mul24(zl, ls) + sw<T>(ky)];
   }
 }
 
@@ -402,6 +425,7 @@ __device__ double zpass_fused_mid(cplx<T>* a, int n, int ls, int cls, int kyb, i
   constexpr int MAXIT = (2048 / 6 + kThreads - 1) / kThreads;  // kyb * n/2 <= 2048 / 6
   const int m = n / 2;
   const int items = kyb * m;
+  const UDiv dm(m);
   cplx<T> v[MAXIT][3][2];
   int jj[MAXIT], kyl_[MAXIT];
 #pragma unroll
@@ -409,11 +433,11 @@ __device__ double zpass_fused_mid(cplx<T>* a, int n, int ls, int cls, int kyb, i
     const int it = threadIdx.x + k * kThreads;
     kyl_[k] = -1;
     if (it < items) {
-      const int kyl = it / m, j = it - kyl * m;
+      const int kyl = dm.q(it), j = dm.r(it, kyl);
       const cplx<T> w = tw[j];  // forward twiddle of the last stage: L = n/2, t = 1
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const cplx<T>* src = a + c * cls + kyl * ls;
+        const cplx<T>* src = a + c * cls + __mul24(kyl, ls);
         const cplx<T> x0 = src[sw<T>(j)];
         const cplx<T> x1 = cmul(src[sw<T>(j + m)], w);
         v[k][c][0] = cadd(x0, x1);
@@ -432,7 +456,8 @@ __device__ double zpass_fused_mid(cplx<T>* a, int n, int ls, int cls, int kyb, i
     if (ky < ny) {
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        const long long f = ((long long)kx * ny + ky) * nz + j + t * m;
+        // below 6 nxh ny nz < 2^31 for every accepted grid
+        const int f = (kx * ny + ky) * nz + j + t * m;
         const T k00 = kplus[f], k11 = kplus[nfreq + f], k22 = kplus[2 * nfreq + f];
         const T k12 = kplus[3 * nfreq + f], k02 = kplus[4 * nfreq + f],
                 k01 = kplus[5 * nfreq + f];
@@ -454,7 +479,7 @@ __device__ double zpass_fused_mid(cplx<T>* a, int n, int ls, int cls, int kyb, i
     // first inverse stage (radix 2, no twiddle): outputs at 2j and 2j + 1
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      cplx<T>* dst = a + c * cls + kyl * ls;
+      cplx<T>* dst = a + c * cls + __mul24(kyl, ls);
       dst[sw<T>(2 * j)] = cadd(v[k][c][0], v[k][c][1]);
       dst[sw<T>(2 * j + 1)] = csub(v[k][c][0], v[k][c][1]);
     }
@@ -474,6 +499,7 @@ __device__ double zpass_fused_mid_scalar(cplx<T>* a, int n, int ls, int kyb, int
   constexpr int MAXIT = (2048 / R + kThreads - 1) / kThreads;  // kyb * n <= 2048
   const int m = n / R;
   const int items = kyb * m;
+  const UDiv dm(m);
   cplx<T> v[MAXIT][R];
   int jj[MAXIT], kyl_[MAXIT];
 #pragma unroll
@@ -481,8 +507,8 @@ __device__ double zpass_fused_mid_scalar(cplx<T>* a, int n, int ls, int kyb, int
     const int it = threadIdx.x + k * kThreads;
     kyl_[k] = -1;
     if (it < items) {
-      const int kyl = it / m, j = it - kyl * m;
-      const cplx<T>* src = a + kyl * ls;
+      const int kyl = dm.q(it), j = dm.r(it, kyl);
+      const cplx<T>* src = a + __mul24(kyl, ls);
 #pragma unroll
       for (int t = 0; t < R; ++t) {
         cplx<T> x = src[sw<T>(j + t * m)];
@@ -503,7 +529,7 @@ __device__ double zpass_fused_mid_scalar(cplx<T>* a, int n, int ls, int kyb, int
     if (ky < ny) {
 #pragma unroll
       for (int t = 0; t < R; ++t) {
-        const T kp = kplus[((long long)kx * ny + ky) * nz + j + t * m];
+        const T kp = kplus[(kx * ny + ky) * nz + j + t * m];
         const cplx<T> r = v[k][t];
         part += wgt * (double)kp * ((double)r.re * r.re + (double)r.im * r.im);
         v[k][t] = {kp * r.re, kp * r.im};
@@ -511,7 +537,7 @@ __device__ double zpass_fused_mid_scalar(cplx<T>* a, int n, int ls, int kyb, int
     }
     // first inverse stage (radix R, L = 1, no twiddles): outputs at jR + t
     dft_small<T, R>(v[k], +1);
-    cplx<T>* dst = a + kyl * ls;
+    cplx<T>* dst = a + __mul24(kyl, ls);
 #pragma unroll
     for (int t = 0; t < R; ++t) dst[sw<T>(j * R + t)] = v[k][t];
   }
@@ -561,8 +587,9 @@ __global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan
                      ((nd == 3 && last_radix == 2 && kyb * nz <= 2048 / 3) ||
                       (nd == 1 && (last_radix == 2 || last_radix == 4 || last_radix == 8)));
   // line l = c * kyb + kyl of the block is component c of frequency line ky0 + kyl
+  const UDiv dkyb(kyb);
   auto gsrc = [&](int l, int z) -> cplx<T> {
-    const int c = l / kyb, ky = ky0 + (l - c * kyb);
+    const int c = dkyb.q(l), ky = ky0 + dkyb.r(l, c);
     cplx<T> v = {T(0), T(0)};
     if (ky < ny) v = B[base + c * cstride + (long long)ky * nz + z];
     return v;
@@ -571,10 +598,10 @@ __global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan
   // and the last inverse stage writes them back (their butterflies touch runs
   // of consecutive elements), so no staging pass is needed
   const bool direct = mode == Z_SOLVE && pz.nstage >= 1;  // nz = 1 (2D) has no stage
-  auto lsrc = [&](int l, int z) { return a[l * ls + sw<T>(z)]; };
-  auto lsink = [&](int l, int z, cplx<T> v) { a[l * ls + sw<T>(z)] = v; };
+  auto lsrc = [&](int l, int z) { return a[__mul24(l, ls) + sw<T>(z)]; };
+  auto lsink = [&](int l, int z, cplx<T> v) { a[__mul24(l, ls) + sw<T>(z)] = v; };
   auto gsink = [&](int l, int z, cplx<T> v) {
-    const int c = l / kyb, ky = ky0 + (l - c * kyb);
+    const int c = dkyb.q(l), ky = ky0 + dkyb.r(l, c);
     if (ky < ny) B[base + c * cstride + (long long)ky * nz + z] = v;
   };
   const int R0 = pz.code & 15u;
@@ -617,8 +644,9 @@ __global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan
   if (mode == Z_SOLVE && !fused) {
     const long long nfreq = (long long)nxh * ny * nz;
     const double wgt = (kx == 0 || (2 * kx == g.nx)) ? 1.0 : 2.0;
+    const UDiv dnz(nz);
     for (int idx0 = threadIdx.x; idx0 < per; idx0 += blockDim.x) {
-      const int kyl = idx0 / nz, kz = idx0 - kyl * nz, ky = ky0 + kyl;
+      const int kyl = dnz.q(idx0), kz = dnz.r(idx0, kyl), ky = ky0 + kyl;
       if (ky >= ny) continue;
       const int idx = kyl * ls + sw<T>(kz);
       const long long f = ((long long)kx * ny + ky) * nz + kz;
@@ -704,21 +732,22 @@ __global__ void __launch_bounds__(kThreads) k_yinv(Grid g, AxisPlan py, const cp
   const long long base = (long long)ld * sstride;
   const long long ibase = base + ((long long)c * nxh + kx) * (long long)ny * nz;
   const int ls = lds_stride<T>(ny);
+  const UDiv dzb(zb);
   staged_fill<8, cplx<T>>(
       zb * ny,
       [&](int idx) {
-        const int zl = idx % zb, ky = idx / zb, z = z0 + zl;
+        const int ky = dzb.q(idx), zl = dzb.r(idx, ky), z = z0 + zl;
         cplx<T> v = {T(0), T(0)};
         if (z < nz) v = B[ibase + (long long)ky * nz + z];
         return v;
       },
       [&](int idx, cplx<T> v) {
-        const int zl = idx % zb, ky = idx / zb;
-        a[zl * ls + sw<T>(ky)] = v;
+        const int ky = dzb.q(idx), zl = dzb.r(idx, ky);
+        a[__mul24(zl, ls) + sw<T>(ky)] = v;
       });
   __syncthreads();
   // the y lines are contiguous in A: the last stage writes them to HBM
-  auto lsrc = [&](int l, int y) { return a[l * ls + sw<T>(y)]; };
+  auto lsrc = [&](int l, int y) { return a[__mul24(l, ls) + sw<T>(y)]; };
   auto gsink = [&](int zl, int y, cplx<T> v) {
     const int z = z0 + zl;
     if (z < nz) A[base + (((long long)c * nz + z) * nxh + kx) * ny + y] = v;
@@ -745,10 +774,11 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
   const int nx = g.nx, ny = g.ny, nxh = g.nxh;
   const int y0 = blockIdx.x * kRows, z = blockIdx.y;
   const long long fbase = (long long)ld * fstride + ((long long)c * g.nz + z) * ny * nx;
+  const UDiv dnx(nx);
   if (mode == XI_PCG && (status == ST_CONVERGED_PENDING || status == ST_MAXIT_PENDING)) {
     const T alpha = T(st[ld].alpha);
     for (int idx = threadIdx.x; idx < kRows * nx; idx += blockDim.x) {
-      const int row = idx / nx, xx = idx - row * nx, y = y0 + row;
+      const int row = dnx.q(idx), xx = dnx.r(idx, row), y = y0 + row;
       if (y < ny) {
         const long long o = fbase + (long long)y * nx + xx;
         x[o] += alpha * p[o];
@@ -772,7 +802,7 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
       const int idx = threadIdx.x + k * kThreads;
-      const int row = idx / nx, xx = idx - row * nx, y = y0 + row;
+      const int row = dnx.q(idx), xx = dnx.r(idx, row), y = y0 + row;
       if (idx < nout && y < ny) {
         const long long o = fbase + (long long)y * nx + xx;
         pv0[k] = p[o];
@@ -791,7 +821,7 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
       },
       [&](int idx, cplx<T> v) {
         const int yl = idx % kRows, kx = idx / kRows;
-        S[yl * (nxh + 1) + kx] = v;
+        S[__mul24(yl, nxh + 1) + kx] = v;
       });
   __syncthreads();
   // Complex line j carries real rows 2j and 2j+1: X_a + i X_b, with the
@@ -800,16 +830,17 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
   const int half = nx / 2;
   auto packed = [&](int j, int k) -> cplx<T> {
     cplx<T> xa, xb;
+    const int s0 = __mul24(2 * j, nxh + 1);
     if (k <= half) {
-      xa = S[(2 * j) * (nxh + 1) + k];
-      xb = S[(2 * j + 1) * (nxh + 1) + k];
+      xa = S[s0 + k];
+      xb = S[s0 + nxh + 1 + k];
       if (k == 0 || k == half) {
         xa.im = T(0);
         xb.im = T(0);
       }
     } else {
-      xa = conjg(S[(2 * j) * (nxh + 1) + (nx - k)]);
-      xb = conjg(S[(2 * j + 1) * (nxh + 1) + (nx - k)]);
+      xa = conjg(S[s0 + (nx - k)]);
+      xb = conjg(S[s0 + nxh + 1 + (nx - k)]);
     }
     return {xa.re - xb.im, xa.im + xb.re};
   };
@@ -835,7 +866,7 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         const int idx = base + k * kThreads;
-        const int row = idx / nx, xx = idx - row * nx, y = y0 + row;
+        const int row = dnx.q(idx), xx = dnx.r(idx, row), y = y0 + row;
         if (idx < nout && y < ny) {
           const long long o = fbase + (long long)y * nx + xx;
           pv[k] = p[o];
@@ -846,9 +877,9 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
       const int idx = base + k * kThreads;
-      const int row = idx / nx, xx = idx - row * nx, y = y0 + row;
+      const int row = dnx.q(idx), xx = dnx.r(idx, row), y = y0 + row;
       if (idx >= nout || y >= ny) continue;
-      const cplx<T> v = res[(row >> 1) * lsx + sw<T>(xx)];
+      const cplx<T> v = res[__mul24(row >> 1, lsx) + sw<T>(xx)];
       const T zv = (row & 1) ? v.im : v.re;
       const long long o = fbase + (long long)y * nx + xx;
       if (mode == XI_PLAIN) {

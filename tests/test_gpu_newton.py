@@ -67,23 +67,26 @@ def _gpu(fh, n, phase, params, E, nincr, ref, eta_nw=1e-9, eta_cg=1e-10):
     return out
 
 
-def _compare(st, u, ep, al, uo, epo, alo, res):
+def _compare(st, u, ep, al, uo, epo, alo, res, tol_stress=1e-9, tol_field=1e-8,
+             same_yield_set=True):
     for k, r in enumerate(res):
         assert st["newton_steps"][k] == r.newton_steps, (k, st["newton_steps"], r.newton_steps)
         assert st["converged"][k] == int(r.converged)
         for a, b in zip(st["pcg_iterations"][k], r.pcg_iterations):
             assert abs(a - b) <= max(1, 0.01 * b), (k, st["pcg_iterations"][k], r.pcg_iterations)
         ms = np.array(st["macro_stress"][k])
-        assert np.abs(ms - r.macro_stress).max() <= 1e-9 * np.abs(r.macro_stress).max()
-        assert abs(st["plastic_fraction"][k] - r.plastic_fraction) <= 1e-12
-    assert np.linalg.norm(u - uo) <= 1e-8 * max(np.linalg.norm(uo), 1e-300)
+        assert np.abs(ms - r.macro_stress).max() <= tol_stress * np.abs(r.macro_stress).max()
+        if same_yield_set:
+            assert abs(st["plastic_fraction"][k] - r.plastic_fraction) <= 1e-12
+    assert np.linalg.norm(u - uo) <= tol_field * max(np.linalg.norm(uo), 1e-300)
     alo_t = alo.T                    # oracle (N, 8) -> (8, N)
     if alo.max() > 0:
-        assert np.abs(al - alo_t).max() <= 1e-8 * alo.max()
-    assert np.array_equal(al > 0, alo_t > 0)
+        assert np.abs(al - alo_t).max() <= tol_field * alo.max()
+    if same_yield_set:
+        assert np.array_equal(al > 0, alo_t > 0)
     epo_t = np.transpose(epo, (2, 1, 0))  # (N, 8, 6) -> (6, 8, N)
     if np.abs(epo).max() > 0:
-        assert np.abs(ep - epo_t).max() <= 1e-8 * np.abs(epo).max()
+        assert np.abs(ep - epo_t).max() <= tol_field * np.abs(epo).max()
 
 
 @pytest.mark.parametrize("ref", ["tangent", "elastic"])
@@ -119,6 +122,34 @@ def test_newton_with_equal_elastic_phases(fh):
     assert st["pcg_iterations"][0] == [0] and st["plastic_fraction"][0] == 0.0
     assert st["plastic_fraction"][-1] > 0.0
     _compare(st, u, ep, al, uo, epo, alo, res)
+
+
+def test_newton_through_full_yield_matches_oracle(fh):
+    """The benchmark's loading (Sec. 6.3 phases with equal elastic
+    constants, deviatoric strain 0.005 in 5 increments, eta^NW = eta^CG =
+    1e-5) at 12^3: the soft phase yields in the second increment and almost
+    every point by the last, with Newton steps that first grow the
+    displacement increment (ratios up to 0.8) before they contract.  Newton
+    steps per increment equal, PCG iterations +-max(1, 1 %).  Each Newton
+    system is solved to 1e-5 only, so where a PCG test lands next to its
+    threshold the two sides may stop one iteration apart and their iterates
+    differ by up to about that tolerance: fields and stresses are compared
+    to 1e-6 relative, and the share of yielding points to 1e-3."""
+    n = 12
+    phase, params = _problem(n, 3, 1.0)
+    E = np.array([0.005, -0.005, 0.0, 0.0, 0.0, 0.0])
+    rc, st, u, ep, al = _gpu(fh, n, phase, params, E, 5, fh.FH_NEWTON_REF_TANGENT,
+                             eta_nw=1e-5, eta_cg=1e-5)
+    assert rc == 0, st
+    pp = op.PlasticProblem((n,) * 3, phase, params)
+    uo, epo, alo, res = op.newton_solve(pp, E, 5, eta_nw=1e-5, eta_cg=1e-5)
+    say("full yield: gpu", st["newton_steps"], st["pcg_iterations"], st["plastic_fraction"])
+    say("full yield: oracle", [r.newton_steps for r in res], [r.pcg_iterations for r in res])
+    assert st["plastic_fraction"][-1] > 0.95 and max(r.newton_steps for r in res) >= 5
+    for k, r in enumerate(res):
+        assert abs(st["plastic_fraction"][k] - r.plastic_fraction) <= 1e-3
+    _compare(st, u, ep, al, uo, epo, alo, res, tol_stress=1e-6, tol_field=1e-6,
+             same_yield_set=False)
 
 
 def test_newton_residual_at_48(fh):
