@@ -35,10 +35,15 @@ constexpr int kThreads = 256;
 // 509 -> 420 us; FP32 inverse 288 -> 245 us, FP32 forward slower).  FP32
 // blocks of 16 rows move half the bytes of FP64 ones, and 32 rows
 // (nx <= 128) can be chosen by the autotuner.
+// Rows per block of the x passes.  FP32 lines up to 128 take 32 rows when
+// the batch tuner chose them (g.xrows) and, untuned, in the forward pass
+// (128^3: 157 -> 146 us per 6-load launch; the inverse pass is slower that
+// way, 172 -> 226 us).
 template <typename T>
 static int xpass_rows(const Grid& g, bool inverse) {
   if (g.nx >= 256) return (sizeof(T) == 8 || inverse) ? 8 : 16;
-  return (sizeof(T) == 4 && g.xrows == 32 && g.nx <= 128) ? 32 : 16;
+  if (sizeof(T) == 4 && g.nx <= 128 && (g.xrows == 32 || (g.xrows == 0 && !inverse))) return 32;
+  return 16;
 }
 
 template <typename T>

@@ -245,9 +245,12 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT))
 // 2^-(2-|M|) / h_beta, which scale the gradient coefficients on the way in
 // and the modal forces on the way out.  The PCG product p.q is taken at the
 // output nodes (p is still in the LDS plane), so no per-voxel energy is
-// formed.  Two node planes sit in LDS and the next one is prefetched into
-// registers while the current slab is computed; the modal forces of a slab's
-// upper face stay in registers until the next slab adds its own.
+// formed.  The next node plane is prefetched into registers while the
+// current slab is computed; the modal forces of a slab's upper face stay in
+// registers until the next slab adds its own.  Three node planes rotate in
+// LDS and the lower-face forces are double-buffered, so a slab needs one
+// barrier: every buffer a step overwrites was last read before the previous
+// step's barrier.
 template <typename T, int M>
 __device__ __forceinline__ void iso_term(const T (&w)[3][8], T (&f)[3][8], const T lam,
                                          const T mu2, const T ax, const T ay, const T az) {
@@ -337,9 +340,14 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
   using Cfg = HexCfg<T, TX, TY>;
   constexpr int EX = Cfg::EX, PX = Cfg::PX, NEL = Cfg::NEL, NP = Cfg::NP, NT = Cfg::NT;
   constexpr int NPF = (NP + NT - 1) / NT;  // plane nodes per thread
-  __shared__ T plane[2][3][NP];
-  __shared__ uint8_t phl[2][NP];  // voxel phases of the slab above each plane
-  __shared__ T force[12][NEL];  // lower-face totals of the current slab
+  // three rotating node planes: the next one is stored while the current
+  // slab reads the other two, so one barrier per slab suffices
+  __shared__ T plane[3][3][NP];
+  __shared__ uint8_t phl[3][NP];  // voxel phases of the slab above each plane
+  // lower-face corners 0..2 of the current slab, double-buffered across
+  // slabs; corner 3 of a thread's element lands on its own output node and
+  // stays in registers
+  __shared__ T force[2][9][NEL];
   __shared__ double red[32];
   // per-phase {V lambda, 2 V mu}, sized by the launch (2 nphase_max)
   extern __shared__ __align__(16) unsigned char kop_dyn[];
@@ -423,14 +431,16 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
   fetch(z0);
   store(1);
   if (z0 + 1 <= z1) fetch(z0 + 1);
+  __syncthreads();
   const int nsteps = z1 - z0 + 1;
+  int blo = 0, bhi = 1, bnx = 2;
   for (int s = 0; s < nsteps; ++s) {
     const int zs = z0 - 1 + s;
-    const int blo = s & 1, bhi = blo ^ 1;
+    const int fb = s & 1;
     const int ox = ei, oy = ej;
     const bool out_ok = s > 0 && ox < TX && oy < TY && x0 + ox < nx && y0 + oy < ny;
     const long long o = ((long long)zs * ny + (y0 + oy)) * nx + (x0 + ox);
-    __syncthreads();
+    T own[3] = {T(0), T(0), T(0)};
     if (is_elem) {
       T w[3][8];
 #pragma unroll
@@ -518,7 +528,8 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
               fl[k | bit] = fm + fd;
             }
 #pragma unroll
-          for (int k = 0; k < 4; ++k) force[c * 4 + k][tid] = fl[k];
+          for (int k = 0; k < 3; ++k) force[fb][c * 3 + k][tid] = fl[k];
+          own[c] = fl[3];
         }
       }
     }
@@ -530,23 +541,29 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
       pd1 = plane[blo][1][pidx];
       pd2 = plane[blo][2][pidx];
     }
-    __syncthreads();
-    // the lower plane is no longer read: refill it with plane zs+2, prefetch zs+3
+    // plane zs+2 goes into the buffer of plane zs-1, which no thread reads
+    // any more (every thread passed the previous barrier after its last
+    // read); then prefetch zs+3
     if (zs + 2 <= z1) {
-      store(blo);
+      store(bnx);
       if (zs + 3 <= z1) fetch(zs + 3);
     }
+    __syncthreads();
     if (out_ok) {
       const int e00 = oy * PX + ox;
       const T pd[3] = {pd0, pd1, pd2};
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const T v = force[c * 4 + 3][e00] + force[c * 4 + 2][e00 + 1] +
-                    force[c * 4 + 1][e00 + PX] + force[c * 4 + 0][e00 + PX + 1];
+        const T v = own[c] + force[fb][c * 3 + 2][e00 + 1] + force[fb][c * 3 + 1][e00 + PX] +
+                    force[fb][c * 3 + 0][e00 + PX + 1];
         qb[c * N + o] = v;
         dot += (double)pd[c] * (double)v;
       }
     }
+    const int t = blo;
+    blo = bhi;
+    bhi = bnx;
+    bnx = t;
   }
   if (pq_part) {
     const double tot = block_sum_k(dot, red);
