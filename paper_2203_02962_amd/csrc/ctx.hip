@@ -182,6 +182,12 @@ struct fh_ctx {
   int nms = 1;
   bool use_graph = false;
   bool own_stream = false;
+  // single solves: one PCG iteration replayed from a hipGraph on a private
+  // stream (the caller's stream may be the null stream, which cannot be
+  // captured), forked from and joined back to `stream` with the two events
+  bool graph = false;  // FH_FLAG_GRAPH of the current solve
+  hipStream_t gstream = nullptr;
+  hipEvent_t gfork = nullptr, gjoin = nullptr;
   uint8_t* phase_pack = nullptr;
   std::vector<std::vector<double>> cmean_ms;
   std::vector<unsigned long long> phase_counts;  // voxels per phase (compute_mean)
@@ -908,6 +914,49 @@ void kt_collect(fh_ctx* c);
     kt_end(c, _slot);                    \
   } while (0)
 
+// Launch counts of one replayed iteration, per kernel class (the replay
+// records no events, so kt_begin does not see its launches).
+void kt_count_iteration(fh_ctx* c) {
+  for (int cls : {FH_K_OPERATOR, FH_K_XFWD, FH_K_YFWD, FH_K_ZSOLVE, FH_K_YINV, FH_K_XINV})
+    c->kt.issued[cls] += 1;
+  c->kt.issued[FH_K_SCALAR] += 2;
+}
+
+// Moves a context's work to its private stream for the PCG loop of a single
+// solve and back: an event on the caller's stream orders the loop after the
+// set-up, an event on the private stream orders the caller's later work
+// after the loop.  The private stream and events are created on first use
+// and kept until fh_destroy.
+struct GraphStream {
+  fh_ctx* c;
+  hipStream_t saved = nullptr;
+  bool on = false;
+  explicit GraphStream(fh_ctx* cc) : c(cc) {}
+  int fork() {
+    if (!c->gstream) {
+      if (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess) {
+        c->gstream = nullptr;
+        return fail(c, FH_EDEVICE, "hipStreamCreate for graph replay failed");
+      }
+      if (hipEventCreateWithFlags(&c->gfork, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&c->gjoin, hipEventDisableTiming) != hipSuccess)
+        return fail(c, FH_EDEVICE, "hipEventCreate for graph replay failed");
+    }
+    HIPCHK(c, hipEventRecord(c->gfork, c->stream));
+    HIPCHK(c, hipStreamWaitEvent(c->gstream, c->gfork, 0));
+    saved = c->stream;
+    c->stream = c->gstream;
+    on = true;
+    return FH_OK;
+  }
+  ~GraphStream() {
+    if (!on) return;
+    hipEventRecord(c->gjoin, c->gstream);
+    hipStreamWaitEvent(saved, c->gjoin, 0);
+    c->stream = saved;
+  }
+};
+
 // ------------------------------------------------------------------ PCG
 // One PCG solve per load case on buffers of type T (double, or float for the
 // inner solves of the refinement).  The right-hand side must already be in
@@ -950,6 +999,12 @@ int pcg_run(fh_ctx* c, int nload, const PcgBufs<T>& bf, double eta, int itmax, i
     hs[j].eta2 = eta2v ? (*eta2v)[j] : eta * eta;
     hs[j].itmax = itmaxv ? std::max(1, (*itmaxv)[j]) : itmax;
   }
+  const bool single_graph = !c->use_graph && c->graph;
+  GraphStream gs(c);
+  if (single_graph) {
+    const int rc = gs.fork();
+    if (rc) return rc;
+  }
   HIPCHK(c, hipMemcpyAsync(L.st, hs.data(), sizeof(fh::PcgState) * nload, hipMemcpyHostToDevice,
                            c->stream));
   if (zero_x) HIPCHK(c, fh::launch_fill<T>(bf.x, T(0), F * nload, c->stream));
@@ -986,11 +1041,14 @@ int pcg_run(fh_ctx* c, int nload, const PcgBufs<T>& bf, double eta, int itmax, i
                                                  bf.x, bf.p, F, nload, L.st, c->stream)));
       return FH_OK;
   };
-  // Batched solves capture one iteration (all kernels, all systems) in a
-  // hipGraph and replay it; kernels read everything that changes from the
-  // device-resident PCG state, so the same graph serves every iteration.
+  // One iteration (all kernels, all load cases, all systems of a batch) is
+  // captured in a hipGraph and replayed; kernels read everything that
+  // changes from the device-resident PCG state, so the same graph serves
+  // every iteration.  Batched solves capture on their group's own stream;
+  // single solves with FH_FLAG_GRAPH move to the context's private stream
+  // for the loop.
   hipGraphExec_t exec = nullptr;
-  if (c->use_graph) {
+  if (c->use_graph || single_graph) {
     hipGraph_t graph = nullptr;
     const bool kt_was = c->kt.on;
     c->kt.on = false;
@@ -1023,13 +1081,15 @@ int pcg_run(fh_ctx* c, int nload, const PcgBufs<T>& bf, double eta, int itmax, i
   std::vector<int> prev_iter(nload, 0);
   while (true) {
     for (int k = 0; k < window && done_iters < cap; ++k, ++done_iters) {
-      if (exec) {
+      // sampled iterations sit mid-way between the 16-iteration status
+      // polls: the iteration right after a poll starts on an idle GPU, and
+      // its first event pair would include the host's launch latency
+      const bool sampled = done_iters % c->kt.period == c->kt.period / 2;
+      if (exec && !(c->kt.on && sampled)) {
         HIPCHK(c, hipGraphLaunch(exec, c->stream));
+        if (c->kt.on) kt_count_iteration(c);
       } else {
-        // sampled iterations sit mid-way between the 16-iteration status
-        // polls: the iteration right after a poll starts on an idle GPU, and
-        // its first event pair would include the host's launch latency
-        c->kt.sample = done_iters % c->kt.period == c->kt.period / 2;
+        c->kt.sample = sampled;
         c->kt.cur_iter = done_iters;
         const int rc = one_iteration();
         c->kt.sample = true;
@@ -1815,6 +1875,12 @@ void fh_destroy(fh_ctx* c) {
   if (c->host_pinned) hipHostFree(c->host_pinned);
   for (hipEvent_t e : c->kt.ev) hipEventDestroy(e);
   hipFree(c->phase_pack);
+  if (c->gstream) {
+    hipStreamSynchronize(c->gstream);
+    hipStreamDestroy(c->gstream);
+  }
+  if (c->gfork) hipEventDestroy(c->gfork);
+  if (c->gjoin) hipEventDestroy(c->gjoin);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -2051,6 +2117,7 @@ int fh_solve(fh_ctx* c, const fh_opts* opt, fh_stats* st) {
   c->kt.on = (o.flags & FH_FLAG_TIME_KERNELS) != 0;
   c->kt.period = (o.flags & FH_FLAG_TIME_SAMPLED) ? 8 : 1;
   c->kt.sample = true;
+  c->graph = (o.flags & FH_FLAG_GRAPH) != 0;
   if (o.flags & FH_FLAG_REBUILD) c->symbol_ok = c->rhs_ok = false;
   c->kt.used = 0;
   c->kt.timed_iters.clear();

@@ -27,6 +27,7 @@ FH_FLAG_REBUILD = 2
 FH_FLAG_WARM_START = 4
 FH_FLAG_TIME_SAMPLED = 8
 FH_FLAG_BATCH_SERIAL = 16
+FH_FLAG_GRAPH = 32
 FH_REF_MEAN, FH_REF_IDENTITY, FH_REF_BEST = 0, 1, 2
 FH_MAX_INCREMENTS, FH_MAX_NEWTON = 64, 64
 FH_NEWTON_REF_TANGENT, FH_NEWTON_REF_ELASTIC = 0, 1
@@ -397,10 +398,12 @@ class Context:
 
     def solve(self, eta=1e-10, itmax=10000, precision=FH_FP64, poll=0, eta_inner=0.0,
               time_kernels=False, rebuild=False, warm_start=False, guess_dev=None,
-              time_sampled=False):
+              time_sampled=False, graph=False):
+        """graph: replay one captured PCG iteration from a hipGraph
+        (FH_FLAG_GRAPH) instead of launching every kernel from the host."""
         flags = (FH_FLAG_TIME_KERNELS if time_kernels else 0) | \
             (FH_FLAG_REBUILD if rebuild else 0) | (FH_FLAG_WARM_START if warm_start else 0) | \
-            (FH_FLAG_TIME_SAMPLED if time_sampled else 0)
+            (FH_FLAG_TIME_SAMPLED if time_sampled else 0) | (FH_FLAG_GRAPH if graph else 0)
         o = self.opts(eta, itmax, precision, poll, eta_inner, flags)
         if guess_dev is not None:
             o.guess_dev = _tptr(guess_dev, _f64(), self.nload * self.nd * self.N,

@@ -275,6 +275,33 @@ def test_solve_is_bitwise_deterministic(fh):
     assert all(np.array_equal(a, b) for a, b in zip(u1, u2))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_graph_replay_matches_host_launches(fh, precision):
+    """With FH_FLAG_GRAPH a single solve replays one captured PCG iteration
+    from a hipGraph on the context's private stream; by default the host
+    launches every kernel.  The kernels and their order are the same, so
+    C_hom, the fluctuations, the iteration counts and the residual
+    histories are bit for bit equal, over repeated solves in both orders."""
+    say("graph replay vs eager", precision)
+    from paper_2203_02962_amd.runner import fluctuations
+    prec = fh.FH_FP64 if precision == "fp64" else fh.FH_FP32_REFINED
+    wl, prob = _spheres_case(16, (2.0, 3.5), 100.0, 3)
+    ctx = _ctx(fh, wl)
+    runs = []
+    for graph in (False, True, True, False):
+        rc, st = ctx.solve(eta=1e-10, precision=prec, graph=graph, rebuild=True)
+        assert rc == 0
+        runs.append((st["iterations"], ctx.get_homogenized(), fluctuations(ctx),
+                     [ctx.get_history(j) for j in range(6)]))
+    it0, H0, u0, h0 = runs[0]
+    for it, H, u, h in runs[1:]:
+        assert it == it0
+        assert np.array_equal(H, H0)
+        assert all(np.array_equal(a, b) for a, b in zip(u, u0))
+        assert all(np.array_equal(a, b) for a, b in zip(h, h0))
+    ctx.close()
+
+
 def test_kernel_timing_counts(fh):
     """Event timing of every launch, or of every 8th PCG iteration: the
     launch counts, timed counts and totals are consistent, and timing does
@@ -286,6 +313,12 @@ def test_kernel_timing_counts(fh):
     H0 = ctx.get_homogenized()
     rc1, st1 = ctx.solve(eta=1e-10, time_kernels=True, rebuild=True)
     rc2, st2 = ctx.solve(eta=1e-10, time_kernels=True, time_sampled=True, rebuild=True)
+    # graph replay between the sampled iterations: the same counts
+    rc3, st3 = ctx.solve(eta=1e-10, time_kernels=True, time_sampled=True, rebuild=True,
+                         graph=True)
+    assert rc3 == 0 and np.array_equal(ctx.get_homogenized(), H0)
+    for key in ("iterations", "kernel_issued", "kernel_launches", "kernel_units"):
+        assert st3[key] == st2[key], key
     assert rc0 == rc1 == rc2 == 0
     assert st0["iterations"] == st1["iterations"] == st2["iterations"]
     assert np.array_equal(ctx.get_homogenized(), H0)
