@@ -25,6 +25,8 @@
 // stage); twiddles come from a per-length table staged in LDS.
 #include "fh_internal.h"
 
+#include <type_traits>
+
 namespace fh {
 
 constexpr int kThreads = 256;
@@ -122,11 +124,11 @@ __device__ __forceinline__ void dft_small(cplx<T>* x, int s) {
 // FP32 lines (8-byte complex values) keep the plain layout, stride n + 1,
 // which measured faster for them.
 template <typename T>
-__host__ __device__ __forceinline__ int sw(int e) {
+__host__ __device__ constexpr int sw(int e) {
   return sizeof(T) == 8 ? e + (e >> 3) : e;
 }
 template <typename T>
-__host__ __device__ __forceinline__ int lds_stride(int n) {
+__host__ __device__ constexpr int lds_stride(int n) {
   return sizeof(T) == 8 ? ((n + (n >> 3) + 1) | 1) : n + 1;
 }
 
@@ -159,12 +161,17 @@ constexpr int kMaxPts = 2048;
 // src(line, e) gives element e of a line and sink(line, e, v) stores one;
 // with in_place false the inputs come from another buffer and the barrier
 // between reads and writes is skipped.  In the first stage (L = 1) every
-// twiddle is 1 and the table is not read.
-template <typename T, int R, typename Src, typename Sink>
+// twiddle is 1 and the table is not read.  NC and LC, when nonzero, are the
+// line length and the stride L known at compile time (power-of-two plans):
+// every index then comes from shifts and masks and the element offsets of a
+// butterfly fold into the addresses.
+template <typename T, int R, int NC = 0, int LC = 0, typename Src, typename Sink>
 __device__ __forceinline__ void stockham_stage_io(const Src& src, const Sink& sink, bool in_place,
-                                                  int n, int nlines, int L, const cplx<T>* tw,
-                                                  int sign) {
+                                                  int n_rt, int nlines, int L_rt,
+                                                  const cplx<T>* tw, int sign) {
   constexpr int MAXIT = (kMaxPts / R + kThreads - 1) / kThreads;
+  const int n = NC ? NC : n_rt;
+  const int L = LC ? LC : L_rt;
   const int m = n / R;
   const int items = nlines * m;
   const int twstep = n / (L * R);
@@ -176,23 +183,31 @@ __device__ __forceinline__ void stockham_stage_io(const Src& src, const Sink& si
     const int it = threadIdx.x + k * kThreads;
     dst[k] = -1;
     if (it < items) {
-      const int line = dm.q(it);
-      const int j = dm.r(it, line);
-      const int jl = dL.q(j);
-      const int kk = dL.r(j, jl);
+      int line, j, jl, kk;
+      if constexpr (NC > 0 && LC > 0) {
+        line = it / (NC / R);
+        j = it % (NC / R);
+        jl = j / LC;
+        kk = j % LC;
+      } else {
+        line = dm.q(it);
+        j = dm.r(it, line);
+        jl = dL.q(j);
+        kk = dL.r(j, jl);
+      }
 #pragma unroll
       for (int t = 0; t < R; ++t) {
         cplx<T> a = src(line, j + t * m);
         if (t > 0 && L > 1) {
           // t*kk < R*L, so the index stays below n
-          cplx<T> w = tw[t * __mul24(kk, twstep)];
+          cplx<T> w = tw[(NC > 0 && LC > 0) ? t * kk * (NC / (LC * R)) : t * __mul24(kk, twstep)];
           if (sign > 0) w.im = -w.im;
           a = cmul(a, w);
         }
         v[k][t] = a;
       }
       dst[k] = line;
-      de[k] = __mul24(jl, L * R) + kk;
+      de[k] = (NC > 0 && LC > 0) ? jl * (LC * R) + kk : __mul24(jl, L * R) + kk;
     }
   }
   if (in_place) __syncthreads();
@@ -264,6 +279,44 @@ __device__ cplx<T>* fft_lines(cplx<T>* a, const AxisPlan& plan, int nlines, cons
                               int sign) {
   fft_stages<T, P3>(a, plan, false, 0, plan.nstage, 1, nlines, tw, sign);
   return a;
+}
+
+// Radix plan of a power-of-two length as the host builds it: radix 8 while
+// it divides, then 4, then 2.
+__host__ __device__ constexpr int p2_nstage(int n) {
+  int s = 0;
+  while (n % 8 == 0) { n /= 8; ++s; }
+  while (n % 4 == 0) { n /= 4; ++s; }
+  while (n % 2 == 0) { n /= 2; ++s; }
+  return s;
+}
+__host__ __device__ constexpr int p2_radix(int n, int st) {
+  int s = 0;
+  while (n % 8 == 0) { if (s++ == st) return 8; n /= 8; }
+  while (n % 4 == 0) { if (s++ == st) return 4; n /= 4; }
+  while (n % 2 == 0) { if (s++ == st) return 2; n /= 2; }
+  return 1;
+}
+__host__ __device__ constexpr unsigned p2_code(int n) {
+  unsigned c = 0;
+  for (int st = 0; st < p2_nstage(n); ++st) c |= (unsigned)p2_radix(n, st) << (4 * st);
+  return c;
+}
+
+// In-place LDS stages [S, SEND) of the compile-time plan of N, radices in
+// plan order or reversed; L is the product of the radices before stage S.
+template <typename T, int N, int S, int SEND, bool REV, int L>
+__device__ __forceinline__ void stages_ct(cplx<T>* a, int nlines, const cplx<T>* tw, int sign) {
+  if constexpr (S < SEND) {
+    constexpr int NS = p2_nstage(N);
+    constexpr int R = p2_radix(N, REV ? NS - 1 - S : S);
+    constexpr int ls = lds_stride<T>(N);
+    stockham_stage_io<T, R, N, L>(
+        [&](int line, int e) { return a[line * ls + sw<T>(e)]; },
+        [&](int line, int e, cplx<T> v) { a[line * ls + sw<T>(e)] = v; }, true, N, nlines, L,
+        tw, sign);
+    stages_ct<T, N, S + 1, SEND, REV, L * R>(a, nlines, tw, sign);
+  }
 }
 
 template <typename T>
@@ -423,11 +476,12 @@ __global__ void __launch_bounds__(kThreads) k_yfwd(Grid g, AxisPlan py, const cp
 // needs exactly those two, so only the three components of a frequency pair
 // have to meet in one thread: one LDS round trip and the solve pass are
 // saved.
-template <typename T>
-__device__ double zpass_fused_mid(cplx<T>* a, int n, int ls, int cls, int kyb, int ky0, int ny,
+template <typename T, int NC = 0>
+__device__ double zpass_fused_mid(cplx<T>* a, int n_rt, int ls, int cls, int kyb, int ky0, int ny,
                                   int nz, int kx, const cplx<T>* tw, const T* kplus,
                                   long long nfreq, double wgt) {
   constexpr int MAXIT = (2048 / 6 + kThreads - 1) / kThreads;  // kyb * n/2 <= 2048 / 6
+  const int n = NC ? NC : n_rt;
   const int m = n / 2;
   const int items = kyb * m;
   const UDiv dm(m);
@@ -438,7 +492,8 @@ __device__ double zpass_fused_mid(cplx<T>* a, int n, int ls, int cls, int kyb, i
     const int it = threadIdx.x + k * kThreads;
     kyl_[k] = -1;
     if (it < items) {
-      const int kyl = dm.q(it), j = dm.r(it, kyl);
+      const int kyl = NC ? it / (NC / 2) : dm.q(it);
+      const int j = NC ? it % (NC / 2) : dm.r(it, kyl);
       const cplx<T> w = tw[j];  // forward twiddle of the last stage: L = n/2, t = 1
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -555,7 +610,9 @@ __device__ double zpass_fused_mid_scalar(cplx<T>* a, int n, int ls, int kyb, int
 // Power-of-two lengths run four waves per SIMD (at most 128 VGPRs, 7 spilled
 // in FP64): 212 -> 192 us per 6-load launch at 128^3; with radix-3 stages
 // that budget would spill 44 registers, so those keep the compiler's choice.
-template <typename T, bool P3>
+// NZ > 0: the z length, a power of two whose plan is p2_code(NZ), known at
+// compile time (the solve stages then use the compile-time stage code).
+template <typename T, bool P3, int NZ = 0>
 __global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan pz, const cplx<double>* twz,
                                                    int mode, int kyb, cplx<T>* B,
                                                    long long sstride, const T* kplus,
@@ -576,7 +633,7 @@ __global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan
   const int active = load_status(st, ld) == ST_ACTIVE;
   if (!active) return;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int ny = g.ny, nz = g.nz, nxh = g.nxh, nd = g.nd;
+  const int ny = g.ny, nz = NZ ? NZ : g.nz, nxh = g.nxh, nd = g.nd;
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* a = tw + nz;
   load_twiddles(tw, twz, nz);
@@ -628,21 +685,41 @@ __global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan
   if (fused) {
     const long long nfreq = (long long)nxh * ny * nz;
     const double wgt = (kx == 0 || (2 * kx == g.nx)) ? 1.0 : 2.0;
-    stage_io_any<T, P3>(R0, gsrc, lsink, false, nz, nd * kyb, 1, tw, -1);
-    fft_stages<T, P3>(a, pz, false, 1, pz.nstage - 1, R0, nd * kyb, tw, -1);
-    if (nd == 3)
-      part = zpass_fused_mid<T>(a, nz, ls, cls, kyb, ky0, ny, nz, kx, tw, kplus, nfreq, wgt);
-    else if (last_radix == 2)
-      part = zpass_fused_mid_scalar<T, 2>(a, nz, ls, kyb, ky0, ny, nz, kx, tw, kplus, wgt);
-    else if (last_radix == 4)
-      part = zpass_fused_mid_scalar<T, 4>(a, nz, ls, kyb, ky0, ny, nz, kx, tw, kplus, wgt);
-    else
-      part = zpass_fused_mid_scalar<T, 8>(a, nz, ls, kyb, ky0, ny, nz, kx, tw, kplus, wgt);
-    fft_stages<T, P3>(a, pz, true, 1, pz.nstage - 1, last_radix, nd * kyb, tw, +1);
-    stage_io_any<T, P3>(R0, lsrc, gsink, false, nz, nd * kyb, nz / R0, tw, +1);
+    if constexpr (NZ > 0) {
+      constexpr int NS = p2_nstage(NZ), R0c = p2_radix(NZ, 0), RLc = p2_radix(NZ, NS - 1);
+      stockham_stage_io<T, R0c, NZ, 1>(gsrc, lsink, false, NZ, nd * kyb, 1, tw, -1);
+      stages_ct<T, NZ, 1, NS - 1, false, R0c>(a, nd * kyb, tw, -1);
+      if (nd == 3)
+        part = zpass_fused_mid<T, NZ>(a, NZ, ls, cls, kyb, ky0, ny, nz, kx, tw, kplus, nfreq,
+                                      wgt);
+      else
+        part = zpass_fused_mid_scalar<T, RLc>(a, NZ, ls, kyb, ky0, ny, nz, kx, tw, kplus, wgt);
+      stages_ct<T, NZ, 1, NS - 1, true, RLc>(a, nd * kyb, tw, +1);
+      stockham_stage_io<T, R0c, NZ, NZ / R0c>(lsrc, gsink, false, NZ, nd * kyb, NZ / R0c, tw,
+                                              +1);
+    } else {
+      stage_io_any<T, P3>(R0, gsrc, lsink, false, nz, nd * kyb, 1, tw, -1);
+      fft_stages<T, P3>(a, pz, false, 1, pz.nstage - 1, R0, nd * kyb, tw, -1);
+      if (nd == 3)
+        part = zpass_fused_mid<T>(a, nz, ls, cls, kyb, ky0, ny, nz, kx, tw, kplus, nfreq, wgt);
+      else if (last_radix == 2)
+        part = zpass_fused_mid_scalar<T, 2>(a, nz, ls, kyb, ky0, ny, nz, kx, tw, kplus, wgt);
+      else if (last_radix == 4)
+        part = zpass_fused_mid_scalar<T, 4>(a, nz, ls, kyb, ky0, ny, nz, kx, tw, kplus, wgt);
+      else
+        part = zpass_fused_mid_scalar<T, 8>(a, nz, ls, kyb, ky0, ny, nz, kx, tw, kplus, wgt);
+      fft_stages<T, P3>(a, pz, true, 1, pz.nstage - 1, last_radix, nd * kyb, tw, +1);
+      stage_io_any<T, P3>(R0, lsrc, gsink, false, nz, nd * kyb, nz / R0, tw, +1);
+    }
   } else if (direct) {
-    stage_io_any<T, P3>(R0, gsrc, lsink, false, nz, nd * kyb, 1, tw, -1);
-    fft_stages<T, P3>(a, pz, false, 1, pz.nstage, R0, nd * kyb, tw, -1);
+    if constexpr (NZ > 0) {
+      constexpr int NS = p2_nstage(NZ), R0c = p2_radix(NZ, 0);
+      stockham_stage_io<T, R0c, NZ, 1>(gsrc, lsink, false, NZ, nd * kyb, 1, tw, -1);
+      stages_ct<T, NZ, 1, NS, false, R0c>(a, nd * kyb, tw, -1);
+    } else {
+      stage_io_any<T, P3>(R0, gsrc, lsink, false, nz, nd * kyb, 1, tw, -1);
+      fft_stages<T, P3>(a, pz, false, 1, pz.nstage, R0, nd * kyb, tw, -1);
+    }
   } else {
     res = fft_lines<T, P3>(a, pz, nd * kyb, tw, -1);
   }
@@ -651,7 +728,8 @@ __global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan
     const double wgt = (kx == 0 || (2 * kx == g.nx)) ? 1.0 : 2.0;
     const UDiv dnz(nz);
     for (int idx0 = threadIdx.x; idx0 < per; idx0 += blockDim.x) {
-      const int kyl = dnz.q(idx0), kz = dnz.r(idx0, kyl), ky = ky0 + kyl;
+      const int kyl = NZ ? idx0 / NZ : dnz.q(idx0);
+      const int kz = NZ ? idx0 % NZ : dnz.r(idx0, kyl), ky = ky0 + kyl;
       if (ky >= ny) continue;
       const int idx = kyl * ls + sw<T>(kz);
       const long long f = ((long long)kx * ny + ky) * nz + kz;
@@ -701,9 +779,16 @@ __global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan
       }
     }
     __syncthreads();
-    const int RL = (pz.code >> (4 * (pz.nstage - 1))) & 15u;
-    fft_stages<T, P3>(a, pz, false, 0, pz.nstage - 1, 1, nd * kyb, tw, +1);
-    stage_io_any<T, P3>(RL, lsrc, gsink, false, nz, nd * kyb, nz / RL, tw, +1);
+    if constexpr (NZ > 0) {
+      constexpr int NS = p2_nstage(NZ), RLc = p2_radix(NZ, NS - 1);
+      stages_ct<T, NZ, 0, NS - 1, false, 1>(a, nd * kyb, tw, +1);
+      stockham_stage_io<T, RLc, NZ, NZ / RLc>(lsrc, gsink, false, NZ, nd * kyb, NZ / RLc, tw,
+                                              +1);
+    } else {
+      const int RL = (pz.code >> (4 * (pz.nstage - 1))) & 15u;
+      fft_stages<T, P3>(a, pz, false, 0, pz.nstage - 1, 1, nd * kyb, tw, +1);
+      stage_io_any<T, P3>(RL, lsrc, gsink, false, nz, nd * kyb, nz / RL, tw, +1);
+    }
   }
   if (!direct) {
     for (int idx = threadIdx.x; idx < nd * per; idx += blockDim.x) {
@@ -1037,15 +1122,24 @@ hipError_t launch_zpass(const Grid& g, const AxisPlan& pz, const cplx<double>* t
   dim3 grid((lg_n + 7) / 8 * 8, 1, nload);
   if (nblocks_out) *nblocks_out = lg_n;
   size_t lds = sizeof(cplx<T>) * (size_t)(g.nz + g.nd * kyb * lds_stride<T>(g.nz));
-  if (lds > 65536)
-    hipFuncSetAttribute(P3K ? (const void*)k_zpass<T, true> : (const void*)k_zpass<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
-  if (P3K)
-    hipLaunchKernelGGL((k_zpass<T, true>), grid, dim3(kThreads), lds, s, g, pz, twz, mode, kyb, B, sstride,
-                     kplus, st, rz_part);
-  else
-    hipLaunchKernelGGL((k_zpass<T, false>), grid, dim3(kThreads), lds, s, g, pz, twz, mode, kyb, B, sstride,
-                     kplus, st, rz_part);
+  auto go = [&](auto kern) {
+    if (lds > 65536)
+      hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, s, g, pz, twz, mode, kyb, B, sstride,
+                       kplus, st, rz_part);
+  };
+  // power-of-two lengths with the host's plan: the compile-time stage code
+  auto ct = [&](auto nzc) {
+    constexpr int NZ = decltype(nzc)::value;
+    return g.nz == NZ && pz.n == NZ && pz.nstage == p2_nstage(NZ) && pz.code == p2_code(NZ);
+  };
+  if (P3K) go(k_zpass<T, true>);
+  else if (ct(std::integral_constant<int, 128>{})) go(k_zpass<T, false, 128>);
+  else if (ct(std::integral_constant<int, 64>{})) go(k_zpass<T, false, 64>);
+  else if (ct(std::integral_constant<int, 256>{})) go(k_zpass<T, false, 256>);
+  else if (ct(std::integral_constant<int, 32>{})) go(k_zpass<T, false, 32>);
+  else if (ct(std::integral_constant<int, 16>{})) go(k_zpass<T, false, 16>);
+  else go(k_zpass<T, false>);
   return hipGetLastError();
 }
 
