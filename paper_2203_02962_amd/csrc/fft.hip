@@ -367,7 +367,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // Five waves per SIMD (at most 96 VGPRs): measured 255 -> 231 us per 6-load
 // launch at 128^3 in FP64 (the other passes are slower that way).  FP64 with
 // radix-3 stages would spill 27 registers in that budget and keeps four.
-template <typename T, bool P3, int kRows>
+template <typename T, bool P3, int kRows, int NX = 0>
 __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && P3) ? 4 : 5) k_xfwd(Grid g, AxisPlan px, const cplx<double>* twx,
                                                   int mode, T* r, long long rstride, const T* q,
                                                   long long qstride, cplx<T>* A,
@@ -375,7 +375,7 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && P3) ? 4 : 5) k_xf
   const int ld = blockIdx.z / g.nd, c = blockIdx.z % g.nd;
   if (load_status(st, ld) != ST_ACTIVE) return;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int nx = g.nx, ny = g.ny, nxh = g.nxh;
+  const int nx = NX ? NX : g.nx, ny = g.ny, nxh = g.nxh;
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* a = tw + nx;
   load_twiddles(tw, twx, nx);
@@ -406,7 +406,11 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && P3) ? 4 : 5) k_xf
         if (row & 1) d.im = v; else d.re = v;
       });
   __syncthreads();
-  cplx<T>* res = fft_lines<T, P3>(a, px, kRows / 2, tw, -1);
+  cplx<T>* res = a;
+  if constexpr (NX > 0)
+    stages_ct<T, NX, 0, p2_nstage(NX), false, 1>(a, kRows / 2, tw, -1);
+  else
+    res = fft_lines<T, P3>(a, px, kRows / 2, tw, -1);
   const long long abase = (long long)ld * sstride + ((long long)c * g.nz + z) * nxh * ny;
   for (int idx = threadIdx.x; idx < kRows * nxh; idx += blockDim.x) {
     const int yl = idx % kRows, kx = idx / kRows, y = y0 + yl;
@@ -427,15 +431,16 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && P3) ? 4 : 5) k_xf
 }
 
 // ------------------------------------------------------------- y forward
-// grid (ceil(nz/zb), nxh, nload*nd); zb lines per block, zb*ny <= kMaxPts
-template <typename T, bool P3>
+// grid (ceil(nz/zb), nxh, nload*nd); zb lines per block, zb*ny <= kMaxPts.
+// NY > 0: power-of-two length with its compile-time plan (as in k_zpass).
+template <typename T, bool P3, int NY = 0>
 __global__ void __launch_bounds__(kThreads) k_yfwd(Grid g, AxisPlan py, const cplx<double>* twy,
                                                   int zb, const cplx<T>* A, cplx<T>* B,
                                                   long long sstride, const PcgState* st) {
   const int ld = blockIdx.z / g.nd, c = blockIdx.z % g.nd;
   if (load_status(st, ld) != ST_ACTIVE) return;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int ny = g.ny, nz = g.nz, nxh = g.nxh;
+  const int ny = NY ? NY : g.ny, nz = g.nz, nxh = g.nxh;
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* a = tw + ny;
   load_twiddles(tw, twy, ny);
@@ -451,7 +456,11 @@ __global__ void __launch_bounds__(kThreads) k_yfwd(Grid g, AxisPlan py, const cp
   };
   auto lsink = [&](int l, int y, cplx<T> v) { a[__mul24(l, ls) + sw<T>(y)] = v; };
   cplx<T>* res = a;
-  if (py.nstage >= 1) {
+  if constexpr (NY > 0) {
+    constexpr int NS = p2_nstage(NY), R0c = p2_radix(NY, 0);
+    stockham_stage_io<T, R0c, NY, 1>(gsrc, lsink, false, NY, zb, 1, tw, -1);
+    stages_ct<T, NY, 1, NS, false, R0c>(a, zb, tw, -1);
+  } else if (py.nstage >= 1) {
     const int R0 = py.code & 15u;
     stage_io_any<T, P3>(R0, gsrc, lsink, false, ny, zb, 1, tw, -1);
     fft_stages<T, P3>(a, py, false, 1, py.nstage, R0, zb, tw, -1);
@@ -807,14 +816,14 @@ __global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan
 }
 
 // ------------------------------------------------------------- y inverse
-template <typename T, bool P3>
+template <typename T, bool P3, int NY = 0>
 __global__ void __launch_bounds__(kThreads) k_yinv(Grid g, AxisPlan py, const cplx<double>* twy,
                                                   int zb, const cplx<T>* B, cplx<T>* A,
                                                   long long sstride, const PcgState* st) {
   const int ld = blockIdx.z / g.nd, c = blockIdx.z % g.nd;
   if (load_status(st, ld) != ST_ACTIVE) return;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int ny = g.ny, nz = g.nz, nxh = g.nxh;
+  const int ny = NY ? NY : g.ny, nz = g.nz, nxh = g.nxh;
   cplx<T>* tw = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* a = tw + ny;
   load_twiddles(tw, twy, ny);
@@ -842,7 +851,11 @@ __global__ void __launch_bounds__(kThreads) k_yinv(Grid g, AxisPlan py, const cp
     const int z = z0 + zl;
     if (z < nz) A[base + (((long long)c * nz + z) * nxh + kx) * ny + y] = v;
   };
-  if (py.nstage >= 1) {
+  if constexpr (NY > 0) {
+    constexpr int NS = p2_nstage(NY), RLc = p2_radix(NY, NS - 1);
+    stages_ct<T, NY, 0, NS - 1, false, 1>(a, zb, tw, +1);
+    stockham_stage_io<T, RLc, NY, NY / RLc>(lsrc, gsink, false, NY, zb, NY / RLc, tw, +1);
+  } else if (py.nstage >= 1) {
     const int RL = (py.code >> (4 * (py.nstage - 1))) & 15u;
     fft_stages<T, P3>(a, py, false, 0, py.nstage - 1, 1, zb, tw, +1);
     stage_io_any<T, P3>(RL, lsrc, gsink, false, ny, zb, ny / RL, tw, +1);
@@ -854,14 +867,14 @@ __global__ void __launch_bounds__(kThreads) k_yinv(Grid g, AxisPlan py, const cp
 
 // ------------------------------------------------------------- x inverse
 // grid (ceil(ny/16), nz, nload*nd).  LDS: tw[nx], a[8 nx], S[16 nxh].
-template <typename T, bool P3, int kRows>
+template <typename T, bool P3, int kRows, int NX = 0>
 __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cplx<double>* twx,
                                                   int mode, const cplx<T>* A, long long sstride,
                                                   T* out, T* x, T* p, long long fstride,
                                                   const PcgState* st) {
   const int ld = blockIdx.z / g.nd, c = blockIdx.z % g.nd;
   const int status = load_status(st, ld);
-  const int nx = g.nx, ny = g.ny, nxh = g.nxh;
+  const int nx = NX ? NX : g.nx, ny = g.ny, nxh = g.nxh;
   const int y0 = blockIdx.x * kRows, z = blockIdx.y;
   const long long fbase = (long long)ld * fstride + ((long long)c * g.nz + z) * ny * nx;
   const UDiv dnx(nx);
@@ -934,12 +947,20 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
     }
     return {xa.re - xb.im, xa.im + xb.re};
   };
-  const int R0 = px.code & 15u;
-  if (R0 == 8) stockham_stage_from<T, 8>(packed, false, a, nx, lsx, kRows / 2, 1, tw, +1);
-  else if (R0 == 4) stockham_stage_from<T, 4>(packed, false, a, nx, lsx, kRows / 2, 1, tw, +1);
-  else if (R0 == 2) stockham_stage_from<T, 2>(packed, false, a, nx, lsx, kRows / 2, 1, tw, +1);
-  else if constexpr (P3) stockham_stage_from<T, 3>(packed, false, a, nx, lsx, kRows / 2, 1, tw, +1);
-  fft_stages<T, P3>(a, px, false, 1, px.nstage, R0, kRows / 2, tw, +1);
+  if constexpr (NX > 0) {
+    constexpr int R0c = p2_radix(NX, 0);
+    stockham_stage_io<T, R0c, NX, 1>(
+        packed, [&](int line, int e, cplx<T> v) { a[line * lsx + sw<T>(e)] = v; }, false, NX,
+        kRows / 2, 1, tw, +1);
+    stages_ct<T, NX, 1, p2_nstage(NX), false, R0c>(a, kRows / 2, tw, +1);
+  } else {
+    const int R0 = px.code & 15u;
+    if (R0 == 8) stockham_stage_from<T, 8>(packed, false, a, nx, lsx, kRows / 2, 1, tw, +1);
+    else if (R0 == 4) stockham_stage_from<T, 4>(packed, false, a, nx, lsx, kRows / 2, 1, tw, +1);
+    else if (R0 == 2) stockham_stage_from<T, 2>(packed, false, a, nx, lsx, kRows / 2, 1, tw, +1);
+    else if constexpr (P3) stockham_stage_from<T, 3>(packed, false, a, nx, lsx, kRows / 2, 1, tw, +1);
+    fft_stages<T, P3>(a, px, false, 1, px.nstage, R0, kRows / 2, tw, +1);
+  }
   cplx<T>* res = a;
   const T alpha = (mode == XI_PCG) ? T(st[ld].alpha) : T(0);
   const T beta = (mode == XI_PCG) ? T(st[ld].beta) : T(0);
@@ -1044,6 +1065,13 @@ __global__ void k_cast_symbol(long long n, const double* src, float* dst) {
 }
 
 // ------------------------------------------------------------ launchers
+// The axis of length N runs with the compile-time plan when the host's plan
+// is exactly p2_code(N).
+template <int N>
+static bool ct_plan(const AxisPlan& p, int n) {
+  return n == N && p.n == N && p.nstage == p2_nstage(N) && p.code == p2_code(N);
+}
+
 template <typename T>
 hipError_t launch_xfwd(const Grid& g, const AxisPlan& px, const cplx<double>* twx, int mode,
                        T* r, long long rstride, const T* q, long long qstride, cplx<T>* A,
@@ -1059,11 +1087,22 @@ hipError_t launch_xfwd(const Grid& g, const AxisPlan& px, const cplx<double>* tw
                        qstride, A, sstride, st);
   };
   if (kRows == 32) {
-    if (P3K) go(k_xfwd<T, true, 32>); else go(k_xfwd<T, false, 32>);
+    if (P3K) go(k_xfwd<T, true, 32>);
+    else if (ct_plan<128>(px, g.nx)) go(k_xfwd<T, false, 32, 128>);
+    else if (ct_plan<64>(px, g.nx)) go(k_xfwd<T, false, 32, 64>);
+    else if (ct_plan<32>(px, g.nx)) go(k_xfwd<T, false, 32, 32>);
+    else go(k_xfwd<T, false, 32>);
   } else if (kRows == 8) {
-    if (P3K) go(k_xfwd<T, true, 8>); else go(k_xfwd<T, false, 8>);
+    if (P3K) go(k_xfwd<T, true, 8>);
+    else if (ct_plan<256>(px, g.nx)) go(k_xfwd<T, false, 8, 256>);
+    else go(k_xfwd<T, false, 8>);
   } else {
-    if (P3K) go(k_xfwd<T, true, 16>); else go(k_xfwd<T, false, 16>);
+    if (P3K) go(k_xfwd<T, true, 16>);
+    else if (ct_plan<128>(px, g.nx)) go(k_xfwd<T, false, 16, 128>);
+    else if (ct_plan<256>(px, g.nx)) go(k_xfwd<T, false, 16, 256>);
+    else if (ct_plan<64>(px, g.nx)) go(k_xfwd<T, false, 16, 64>);
+    else if (ct_plan<32>(px, g.nx)) go(k_xfwd<T, false, 16, 32>);
+    else go(k_xfwd<T, false, 16>);
   }
   return hipGetLastError();
 }
@@ -1084,13 +1123,18 @@ hipError_t launch_yfwd(const Grid& g, const AxisPlan& py, const cplx<double>* tw
   const int zb = ypass_zb(g);
   dim3 grid((g.nz + zb - 1) / zb, g.nxh, nload * g.nd);
   size_t lds = sizeof(cplx<T>) * (size_t)(g.ny + zb * lds_stride<T>(g.ny));
-  if (lds > 65536)
-    hipFuncSetAttribute(P3K ? (const void*)k_yfwd<T, true> : (const void*)k_yfwd<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
-  if (P3K)
-    hipLaunchKernelGGL((k_yfwd<T, true>), grid, dim3(kThreads), lds, s, g, py, twy, zb, A, B, sstride, st);
-  else
-    hipLaunchKernelGGL((k_yfwd<T, false>), grid, dim3(kThreads), lds, s, g, py, twy, zb, A, B, sstride, st);
+  auto go = [&](auto kern) {
+    if (lds > 65536)
+      hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, s, g, py, twy, zb, A, B, sstride, st);
+  };
+  if (P3K) go(k_yfwd<T, true>);
+  else if (ct_plan<128>(py, g.ny)) go(k_yfwd<T, false, 128>);
+  else if (ct_plan<64>(py, g.ny)) go(k_yfwd<T, false, 64>);
+  else if (ct_plan<256>(py, g.ny)) go(k_yfwd<T, false, 256>);
+  else if (ct_plan<32>(py, g.ny)) go(k_yfwd<T, false, 32>);
+  else if (ct_plan<16>(py, g.ny)) go(k_yfwd<T, false, 16>);
+  else go(k_yfwd<T, false>);
   return hipGetLastError();
 }
 
@@ -1151,13 +1195,18 @@ hipError_t launch_yinv(const Grid& g, const AxisPlan& py, const cplx<double>* tw
   const int zb = ypass_zb(g);
   dim3 grid((g.nz + zb - 1) / zb, g.nxh, nload * g.nd);
   size_t lds = sizeof(cplx<T>) * (size_t)(g.ny + zb * lds_stride<T>(g.ny));
-  if (lds > 65536)
-    hipFuncSetAttribute(P3K ? (const void*)k_yinv<T, true> : (const void*)k_yinv<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
-  if (P3K)
-    hipLaunchKernelGGL((k_yinv<T, true>), grid, dim3(kThreads), lds, s, g, py, twy, zb, B, A, sstride, st);
-  else
-    hipLaunchKernelGGL((k_yinv<T, false>), grid, dim3(kThreads), lds, s, g, py, twy, zb, B, A, sstride, st);
+  auto go = [&](auto kern) {
+    if (lds > 65536)
+      hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, s, g, py, twy, zb, B, A, sstride, st);
+  };
+  if (P3K) go(k_yinv<T, true>);
+  else if (ct_plan<128>(py, g.ny)) go(k_yinv<T, false, 128>);
+  else if (ct_plan<64>(py, g.ny)) go(k_yinv<T, false, 64>);
+  else if (ct_plan<256>(py, g.ny)) go(k_yinv<T, false, 256>);
+  else if (ct_plan<32>(py, g.ny)) go(k_yinv<T, false, 32>);
+  else if (ct_plan<16>(py, g.ny)) go(k_yinv<T, false, 16>);
+  else go(k_yinv<T, false>);
   return hipGetLastError();
 }
 
@@ -1177,11 +1226,22 @@ hipError_t launch_xinv(const Grid& g, const AxisPlan& px, const cplx<double>* tw
                        p, fstride, st);
   };
   if (kRows == 32) {
-    if (P3K) go(k_xinv<T, true, 32>); else go(k_xinv<T, false, 32>);
+    if (P3K) go(k_xinv<T, true, 32>);
+    else if (ct_plan<128>(px, g.nx)) go(k_xinv<T, false, 32, 128>);
+    else if (ct_plan<64>(px, g.nx)) go(k_xinv<T, false, 32, 64>);
+    else if (ct_plan<32>(px, g.nx)) go(k_xinv<T, false, 32, 32>);
+    else go(k_xinv<T, false, 32>);
   } else if (kRows == 8) {
-    if (P3K) go(k_xinv<T, true, 8>); else go(k_xinv<T, false, 8>);
+    if (P3K) go(k_xinv<T, true, 8>);
+    else if (ct_plan<256>(px, g.nx)) go(k_xinv<T, false, 8, 256>);
+    else go(k_xinv<T, false, 8>);
   } else {
-    if (P3K) go(k_xinv<T, true, 16>); else go(k_xinv<T, false, 16>);
+    if (P3K) go(k_xinv<T, true, 16>);
+    else if (ct_plan<128>(px, g.nx)) go(k_xinv<T, false, 16, 128>);
+    else if (ct_plan<256>(px, g.nx)) go(k_xinv<T, false, 16, 256>);
+    else if (ct_plan<64>(px, g.nx)) go(k_xinv<T, false, 16, 64>);
+    else if (ct_plan<32>(px, g.nx)) go(k_xinv<T, false, 16, 32>);
+    else go(k_xinv<T, false, 16>);
   }
   return hipGetLastError();
 }
