@@ -281,13 +281,14 @@ __device__ cplx<T>* fft_lines(cplx<T>* a, const AxisPlan& plan, int nlines, cons
   return a;
 }
 
-// Radix plan of a power-of-two length as the host builds it: radix 8 while
-// it divides, then 4, then 2.
+// Radix plan of a length as the host builds it: radix 8 while it divides,
+// then 4, then 2, then 3.
 __host__ __device__ constexpr int p2_nstage(int n) {
   int s = 0;
   while (n % 8 == 0) { n /= 8; ++s; }
   while (n % 4 == 0) { n /= 4; ++s; }
   while (n % 2 == 0) { n /= 2; ++s; }
+  while (n % 3 == 0) { n /= 3; ++s; }
   return s;
 }
 __host__ __device__ constexpr int p2_radix(int n, int st) {
@@ -295,6 +296,7 @@ __host__ __device__ constexpr int p2_radix(int n, int st) {
   while (n % 8 == 0) { if (s++ == st) return 8; n /= 8; }
   while (n % 4 == 0) { if (s++ == st) return 4; n /= 4; }
   while (n % 2 == 0) { if (s++ == st) return 2; n /= 2; }
+  while (n % 3 == 0) { if (s++ == st) return 3; n /= 3; }
   return 1;
 }
 __host__ __device__ constexpr unsigned p2_code(int n) {
@@ -368,7 +370,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // launch at 128^3 in FP64 (the other passes are slower that way).  FP64 with
 // radix-3 stages would spill 27 registers in that budget and keeps four.
 template <typename T, bool P3, int kRows, int NX = 0>
-__global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && P3) ? 4 : 5) k_xfwd(Grid g, AxisPlan px, const cplx<double>* twx,
+__global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && P3 && NX == 0) ? 4 : 5) k_xfwd(Grid g, AxisPlan px, const cplx<double>* twx,
                                                   int mode, T* r, long long rstride, const T* q,
                                                   long long qstride, cplx<T>* A,
                                                   long long sstride, const PcgState* st) {
@@ -619,10 +621,10 @@ __device__ double zpass_fused_mid_scalar(cplx<T>* a, int n, int ls, int kyb, int
 // Power-of-two lengths run four waves per SIMD (at most 128 VGPRs, 7 spilled
 // in FP64): 212 -> 192 us per 6-load launch at 128^3; with radix-3 stages
 // that budget would spill 44 registers, so those keep the compiler's choice.
-// NZ > 0: the z length, a power of two whose plan is p2_code(NZ), known at
-// compile time (the solve stages then use the compile-time stage code).
+// NZ > 0: the z length, whose plan is p2_code(NZ), known at compile time
+// (the solve stages then use the compile-time stage code).
 template <typename T, bool P3, int NZ = 0>
-__global__ void __launch_bounds__(kThreads, P3 ? 1 : 4) k_zpass(Grid g, AxisPlan pz, const cplx<double>* twz,
+__global__ void __launch_bounds__(kThreads, (P3 && NZ == 0) ? 1 : 4) k_zpass(Grid g, AxisPlan pz, const cplx<double>* twz,
                                                    int mode, int kyb, cplx<T>* B,
                                                    long long sstride, const T* kplus,
                                                    const PcgState* st, double* rz_part) {
@@ -1087,7 +1089,9 @@ hipError_t launch_xfwd(const Grid& g, const AxisPlan& px, const cplx<double>* tw
                        qstride, A, sstride, st);
   };
   if (kRows == 32) {
-    if (P3K) go(k_xfwd<T, true, 32>);
+    if (ct_plan<96>(px, g.nx)) go(k_xfwd<T, true, 32, 96>);
+    else if (ct_plan<48>(px, g.nx)) go(k_xfwd<T, true, 32, 48>);
+    else if (P3K) go(k_xfwd<T, true, 32>);
     else if (ct_plan<128>(px, g.nx)) go(k_xfwd<T, false, 32, 128>);
     else if (ct_plan<64>(px, g.nx)) go(k_xfwd<T, false, 32, 64>);
     else if (ct_plan<32>(px, g.nx)) go(k_xfwd<T, false, 32, 32>);
@@ -1097,7 +1101,9 @@ hipError_t launch_xfwd(const Grid& g, const AxisPlan& px, const cplx<double>* tw
     else if (ct_plan<256>(px, g.nx)) go(k_xfwd<T, false, 8, 256>);
     else go(k_xfwd<T, false, 8>);
   } else {
-    if (P3K) go(k_xfwd<T, true, 16>);
+    if (ct_plan<96>(px, g.nx)) go(k_xfwd<T, true, 16, 96>);
+    else if (ct_plan<48>(px, g.nx)) go(k_xfwd<T, true, 16, 48>);
+    else if (P3K) go(k_xfwd<T, true, 16>);
     else if (ct_plan<128>(px, g.nx)) go(k_xfwd<T, false, 16, 128>);
     else if (ct_plan<256>(px, g.nx)) go(k_xfwd<T, false, 16, 256>);
     else if (ct_plan<64>(px, g.nx)) go(k_xfwd<T, false, 16, 64>);
@@ -1128,7 +1134,9 @@ hipError_t launch_yfwd(const Grid& g, const AxisPlan& py, const cplx<double>* tw
       hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, s, g, py, twy, zb, A, B, sstride, st);
   };
-  if (P3K) go(k_yfwd<T, true>);
+  if (ct_plan<96>(py, g.ny)) go(k_yfwd<T, true, 96>);
+  else if (ct_plan<48>(py, g.ny)) go(k_yfwd<T, true, 48>);
+  else if (P3K) go(k_yfwd<T, true>);
   else if (ct_plan<128>(py, g.ny)) go(k_yfwd<T, false, 128>);
   else if (ct_plan<64>(py, g.ny)) go(k_yfwd<T, false, 64>);
   else if (ct_plan<256>(py, g.ny)) go(k_yfwd<T, false, 256>);
@@ -1177,7 +1185,9 @@ hipError_t launch_zpass(const Grid& g, const AxisPlan& pz, const cplx<double>* t
     constexpr int NZ = decltype(nzc)::value;
     return g.nz == NZ && pz.n == NZ && pz.nstage == p2_nstage(NZ) && pz.code == p2_code(NZ);
   };
-  if (P3K) go(k_zpass<T, true>);
+  if (ct(std::integral_constant<int, 96>{})) go(k_zpass<T, true, 96>);
+  else if (ct(std::integral_constant<int, 48>{})) go(k_zpass<T, true, 48>);
+  else if (P3K) go(k_zpass<T, true>);
   else if (ct(std::integral_constant<int, 128>{})) go(k_zpass<T, false, 128>);
   else if (ct(std::integral_constant<int, 64>{})) go(k_zpass<T, false, 64>);
   else if (ct(std::integral_constant<int, 256>{})) go(k_zpass<T, false, 256>);
@@ -1200,7 +1210,9 @@ hipError_t launch_yinv(const Grid& g, const AxisPlan& py, const cplx<double>* tw
       hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(kern, grid, dim3(kThreads), lds, s, g, py, twy, zb, B, A, sstride, st);
   };
-  if (P3K) go(k_yinv<T, true>);
+  if (ct_plan<96>(py, g.ny)) go(k_yinv<T, true, 96>);
+  else if (ct_plan<48>(py, g.ny)) go(k_yinv<T, true, 48>);
+  else if (P3K) go(k_yinv<T, true>);
   else if (ct_plan<128>(py, g.ny)) go(k_yinv<T, false, 128>);
   else if (ct_plan<64>(py, g.ny)) go(k_yinv<T, false, 64>);
   else if (ct_plan<256>(py, g.ny)) go(k_yinv<T, false, 256>);
@@ -1226,7 +1238,9 @@ hipError_t launch_xinv(const Grid& g, const AxisPlan& px, const cplx<double>* tw
                        p, fstride, st);
   };
   if (kRows == 32) {
-    if (P3K) go(k_xinv<T, true, 32>);
+    if (ct_plan<96>(px, g.nx)) go(k_xinv<T, true, 32, 96>);
+    else if (ct_plan<48>(px, g.nx)) go(k_xinv<T, true, 32, 48>);
+    else if (P3K) go(k_xinv<T, true, 32>);
     else if (ct_plan<128>(px, g.nx)) go(k_xinv<T, false, 32, 128>);
     else if (ct_plan<64>(px, g.nx)) go(k_xinv<T, false, 32, 64>);
     else if (ct_plan<32>(px, g.nx)) go(k_xinv<T, false, 32, 32>);
@@ -1236,7 +1250,9 @@ hipError_t launch_xinv(const Grid& g, const AxisPlan& px, const cplx<double>* tw
     else if (ct_plan<256>(px, g.nx)) go(k_xinv<T, false, 8, 256>);
     else go(k_xinv<T, false, 8>);
   } else {
-    if (P3K) go(k_xinv<T, true, 16>);
+    if (ct_plan<96>(px, g.nx)) go(k_xinv<T, true, 16, 96>);
+    else if (ct_plan<48>(px, g.nx)) go(k_xinv<T, true, 16, 48>);
+    else if (P3K) go(k_xinv<T, true, 16>);
     else if (ct_plan<128>(px, g.nx)) go(k_xinv<T, false, 16, 128>);
     else if (ct_plan<256>(px, g.nx)) go(k_xinv<T, false, 16, 256>);
     else if (ct_plan<64>(px, g.nx)) go(k_xinv<T, false, 16, 64>);
