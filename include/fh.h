@@ -427,9 +427,19 @@ typedef struct fh_batch_report {
  * each system's homogenized tensor in energy form; st (may be NULL) one
  * fh_stats per system; rep (may be NULL) the per-group tuning and timings.
  * opt as for fh_solve (FH_FP32_REFINED recommended).  At most FH_MAX_GROUPS
- * distinct grid sizes.  Device scratch is allocated inside the call.       */
+ * distinct grid sizes.  With a workspace bound to ctx (fh_bind_workspace) of
+ * at least fh_batch_workspace_size bytes, the groups take their fields,
+ * spectra and K^+ from it (disjoint regions, overwritten by the call);
+ * otherwise they allocate them.  A bound workspace that is too small is
+ * FH_ENOMEM.  Small per-group tables (packed phases, twiddles, material
+ * tables) are allocated inside the call either way.                       */
 int fh_solve_batch(fh_ctx *ctx, int nsys, const fh_system *sys, int nload, const double *E,
                    const fh_opts *opt, double *chom, fh_stats *st, fh_batch_report *rep);
+
+/* Device bytes fh_solve_batch takes from a bound workspace for these
+ * systems and nload load cases (arguments as for fh_solve_batch).          */
+int fh_batch_workspace_size(fh_ctx *ctx, int nsys, const fh_system *sys, int nload,
+                            size_t *bytes);
 
 #ifdef __cplusplus
 }

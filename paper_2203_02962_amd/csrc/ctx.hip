@@ -1562,7 +1562,8 @@ struct BatchGate {
 
 int batch_group(fh_ctx* parent, const std::vector<int>& idx, const fh_system* sys, int nload,
                 const double* E, const fh_opts& o, double* chom, fh_stats* st,
-                fh_batch_report* rep, int gi, BatchGate* gate) {
+                fh_batch_report* rep, int gi, BatchGate* gate, char* region,
+                size_t region_bytes) {
   // the gate is passed exactly once, whatever path leaves this function
   struct Arrive {
     BatchGate* g;
@@ -1618,6 +1619,10 @@ int batch_group(fh_ctx* parent, const std::vector<int>& idx, const fh_system* sy
   c->nload = nms * nload;
   c->loads.clear();
   for (int ms = 0; ms < nms; ++ms) c->loads.insert(c->loads.end(), E, E + (size_t)nload * 6);
+  if (region) {  // a region of the caller's bound workspace
+    c->ws_user = region;
+    c->ws_user_bytes = region_bytes;
+  }
   if ((rc = ensure_layout(c))) return pfail(rc);
   fh_ctx::Layout& L = c->L;
   // per microstructure: Cref = mean (Sec. 6.2), Alg. 2 symbol, right-hand sides
@@ -1773,21 +1778,18 @@ int batch_group(fh_ctx* parent, const std::vector<int>& idx, const fh_system* sy
 
 }  // namespace
 
-extern "C" int fh_solve_batch(fh_ctx* c, int nsys, const fh_system* sys, int nload,
-                              const double* E, const fh_opts* opt, double* chom, fh_stats* st,
-                              fh_batch_report* rep) {
-  if (!c || nsys < 1 || !sys || nload < 1 || nload > 8 || !E || !chom) return FH_EINVAL;
-  hipSetDevice(c->device);
-  fh_opts o{1e-10, 10000, FH_FP64, 0, 0, 0.0};
-  if (opt) o = *opt;
-  if (!(o.eta > 0.0) || o.itmax < 1) return fail(c, FH_EINVAL, "bad eta/itmax");
-  // group by grid size, keeping first-appearance order
+// Systems grouped by grid size, in order of first appearance.
+int batch_groups(fh_ctx* c, int nsys, const fh_system* sys,
+                 std::vector<std::vector<int>>& groups) {
   std::vector<std::array<int, 3>> sizes;
-  std::vector<std::vector<int>> groups;
+  groups.clear();
   for (int i = 0; i < nsys; ++i) {
     const fh_system& s = sys[i];
     if (!s.phase_dev || !s.mat || s.nphase < 1 || s.nphase > 16)
       return fail(c, FH_EINVAL, "bad system " + std::to_string(i));
+    for (int k = 0; k < 3; ++k)
+      if (s.n[k] < 2 || s.n[k] > 256 || !factor_ok(s.n[k]) || (k < 2 && s.n[k] % 2))
+        return fail(c, FH_EINVAL, "bad grid size in system " + std::to_string(i));
     std::array<int, 3> key{s.n[0], s.n[1], s.n[2]};
     auto it = std::find(sizes.begin(), sizes.end(), key);
     if (it == sizes.end()) {
@@ -1798,6 +1800,66 @@ extern "C" int fh_solve_batch(fh_ctx* c, int nsys, const fh_system* sys, int nlo
     }
   }
   if ((int)groups.size() > FH_MAX_GROUPS) return fail(c, FH_EINVAL, "too many grid sizes");
+  return FH_OK;
+}
+
+// Device bytes of one group's layout (fields, spectra, K^+, partial sums):
+// the same computation as ensure_layout on a host-only context that carries
+// the group's grid and load count.
+size_t batch_group_bytes(const int n[3], int nms, int nload) {
+  fh_ctx t;
+  t.g.nx = n[0];
+  t.g.ny = n[1];
+  t.g.nz = n[2];
+  t.g.dim = 3;
+  t.g.nd = 3;
+  t.g.nxh = n[0] / 2 + 1;
+  t.g.N = (long long)n[0] * n[1] * n[2];
+  t.g.nphase_max = 1;
+  t.g.G = nload;
+  t.nms = nms;
+  t.nload = nms * nload;
+  return align_up(layout(&t, nullptr, nullptr));
+}
+
+extern "C" int fh_batch_workspace_size(fh_ctx* c, int nsys, const fh_system* sys, int nload,
+                                       size_t* bytes) {
+  if (!c || nsys < 1 || !sys || nload < 1 || nload > 8 || !bytes) return FH_EINVAL;
+  std::vector<std::vector<int>> groups;
+  const int rc = batch_groups(c, nsys, sys, groups);
+  if (rc) return rc;
+  size_t total = 0;
+  for (const auto& gr : groups) total += batch_group_bytes(sys[gr[0]].n, (int)gr.size(), nload);
+  *bytes = total;
+  return FH_OK;
+}
+
+extern "C" int fh_solve_batch(fh_ctx* c, int nsys, const fh_system* sys, int nload,
+                              const double* E, const fh_opts* opt, double* chom, fh_stats* st,
+                              fh_batch_report* rep) {
+  if (!c || nsys < 1 || !sys || nload < 1 || nload > 8 || !E || !chom) return FH_EINVAL;
+  hipSetDevice(c->device);
+  fh_opts o{1e-10, 10000, FH_FP64, 0, 0, 0.0};
+  if (opt) o = *opt;
+  if (!(o.eta > 0.0) || o.itmax < 1) return fail(c, FH_EINVAL, "bad eta/itmax");
+  std::vector<std::vector<int>> groups;
+  int grc = batch_groups(c, nsys, sys, groups);
+  if (grc) return grc;
+  // with a workspace bound to the context, every group takes its layout
+  // from it (disjoint regions in group order) instead of allocating one
+  std::vector<char*> region(groups.size(), nullptr);
+  std::vector<size_t> region_bytes(groups.size(), 0);
+  if (c->ws_user) {
+    size_t off = 0;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      region_bytes[gi] = batch_group_bytes(sys[groups[gi][0]].n, (int)groups[gi].size(), nload);
+      region[gi] = (char*)c->ws_user + off;
+      off += region_bytes[gi];
+    }
+    if (off > c->ws_user_bytes)
+      return fail(c, FH_ENOMEM, "bound workspace too small for the batch: need " +
+                                    std::to_string(off) + " bytes");
+  }
   if (rep) *rep = fh_batch_report{};
   if (rep) rep->ngroups = (int)groups.size();
   if (c->stream) {
@@ -1809,7 +1871,8 @@ extern "C" int fh_solve_batch(fh_ctx* c, int nsys, const fh_system* sys, int nlo
   const int ng = (int)groups.size();
   if ((o.flags & FH_FLAG_BATCH_SERIAL) || ng == 1) {
     for (int gi = 0; gi < ng; ++gi) {
-      const int rc = batch_group(c, groups[gi], sys, nload, E, o, chom, st, rep, gi, nullptr);
+      const int rc = batch_group(c, groups[gi], sys, nload, E, o, chom, st, rep, gi, nullptr,
+                                 region[gi], region_bytes[gi]);
       if (rc < 0) return rc;
       if (rc > 0) worst = rc;
     }
@@ -1826,7 +1889,8 @@ extern "C" int fh_solve_batch(fh_ctx* c, int nsys, const fh_system* sys, int nlo
     holders[gi].device = c->device;
     threads.emplace_back([&, gi] {
       hipSetDevice(c->device);
-      rcs[gi] = batch_group(&holders[gi], groups[gi], sys, nload, E, o, chom, st, rep, gi, &gate);
+      rcs[gi] = batch_group(&holders[gi], groups[gi], sys, nload, E, o, chom, st, rep, gi, &gate,
+                            region[gi], region_bytes[gi]);
     });
   }
   for (std::thread& t : threads) t.join();

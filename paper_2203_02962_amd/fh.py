@@ -40,7 +40,8 @@ PROBLEMS = {"scalar": FH_SCALAR, "elastic": FH_ELASTIC}
 EXPORTED = [
     "fh_create", "fh_destroy", "fh_last_error", "fh_set_stream", "fh_set_grid",
     "fh_set_phases", "fh_set_conductivity_field", "fh_set_reference", "fh_set_load",
-    "fh_workspace_size", "fh_bind_workspace", "fh_solve", "fh_get_fluctuation",
+    "fh_workspace_size", "fh_bind_workspace", "fh_batch_workspace_size", "fh_solve",
+    "fh_get_fluctuation",
     "fh_get_homogenized", "fh_get_reference", "fh_get_history", "fh_apply_operator",
     "fh_apply_preconditioner", "fh_compute_rhs", "fh_compute_rhs_noalloc", "fh_get_symbol",
     "fh_solve_rhs",
@@ -198,6 +199,7 @@ def load_library(path: str = LIB_PATH):
         "fh_set_load": ([P, I, ctypes.POINTER(D)], I),
         "fh_workspace_size": ([P, ctypes.POINTER(ctypes.c_size_t)], I),
         "fh_bind_workspace": ([P, P, ctypes.c_size_t], I),
+        "fh_batch_workspace_size": ([P, I, P, I, ctypes.POINTER(ctypes.c_size_t)], I),
         "fh_solve": ([P, ctypes.POINTER(fh_opts), ctypes.POINTER(fh_stats)], I),
         "fh_get_fluctuation": ([P, I, P], I),
         "fh_get_homogenized": ([P, ctypes.POINTER(D)], I),
@@ -544,15 +546,7 @@ class Context:
         return rc, st.as_dict()
 
 
-    def solve_batch(self, systems, E, eta=1e-6, itmax=10000, precision=FH_FP32_REFINED,
-                    poll=0, eta_inner=0.0, u_out=None, serial=False):
-        """systems: list of (phase_dev uint8 tensor, n (3,), mat (nphase, 6, 6)).
-        u_out: optional list of float64 CUDA tensors (nload x 3 x N each) that
-        receive the fluctuation fields.  serial: solve the grid-size groups
-        one after another (FH_FLAG_BATCH_SERIAL) instead of concurrently.
-        Returns (rc, chom (nsys, nload, nload), [stats dicts], [group reports])."""
-        E = np.ascontiguousarray(np.atleast_2d(E), dtype=np.float64)
-        nload = E.shape[0]
+    def _systems(self, systems, nload, u_out=None):
         mats = [np.ascontiguousarray(m, dtype=np.float64) for _, _, m in systems]
         arr = (fh_system * len(systems))()
         import torch
@@ -564,6 +558,27 @@ class Context:
             arr[i].u_dev = (_tptr(u_out[i], _f64(), nload * 3 * int(np.prod(n)),
                                   self.device).value
                             if u_out is not None and u_out[i] is not None else None)
+        return arr, mats
+
+    def batch_workspace_size(self, systems, nload):
+        """fh_batch_workspace_size: device bytes fh_solve_batch takes from a
+        bound workspace for these systems (list as for solve_batch)."""
+        arr, _mats = self._systems(systems, nload)
+        b = ctypes.c_size_t()
+        self._check(self.lib.fh_batch_workspace_size(self.ptr, len(systems), arr, int(nload),
+                                                     ctypes.byref(b)))
+        return b.value
+
+    def solve_batch(self, systems, E, eta=1e-6, itmax=10000, precision=FH_FP32_REFINED,
+                    poll=0, eta_inner=0.0, u_out=None, serial=False):
+        """systems: list of (phase_dev uint8 tensor, n (3,), mat (nphase, 6, 6)).
+        u_out: optional list of float64 CUDA tensors (nload x 3 x N each) that
+        receive the fluctuation fields.  serial: solve the grid-size groups
+        one after another (FH_FLAG_BATCH_SERIAL) instead of concurrently.
+        Returns (rc, chom (nsys, nload, nload), [stats dicts], [group reports])."""
+        E = np.ascontiguousarray(np.atleast_2d(E), dtype=np.float64)
+        nload = E.shape[0]
+        arr, mats = self._systems(systems, nload, u_out)
         chom = np.zeros((len(systems), nload, nload))
         sts = (fh_stats * len(systems))()
         rep = fh_batch_report()

@@ -561,6 +561,22 @@ def test_fp32_refined_solve_reaches_fp64_accuracy(fh, name, make):
     assert _rel(ctx.get_homogenized(), H) < 1e-10
 
 
+def _same_batch(H, sts, rep, H2, sts2, rep2):
+    """Two batch calls on the same systems agree: bit for bit when the tuner
+    picked the same launch shapes for every group (the shapes set the
+    partial-sum blocks of p.q and r.z, hence their rounding), else C_hom to
+    1e-10 relative and iterations to +-1."""
+    shapes = [(r["n"], r["kz"], r["zb"], r["kyb"], r["xrows"]) for r in rep]
+    shapes2 = [(r["n"], r["kz"], r["zb"], r["kyb"], r["xrows"]) for r in rep2]
+    if shapes == shapes2:
+        assert np.array_equal(H, H2)
+        assert [s["iterations"] for s in sts] == [s["iterations"] for s in sts2]
+    else:
+        assert np.abs(H - H2).max() <= 1e-10 * np.abs(H).max()
+        for a, b in zip(sts, sts2):
+            assert all(abs(x - y) <= 1 for x, y in zip(a["iterations"], b["iterations"]))
+
+
 def _batch_systems(specs):
     """specs: list of (n, seed, contrast); isotropic two-phase spheres."""
     out = []
@@ -574,6 +590,41 @@ def _batch_systems(specs):
         mat = np.stack([isotropic_mandel(1.0, 0.3), isotropic_mandel(contrast, 0.25)])
         out.append((ph, n3, mat))
     return out
+
+
+def test_batch_takes_its_layouts_from_a_bound_workspace(fh):
+    """With a workspace of fh_batch_workspace_size bytes bound to the
+    context, the batch groups carve their fields, spectra and K^+ from it:
+    the call writes into it and gives the same result as with library-owned
+    memory, concurrently and group by group; one byte less is FH_ENOMEM and
+    leaves the context usable."""
+    say("batch workspace")
+    specs = [(16, 1, 10.0), (24, 2, 100.0), (16, 3, 500.0), ((12, 18, 24), 4, 50.0)]
+    sysl = _batch_systems(specs)
+    ctx = fh.Context(0)
+    devs = [(torch.from_numpy(ph).cuda(), n, m) for ph, n, m in sysl]
+    E = np.eye(6)[:2]
+    rc0, H0, st0, rep0 = ctx.solve_batch(devs, E, eta=1e-8)
+    assert rc0 == 0
+    need = ctx.batch_workspace_size(devs, 2)
+    assert need > 3 * 16 ** 3 * 8 * 2 * 5      # at least x, r, p, q, b of the 16^3 systems
+    ws = torch.full((need,), 0x5A, dtype=torch.uint8, device="cuda")
+    ctx.bind_workspace(ws)
+    for serial in (False, True):
+        rc, H, st, rp = ctx.solve_batch(devs, E, eta=1e-8, serial=serial)
+        assert rc == 0
+        _same_batch(H0, st0, rep0, H, st, rp)
+    torch.cuda.synchronize()
+    assert int((ws != 0x5A).sum()) > need // 4   # the layouts went there
+    small = torch.empty((need - 1,), dtype=torch.uint8, device="cuda")
+    ctx.bind_workspace(small)
+    with pytest.raises(fh.FHError):
+        ctx.solve_batch(devs, E, eta=1e-8)
+    ctx.bind_workspace(None)
+    rc, H, st, rp = ctx.solve_batch(devs, E, eta=1e-8)
+    assert rc == 0
+    _same_batch(H0, st0, rep0, H, st, rp)
+    ctx.close()
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
@@ -593,11 +644,11 @@ def test_batch_matches_single_solves_and_oracle(fh, precision):
     rc, H, sts, rep = ctx.solve_batch(devs, np.eye(6), eta=1e-10, precision=prec, eta_inner=1e-4)
     assert rc == 0, sts
     assert len(rep) == 3 and sorted(r["nsys"] for r in rep) == [1, 2, 3]
-    # the groups ran concurrently; one after another they give the same bits
-    rc2, H2, sts2, _ = ctx.solve_batch(devs, np.eye(6), eta=1e-10, precision=prec,
-                                       eta_inner=1e-4, serial=True)
-    assert rc2 == 0 and np.array_equal(H, H2)
-    assert [s["iterations"] for s in sts] == [s["iterations"] for s in sts2]
+    # the groups ran concurrently; one after another they give the same result
+    rc2, H2, sts2, rep2 = ctx.solve_batch(devs, np.eye(6), eta=1e-10, precision=prec,
+                                          eta_inner=1e-4, serial=True)
+    assert rc2 == 0
+    _same_batch(H, sts, rep, H2, sts2, rep2)
     for i, (ph, n, m) in enumerate(sysl):
         wl = dict(dim=3, n=n, problem="elastic", element="hex8", phase=ph, mat=m, loads=np.eye(6))
         c1 = setup_context(wl)
