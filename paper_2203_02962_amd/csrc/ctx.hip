@@ -934,13 +934,20 @@ struct GraphStream {
   explicit GraphStream(fh_ctx* cc) : c(cc) {}
   int fork() {
     if (!c->gstream) {
-      if (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess) {
-        c->gstream = nullptr;
-        return fail(c, FH_EDEVICE, "hipStreamCreate for graph replay failed");
+      // all three or none: a failure leaves nothing half-made behind
+      hipStream_t st = nullptr;
+      hipEvent_t ef = nullptr, ej = nullptr;
+      if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&ef, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&ej, hipEventDisableTiming) != hipSuccess) {
+        if (ej) hipEventDestroy(ej);
+        if (ef) hipEventDestroy(ef);
+        if (st) hipStreamDestroy(st);
+        return fail(c, FH_EDEVICE, "stream or event creation for graph replay failed");
       }
-      if (hipEventCreateWithFlags(&c->gfork, hipEventDisableTiming) != hipSuccess ||
-          hipEventCreateWithFlags(&c->gjoin, hipEventDisableTiming) != hipSuccess)
-        return fail(c, FH_EDEVICE, "hipEventCreate for graph replay failed");
+      c->gstream = st;
+      c->gfork = ef;
+      c->gjoin = ej;
     }
     HIPCHK(c, hipEventRecord(c->gfork, c->stream));
     HIPCHK(c, hipStreamWaitEvent(c->gstream, c->gfork, 0));
@@ -1885,15 +1892,35 @@ extern "C" int fh_solve_batch(fh_ctx* c, int nsys, const fh_system* sys, int nlo
   std::vector<fh_ctx> holders(ng);
   std::vector<int> rcs(ng, FH_OK);
   std::vector<std::thread> threads;
-  for (int gi = 0; gi < ng; ++gi) {
-    holders[gi].device = c->device;
-    threads.emplace_back([&, gi] {
-      hipSetDevice(c->device);
-      rcs[gi] = batch_group(&holders[gi], groups[gi], sys, nload, E, o, chom, st, rep, gi, &gate,
-                            region[gi], region_bytes[gi]);
-    });
+  int started = 0;
+  for (int gi = 0; gi < ng; ++gi) holders[gi].device = c->device;
+  try {
+    for (int gi = 0; gi < ng; ++gi) {
+      threads.emplace_back([&, gi] {
+        hipSetDevice(c->device);
+        try {
+          rcs[gi] = batch_group(&holders[gi], groups[gi], sys, nload, E, o, chom, st, rep, gi,
+                                &gate, region[gi], region_bytes[gi]);
+        } catch (...) {  // host allocation failure inside the group
+          rcs[gi] = FH_ENOMEM;
+          holders[gi].err = "host exception in batch group " + std::to_string(gi);
+        }
+      });
+      ++started;
+    }
+  } catch (...) {
+    // a thread could not be started: the running groups stop waiting for
+    // it at the start line, and the rest run here one after another
+    {
+      std::lock_guard<std::mutex> lk(gate.mu);
+      gate.total = started;
+      if (gate.waiting >= gate.total) gate.cv.notify_all();
+    }
   }
   for (std::thread& t : threads) t.join();
+  for (int gi = started; gi < ng; ++gi)
+    rcs[gi] = batch_group(&holders[gi], groups[gi], sys, nload, E, o, chom, st, rep, gi, nullptr,
+                          region[gi], region_bytes[gi]);
   for (int gi = 0; gi < ng; ++gi) {
     if (rcs[gi] < 0) return fail(c, rcs[gi], holders[gi].err);
     if (rcs[gi] > 0) worst = rcs[gi];
