@@ -132,6 +132,23 @@ __host__ __device__ constexpr int lds_stride(int n) {
   return sizeof(T) == 8 ? ((n + (n >> 3) + 1) | 1) : n + 1;
 }
 
+// Streaming (non-temporal) global accesses for data that is read once and
+// not again in this iteration, or written now and read only in the next one.
+template <typename T>
+__device__ __forceinline__ T ld_nt(const T* p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ __forceinline__ void st_nt(T v, T* p) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ cplx<double> ld_nt(const cplx<double>* p) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return {v.x, v.y};
+}
+__device__ __forceinline__ cplx<float> ld_nt(const cplx<float>* p) {
+  typedef float v2 __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return {v.x, v.y};
+}
+
 // Quotient by a block-uniform divisor d >= 1 through one 24-bit multiply:
 // with M = ceil(2^21 / d), (x M) >> 21 equals x / d whenever x d <= 2^21 and
 // x M < 2^32.  (Write M d = 2^21 + e with 0 <= e < d; the excess x e /
@@ -394,10 +411,10 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && P3 && NX == 0) ? 
         T v = T(0);
         if (y < ny) {
           const long long o = rbase + (long long)y * nx + x;
-          v = r[o];
+          v = ld_nt(&r[o]);
           if (mode == XF_UPDATE_R) {
-            v -= alpha * qb[(long long)y * nx + x];
-            r[o] = v;
+            v -= alpha * ld_nt(&qb[(long long)y * nx + x]);
+            st_nt(v, &r[o]);
           }
         }
         return v;
@@ -453,7 +470,7 @@ __global__ void __launch_bounds__(kThreads) k_yfwd(Grid g, AxisPlan py, const cp
   auto gsrc = [&](int zl, int y) -> cplx<T> {
     const int z = z0 + zl;
     cplx<T> v = {T(0), T(0)};
-    if (z < nz) v = A[base + (((long long)c * nz + z) * nxh + kx) * ny + y];
+    if (z < nz) v = ld_nt(&A[base + (((long long)c * nz + z) * nxh + kx) * ny + y]);
     return v;
   };
   auto lsink = [&](int l, int y, cplx<T> v) { a[__mul24(l, ls) + sw<T>(y)] = v; };
@@ -664,7 +681,7 @@ __global__ void __launch_bounds__(kThreads, (P3 && NZ == 0) ? 1 : 4) k_zpass(Gri
   auto gsrc = [&](int l, int z) -> cplx<T> {
     const int c = dkyb.q(l), ky = ky0 + dkyb.r(l, c);
     cplx<T> v = {T(0), T(0)};
-    if (ky < ny) v = B[base + c * cstride + (long long)ky * nz + z];
+    if (ky < ny) v = ld_nt(&B[base + c * cstride + (long long)ky * nz + z]);
     return v;
   };
   // solve mode: the first forward stage reads the z lines from global memory
@@ -839,7 +856,7 @@ __global__ void __launch_bounds__(kThreads) k_yinv(Grid g, AxisPlan py, const cp
       [&](int idx) {
         const int ky = dzb.q(idx), zl = dzb.r(idx, ky), z = z0 + zl;
         cplx<T> v = {T(0), T(0)};
-        if (z < nz) v = B[ibase + (long long)ky * nz + z];
+        if (z < nz) v = ld_nt(&B[ibase + (long long)ky * nz + z]);
         return v;
       },
       [&](int idx, cplx<T> v) {
@@ -910,8 +927,8 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
       const int row = dnx.q(idx), xx = dnx.r(idx, row), y = y0 + row;
       if (idx < nout && y < ny) {
         const long long o = fbase + (long long)y * nx + xx;
-        pv0[k] = p[o];
-        xv0[k] = x[o];
+        pv0[k] = ld_nt(&p[o]);
+        xv0[k] = ld_nt(&x[o]);
       }
     }
   }
@@ -921,7 +938,7 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
       [&](int idx) {
         const int yl = idx % kRows, kx = idx / kRows, y = y0 + yl;
         cplx<T> v = {T(0), T(0)};
-        if (y < ny) v = A[abase + (long long)kx * ny + y];
+        if (y < ny) v = ld_nt(&A[abase + (long long)kx * ny + y]);
         return v;
       },
       [&](int idx, cplx<T> v) {
@@ -982,8 +999,8 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
         const int row = dnx.q(idx), xx = dnx.r(idx, row), y = y0 + row;
         if (idx < nout && y < ny) {
           const long long o = fbase + (long long)y * nx + xx;
-          pv[k] = p[o];
-          xv[k] = x[o];
+          pv[k] = ld_nt(&p[o]);
+          xv[k] = ld_nt(&x[o]);
         }
       }
     }
@@ -1000,7 +1017,7 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
       } else if (mode == XI_INIT_P) {
         p[o] = zv;
       } else {
-        x[o] = xv[k] + alpha * pv[k];
+        st_nt(xv[k] + alpha * pv[k], &x[o]);
         p[o] = zv + beta * pv[k];
       }
     }
