@@ -504,11 +504,15 @@ __global__ void __launch_bounds__(kThreads) k_yfwd(Grid g, AxisPlan py, const cp
 // needs exactly those two, so only the three components of a frequency pair
 // have to meet in one thread: one LDS round trip and the solve pass are
 // saved.
-template <typename T, int NC = 0>
+constexpr int kFusedMaxIt = (2048 / 6 + kThreads - 1) / kThreads;  // kyb * n/2 <= 2048 / 6
+// PRE: the thread's K^+ entries were loaded into kpre[item][t][0..5] before
+// the forward stages (else they are read here and kpre is not touched)
+template <typename T, int NC = 0, bool PRE = false>
 __device__ double zpass_fused_mid(cplx<T>* a, int n_rt, int ls, int cls, int kyb, int ky0, int ny,
                                   int nz, int kx, const cplx<T>* tw, const T* kplus,
-                                  long long nfreq, double wgt) {
-  constexpr int MAXIT = (2048 / 6 + kThreads - 1) / kThreads;  // kyb * n/2 <= 2048 / 6
+                                  long long nfreq, double wgt,
+                                  const T (&kpre)[kFusedMaxIt][2][6]) {
+  constexpr int MAXIT = kFusedMaxIt;
   const int n = NC ? NC : n_rt;
   const int m = n / 2;
   const int items = kyb * m;
@@ -546,9 +550,10 @@ __device__ double zpass_fused_mid(cplx<T>* a, int n_rt, int ls, int cls, int kyb
       for (int t = 0; t < 2; ++t) {
         // below 6 nxh ny nz < 2^31 for every accepted grid
         const int f = (kx * ny + ky) * nz + j + t * m;
-        const T k00 = kplus[f], k11 = kplus[nfreq + f], k22 = kplus[2 * nfreq + f];
-        const T k12 = kplus[3 * nfreq + f], k02 = kplus[4 * nfreq + f],
-                k01 = kplus[5 * nfreq + f];
+        T kk[6];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) kk[e] = PRE ? kpre[k][t][e] : kplus[e * nfreq + f];
+        const T k00 = kk[0], k11 = kk[1], k22 = kk[2], k12 = kk[3], k02 = kk[4], k01 = kk[5];
         const cplx<T> r0 = v[k][0][t], r1 = v[k][1][t], r2 = v[k][2][t];
         const cplx<T> z0v = {k00 * r0.re + k01 * r1.re + k02 * r2.re,
                              k00 * r0.im + k01 * r1.im + k02 * r2.im};
@@ -580,11 +585,16 @@ __device__ double zpass_fused_mid(cplx<T>* a, int n_rt, int ls, int cls, int kyb
 // 2, 4 or 8.  The solve is a multiplication per frequency, so the R outputs
 // of a forward butterfly are exactly the R inputs of the matching inverse
 // butterfly and never leave the thread.
-template <typename T, int R>
+template <int R>
+constexpr int fused_scalar_maxit() {
+  return (2048 / R + kThreads - 1) / kThreads;  // kyb * n <= 2048
+}
+// PRE: as for the elastic form, kpre[item][t] holds the item's K^+ entries
+template <typename T, int R, bool PRE = false>
 __device__ double zpass_fused_mid_scalar(cplx<T>* a, int n, int ls, int kyb, int ky0, int ny,
                                          int nz, int kx, const cplx<T>* tw, const T* kplus,
-                                         double wgt) {
-  constexpr int MAXIT = (2048 / R + kThreads - 1) / kThreads;  // kyb * n <= 2048
+                                         double wgt, const T (&kpre)[fused_scalar_maxit<R>()][R]) {
+  constexpr int MAXIT = fused_scalar_maxit<R>();
   const int m = n / R;
   const int items = kyb * m;
   const UDiv dm(m);
@@ -617,7 +627,7 @@ __device__ double zpass_fused_mid_scalar(cplx<T>* a, int n, int ls, int kyb, int
     if (ky < ny) {
 #pragma unroll
       for (int t = 0; t < R; ++t) {
-        const T kp = kplus[(kx * ny + ky) * nz + j + t * m];
+        const T kp = PRE ? kpre[k][t] : kplus[(kx * ny + ky) * nz + j + t * m];
         const cplx<T> r = v[k][t];
         part += wgt * (double)kp * ((double)r.re * r.re + (double)r.im * r.im);
         v[k][t] = {kp * r.re, kp * r.im};
@@ -715,27 +725,64 @@ __global__ void __launch_bounds__(kThreads, (P3 && NZ == 0) ? 1 : 4) k_zpass(Gri
     const double wgt = (kx == 0 || (2 * kx == g.nx)) ? 1.0 : 2.0;
     if constexpr (NZ > 0) {
       constexpr int NS = p2_nstage(NZ), R0c = p2_radix(NZ, 0), RLc = p2_radix(NZ, NS - 1);
+      // K^+ of the frequencies this thread solves, loaded before the forward
+      // stages so that its latency overlaps them (same item mapping as the
+      // fused solve)
+      T kpre[kFusedMaxIt][2][6];
+      T kpre1[fused_scalar_maxit<RLc>()][RLc];
+      if (nd == 3) {
+#pragma unroll
+        for (int k = 0; k < kFusedMaxIt; ++k) {
+          const int it = threadIdx.x + k * kThreads, kyl = it / (NZ / 2), j = it % (NZ / 2);
+          const int ky = ky0 + kyl;
+          if (it < kyb * (NZ / 2) && ky < ny) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+              const int f = (kx * ny + ky) * NZ + j + t * (NZ / 2);
+#pragma unroll
+              for (int e = 0; e < 6; ++e) kpre[k][t][e] = kplus[e * nfreq + f];
+            }
+          }
+        }
+      } else {
+        constexpr int M = NZ / RLc;
+#pragma unroll
+        for (int k = 0; k < fused_scalar_maxit<RLc>(); ++k) {
+          const int it = threadIdx.x + k * kThreads, kyl = it / M, j = it % M;
+          const int ky = ky0 + kyl;
+          if (it < kyb * M && ky < ny) {
+#pragma unroll
+            for (int t = 0; t < RLc; ++t) kpre1[k][t] = kplus[(kx * ny + ky) * NZ + j + t * M];
+          }
+        }
+      }
       stockham_stage_io<T, R0c, NZ, 1>(gsrc, lsink, false, NZ, nd * kyb, 1, tw, -1);
       stages_ct<T, NZ, 1, NS - 1, false, R0c>(a, nd * kyb, tw, -1);
       if (nd == 3)
-        part = zpass_fused_mid<T, NZ>(a, NZ, ls, cls, kyb, ky0, ny, nz, kx, tw, kplus, nfreq,
-                                      wgt);
+        part = zpass_fused_mid<T, NZ, true>(a, NZ, ls, cls, kyb, ky0, ny, nz, kx, tw, kplus,
+                                            nfreq, wgt, kpre);
       else
-        part = zpass_fused_mid_scalar<T, RLc>(a, NZ, ls, kyb, ky0, ny, nz, kx, tw, kplus, wgt);
+        part = zpass_fused_mid_scalar<T, RLc, true>(a, NZ, ls, kyb, ky0, ny, nz, kx, tw, kplus,
+                                                    wgt, kpre1);
       stages_ct<T, NZ, 1, NS - 1, true, RLc>(a, nd * kyb, tw, +1);
       stockham_stage_io<T, R0c, NZ, NZ / R0c>(lsrc, gsink, false, NZ, nd * kyb, NZ / R0c, tw,
                                               +1);
     } else {
       stage_io_any<T, P3>(R0, gsrc, lsink, false, nz, nd * kyb, 1, tw, -1);
       fft_stages<T, P3>(a, pz, false, 1, pz.nstage - 1, R0, nd * kyb, tw, -1);
+      // run-time plans read K^+ in the fused solve itself (the unused
+      // preload arguments are never touched)
+      T kpre[kFusedMaxIt][2][6], kp2[fused_scalar_maxit<2>()][2],
+          kp4[fused_scalar_maxit<4>()][4], kp8[fused_scalar_maxit<8>()][8];
       if (nd == 3)
-        part = zpass_fused_mid<T>(a, nz, ls, cls, kyb, ky0, ny, nz, kx, tw, kplus, nfreq, wgt);
+        part = zpass_fused_mid<T>(a, nz, ls, cls, kyb, ky0, ny, nz, kx, tw, kplus, nfreq, wgt,
+                                  kpre);
       else if (last_radix == 2)
-        part = zpass_fused_mid_scalar<T, 2>(a, nz, ls, kyb, ky0, ny, nz, kx, tw, kplus, wgt);
+        part = zpass_fused_mid_scalar<T, 2>(a, nz, ls, kyb, ky0, ny, nz, kx, tw, kplus, wgt, kp2);
       else if (last_radix == 4)
-        part = zpass_fused_mid_scalar<T, 4>(a, nz, ls, kyb, ky0, ny, nz, kx, tw, kplus, wgt);
+        part = zpass_fused_mid_scalar<T, 4>(a, nz, ls, kyb, ky0, ny, nz, kx, tw, kplus, wgt, kp4);
       else
-        part = zpass_fused_mid_scalar<T, 8>(a, nz, ls, kyb, ky0, ny, nz, kx, tw, kplus, wgt);
+        part = zpass_fused_mid_scalar<T, 8>(a, nz, ls, kyb, ky0, ny, nz, kx, tw, kplus, wgt, kp8);
       fft_stages<T, P3>(a, pz, true, 1, pz.nstage - 1, last_radix, nd * kyb, tw, +1);
       stage_io_any<T, P3>(R0, lsrc, gsink, false, nz, nd * kyb, nz / R0, tw, +1);
     }

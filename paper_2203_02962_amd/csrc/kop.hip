@@ -247,7 +247,9 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT))
 // output nodes (p is still in the LDS plane), so no per-voxel energy is
 // formed.  The next node plane is prefetched into registers while the
 // current slab is computed; the modal forces of a slab's upper face stay in
-// registers until the next slab adds its own.  Three node planes rotate in
+// registers until the next slab adds its own, and (FP64, cubic voxels) so do
+// the in-plane modes of its node values, which are the next slab's lower
+// face.  Three node planes rotate in
 // LDS and the lower-face forces are double-buffered, so a slab needs one
 // barrier: every buffer a step overwrites was last read before the previous
 // step's barrier.
@@ -426,6 +428,27 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
 #pragma unroll
   for (int r = 0; r < 12; ++r) carry[r] = T(0);
   double dot = 0.0;
+  // in-plane modes (sum and difference along x, then y) of the four nodes
+  // of an element's face, into w[c][base + 0..3]
+  auto face_modes = [&](const T (&pl)[3][NP], int e0, T (&w)[3][8], int base) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int idx = e0 + (k >> 1) * PX + (k & 1);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) w[c][base + k] = pl[c][idx];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int bit = 1; bit < 4; bit <<= 1)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (k & bit) continue;
+          const T u0 = w[c][base + k], u1 = w[c][base + (k | bit)];
+          w[c][base + k] = u0 + u1;
+          w[c][base + (k | bit)] = u1 - u0;
+        }
+  };
   fetch(z0 - 1);
   store(0);
   fetch(z0);
@@ -434,6 +457,21 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
   __syncthreads();
   const int nsteps = z1 - z0 + 1;
   int blo = 0, bhi = 1, bnx = 2;
+  // In-plane modes of the first slab's lower face; each later slab's lower
+  // face is the previous slab's upper face, so its in-plane transform is
+  // carried instead of redone.  Taken for FP64 on cubic voxels only: in
+  // FP32 the register copies of the carry cost more than the adds they
+  // save, and the general-voxel kernel would spill.
+  constexpr bool FC = CUBE && sizeof(T) == 8;
+  T fwd[12];
+  if (FC && is_elem) {
+    T w[3][8];
+    face_modes(plane[0], ej * PX + ei, w, 0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) fwd[c * 4 + k] = w[c][k];
+  }
   for (int s = 0; s < nsteps; ++s) {
     const int zs = z0 - 1 + s;
     const int fb = s & 1;
@@ -442,25 +480,33 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
     const long long o = ((long long)zs * ny + (y0 + oy)) * nx + (x0 + ox);
     T own[3] = {T(0), T(0), T(0)};
     if (is_elem) {
+      // in-plane modes of the upper face's four nodes (x, then y), kept for
+      // the next slab, whose lower face it is; then the z butterfly with the
+      // lower face's
       T w[3][8];
+      if constexpr (FC) {
+        face_modes(plane[bhi], ej * PX + ei, w, 4);
 #pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        const int idx = (ej + ((a >> 1) & 1)) * PX + (ei + (a & 1));
-        const int buf = (a >> 2) ? bhi : blo;
+        for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) w[c][a] = plane[buf][c][idx];
-      }
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int bit = 1; bit < 8; bit <<= 1)
-#pragma unroll
-          for (int a = 0; a < 8; ++a) {
-            if (a & bit) continue;
-            const T u0 = w[c][a], u1 = w[c][a | bit];
-            w[c][a] = u0 + u1;
-            w[c][a | bit] = u1 - u0;
+          for (int k = 0; k < 4; ++k) {
+            const T lo = fwd[c * 4 + k], hi = w[c][k | 4];
+            fwd[c * 4 + k] = hi;
+            w[c][k] = lo + hi;
+            w[c][k | 4] = hi - lo;
           }
+      } else {  // both faces, then z
+        face_modes(plane[blo], ej * PX + ei, w, 0);
+        face_modes(plane[bhi], ej * PX + ei, w, 4);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const T lo = w[c][k], hi = w[c][k | 4];
+            w[c][k] = lo + hi;
+            w[c][k | 4] = hi - lo;
+          }
+      }
       const int ph = phl[blo][ej * PX + ei];
       const T lam = lmt[2 * ph], mu2 = lmt[2 * ph + 1];
       // -0 is the identity of addition, so the first sum into a mode and the
