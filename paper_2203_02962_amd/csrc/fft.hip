@@ -148,6 +148,15 @@ __device__ __forceinline__ cplx<float> ld_nt(const cplx<float>* p) {
   const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
   return {v.x, v.y};
 }
+// The x passes move real rows in runs of kXW consecutive values per lane:
+// two in FP32, so that each lane still makes 8-byte accesses, one in FP64
+// (nx is even, and every row starts at an even element).
+template <typename T>
+constexpr int kXW = sizeof(T) == 4 ? 2 : 1;
+template <typename T>
+struct xvec {
+  typedef T type __attribute__((ext_vector_type(kXW<T>)));
+};
 
 // Quotient by a block-uniform divisor d >= 1 through one 24-bit multiply:
 // with M = ceil(2^21 / d), (x M) >> 21 equals x / d whenever x d <= 2^21 and
@@ -404,25 +413,36 @@ __global__ void __launch_bounds__(kThreads, (sizeof(T) == 8 && P3 && NX == 0) ? 
   const int lsx = lds_stride<T>(nx);
   const T* qb = q ? q + (long long)ld * qstride + ((long long)c * g.nz + z) * ny * nx : nullptr;
   const UDiv dnx(nx);
-  staged_fill<8, T>(
-      kRows * nx,
-      [&](int idx) {
+  constexpr int W = kXW<T>;
+  using TV = typename xvec<T>::type;
+  staged_fill<8, TV>(
+      kRows * nx / W,
+      [&](int iv) {
+        const int idx = W * iv;
         const int row = dnx.q(idx), x = dnx.r(idx, row), y = y0 + row;
-        T v = T(0);
+        TV v;
+#pragma unroll
+        for (int e = 0; e < W; ++e) v[e] = T(0);
         if (y < ny) {
           const long long o = rbase + (long long)y * nx + x;
-          v = ld_nt(&r[o]);
+          v = ld_nt(reinterpret_cast<const TV*>(&r[o]));
           if (mode == XF_UPDATE_R) {
-            v -= alpha * ld_nt(&qb[(long long)y * nx + x]);
-            st_nt(v, &r[o]);
+            const TV qv = ld_nt(reinterpret_cast<const TV*>(&qb[(long long)y * nx + x]));
+#pragma unroll
+            for (int e = 0; e < W; ++e) v[e] -= alpha * qv[e];
+            st_nt(v, reinterpret_cast<TV*>(&r[o]));
           }
         }
         return v;
       },
-      [&](int idx, T v) {
+      [&](int iv, TV v) {
+        const int idx = W * iv;
         const int row = dnx.q(idx), x = dnx.r(idx, row);
-        cplx<T>& d = a[__mul24(row >> 1, lsx) + sw<T>(x)];
-        if (row & 1) d.im = v; else d.re = v;
+        cplx<T>* d = a + __mul24(row >> 1, lsx);
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+          if (row & 1) d[sw<T>(x + e)].im = v[e]; else d[sw<T>(x + e)].re = v[e];
+        }
       });
   __syncthreads();
   cplx<T>* res = a;
@@ -965,17 +985,19 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
   // PCG mode: the reads of p and x for the first 8 trips of the output loop
   // are issued here, before the spectrum tile, and land during the FFT
   constexpr int CH = 8;
-  const int nout = kRows * nx;
-  T pv0[CH], xv0[CH];
+  constexpr int W = kXW<T>;
+  using TV = typename xvec<T>::type;
+  const int nout = kRows * nx / W;  // runs of W values
+  TV pv0[CH], xv0[CH];
   if (mode == XI_PCG) {
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
-      const int idx = threadIdx.x + k * kThreads;
+      const int iv = threadIdx.x + k * kThreads, idx = W * iv;
       const int row = dnx.q(idx), xx = dnx.r(idx, row), y = y0 + row;
-      if (idx < nout && y < ny) {
+      if (iv < nout && y < ny) {
         const long long o = fbase + (long long)y * nx + xx;
-        pv0[k] = ld_nt(&p[o]);
-        xv0[k] = ld_nt(&x[o]);
+        pv0[k] = ld_nt(reinterpret_cast<const TV*>(&p[o]));
+        xv0[k] = ld_nt(reinterpret_cast<const TV*>(&x[o]));
       }
     }
   }
@@ -1032,7 +1054,7 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
   const T beta = (mode == XI_PCG) ? T(st[ld].beta) : T(0);
   // later trips: the reads of 8 trips are issued before their use
   for (int base = threadIdx.x; base < nout; base += CH * kThreads) {
-    T pv[CH], xv[CH];
+    TV pv[CH], xv[CH];
     if (mode == XI_PCG && base == (int)threadIdx.x) {
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
@@ -1042,30 +1064,41 @@ __global__ void __launch_bounds__(kThreads) k_xinv(Grid g, AxisPlan px, const cp
     } else if (mode == XI_PCG) {
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
-        const int idx = base + k * kThreads;
+        const int iv = base + k * kThreads, idx = W * iv;
         const int row = dnx.q(idx), xx = dnx.r(idx, row), y = y0 + row;
-        if (idx < nout && y < ny) {
+        if (iv < nout && y < ny) {
           const long long o = fbase + (long long)y * nx + xx;
-          pv[k] = ld_nt(&p[o]);
-          xv[k] = ld_nt(&x[o]);
+          pv[k] = ld_nt(reinterpret_cast<const TV*>(&p[o]));
+          xv[k] = ld_nt(reinterpret_cast<const TV*>(&x[o]));
         }
       }
     }
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
-      const int idx = base + k * kThreads;
+      const int iv = base + k * kThreads, idx = W * iv;
       const int row = dnx.q(idx), xx = dnx.r(idx, row), y = y0 + row;
-      if (idx >= nout || y >= ny) continue;
-      const cplx<T> v = res[__mul24(row >> 1, lsx) + sw<T>(xx)];
-      const T zv = (row & 1) ? v.im : v.re;
+      if (iv >= nout || y >= ny) continue;
+      const cplx<T>* line = res + __mul24(row >> 1, lsx);
+      TV zv;
+#pragma unroll
+      for (int e = 0; e < W; ++e) {
+        const cplx<T> v = line[sw<T>(xx + e)];
+        zv[e] = (row & 1) ? v.im : v.re;
+      }
       const long long o = fbase + (long long)y * nx + xx;
       if (mode == XI_PLAIN) {
-        out[o] = zv;
+        *reinterpret_cast<TV*>(&out[o]) = zv;
       } else if (mode == XI_INIT_P) {
-        p[o] = zv;
+        *reinterpret_cast<TV*>(&p[o]) = zv;
       } else {
-        st_nt(xv[k] + alpha * pv[k], &x[o]);
-        p[o] = zv + beta * pv[k];
+        TV xn, pn;
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+          xn[e] = xv[k][e] + alpha * pv[k][e];
+          pn[e] = zv[e] + beta * pv[k][e];
+        }
+        st_nt(xn, reinterpret_cast<TV*>(&x[o]));
+        *reinterpret_cast<TV*>(&p[o]) = pn;
       }
     }
   }
