@@ -630,22 +630,26 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 3)
 // 2^-(2-|M|) / h_beta as in the isotropic elastic kernel (M = the other
 // difference bits of m).  Same z march as that kernel: node planes in LDS,
 // lower-face forces exchanged, upper-face modes carried to the next slab.
-template <typename T, int TX, int TY>
+// A block applies the operator to NL load cases at once (the z index of the
+// grid counts groups of NL): the voxel coefficients are read once for all of
+// them, each barrier serves all of them, and their independent arithmetic
+// interleaves.  Cases past nload, or no longer active, are skipped.
+template <typename T, int TX, int TY, int NL>
 __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 4)
-    k_kop_hex8_scalar(Grid g, int kz, const T* __restrict__ u, T* __restrict__ q,
+    k_kop_hex8_scalar(Grid g, int kz, int nload, const T* __restrict__ u, T* __restrict__ q,
                       const uint8_t* __restrict__ phase, const T* __restrict__ kfield,
                       const T* __restrict__ sk, long long ustride, long long qstride,
                       const PcgState* st, double* pq_part) {
   using Cfg = HexCfg<T, TX, TY>;
   constexpr int EX = Cfg::EX, PX = Cfg::PX, NEL = Cfg::NEL, NP = Cfg::NP, NT = Cfg::NT;
   constexpr int NPF = (NP + NT - 1) / NT;
-  __shared__ T plane[2][NP];
+  __shared__ T plane[2][NL][NP];
   __shared__ T cpl[2][NP];  // coefficients of the slab above each plane
-  __shared__ T force[4][NEL];
-  __shared__ double red[32];
+  __shared__ T force[4][NL][NEL];
+  __shared__ double red[4 * NL];
   extern __shared__ __align__(16) unsigned char kop_dyn[];
   T* skt = reinterpret_cast<T*>(kop_dyn);  // V k per phase (field: V)
-  int bt = blockIdx.x, bz = blockIdx.y, ld = blockIdx.z;
+  int bt = blockIdx.x, bz = blockIdx.y, lg = blockIdx.z;
   {
     const int nb = gridDim.x * gridDim.y * gridDim.z;
     if ((nb & 7) == 0) {
@@ -653,17 +657,26 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 4)
       const int l = (b & 7) * (nb >> 3) + (b >> 3);
       bt = l % gridDim.x;
       bz = (l / gridDim.x) % gridDim.y;
-      ld = l / (gridDim.x * gridDim.y);
+      lg = l / (gridDim.x * gridDim.y);
     }
   }
-  if (st && st[ld].status != ST_ACTIVE) return;
+  const int ld0 = lg * NL;
+  bool act[NL];
+  bool any = false;
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    const int ld = ld0 + l;
+    act[l] = ld < nload && (!st || st[ld].status == ST_ACTIVE);
+    any = any || act[l];
+  }
+  if (!any) return;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int ntx = (nx + TX - 1) / TX;
   const int x0 = (bt % ntx) * TX, y0 = (bt / ntx) * TY;
   const int z0 = bz * kz;
   const int z1 = min(z0 + kz, nz);
-  const T* __restrict__ ub = u + (long long)ld * ustride;
-  T* __restrict__ qb = q + (long long)ld * qstride;
+  const T* __restrict__ ub = u + (long long)ld0 * ustride;
+  T* __restrict__ qb = q + (long long)ld0 * qstride;
   const int tid = threadIdx.x;
   // element (ei, ej) and output node (ox, oy) of this thread, both with pitch PX
   const int ei = tid % PX, ej = tid / PX;
@@ -696,13 +709,19 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 4)
   }
   // A plane fetch also brings the coefficients (field value or phase) of the
   // voxels whose lowest corner is in that plane: one wait per step.
-  T pf[NPF], pc[NPF];
+  T pf[NPF][NL], pc[NPF];
+#pragma unroll
+  for (int k = 0; k < NPF; ++k)
+#pragma unroll
+    for (int l = 0; l < NL; ++l) pf[k][l] = T(0);
   auto fetch = [&](int zp) {
     const long long zb = (long long)wrapi(zp, nz) * ny * nx;
 #pragma unroll
     for (int k = 0; k < NPF; ++k)
       if (poff[k] >= 0) {
-        pf[k] = ub[zb + poff[k]];
+#pragma unroll
+        for (int l = 0; l < NL; ++l)
+          if (act[l]) pf[k][l] = ub[l * ustride + zb + poff[k]];
         pc[k] = kfield ? kfield[zb + poff[k]] : T(phase[zb + poff[k]]);
       }
   };
@@ -710,13 +729,20 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 4)
 #pragma unroll
     for (int k = 0; k < NPF; ++k)
       if (poff[k] >= 0) {
-        plane[buf][tid + k * NT] = pf[k];
+#pragma unroll
+        for (int l = 0; l < NL; ++l) plane[buf][l][tid + k * NT] = pf[k][l];
         cpl[buf][tid + k * NT] = pc[k];
       }
   };
   for (int i = tid; i < g.nphase_max; i += NT) skt[i] = sk[i];
-  T carry[4] = {T(0), T(0), T(0), T(0)};  // upper-face modes of the previous slab
-  double dot = 0.0;
+  T carry[NL][4];  // upper-face modes of the previous slab
+  double dot[NL];
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    dot[l] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) carry[l][k] = T(0);
+  }
   fetch(z0 - 1);
   store(0);
   fetch(z0);
@@ -733,53 +759,58 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 4)
     if (is_elem) {
       const T csrc = cpl[blo][ej * PX + ei];
       const T kk = kfield ? skt[0] * csrc : skt[(int)csrc];
-      T w[8];
 #pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        const int idx = (ej + ((a >> 1) & 1)) * PX + (ei + (a & 1));
-        w[a] = plane[(a >> 2) ? bhi : blo][idx];
-      }
-#pragma unroll
-      for (int bit = 1; bit < 8; bit <<= 1)
+      for (int l = 0; l < NL; ++l) {
+        if (!act[l]) continue;
+        T w[8];
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
-          if (a & bit) continue;
-          const T u0 = w[a], u1 = w[a | bit];
-          w[a] = u0 + u1;
-          w[a | bit] = u1 - u0;
+          const int idx = (ej + ((a >> 1) & 1)) * PX + (ei + (a & 1));
+          w[a] = plane[(a >> 2) ? bhi : blo][l][idx];
         }
-      // mode 0 (the mean) carries no gradient; -0 keeps its butterflies exact
-      // and lets them fold away
-      T f[8];
-      f[0] = T(-0.0);
 #pragma unroll
-      for (int a = 1; a < 8; ++a) f[a] = kk * d[a] * w[a];
-      // transpose transform, z first; the upper face's modes are carried to
-      // the next slab and added before the in-plane transform
-      T fl[4];
+        for (int bit = 1; bit < 8; bit <<= 1)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const T fm = f[k], fd = f[k | 4];
-        fl[k] = fm - fd;
-        if (s > 0) fl[k] += carry[k];
-        carry[k] = fm + fd;
-      }
-      if (s > 0) {
-#pragma unroll
-        for (int bit = 1; bit < 4; bit <<= 1)
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            if (k & bit) continue;
-            const T fm = fl[k], fd = fl[k | bit];
-            fl[k] = fm - fd;
-            fl[k | bit] = fm + fd;
+          for (int a = 0; a < 8; ++a) {
+            if (a & bit) continue;
+            const T u0 = w[a], u1 = w[a | bit];
+            w[a] = u0 + u1;
+            w[a | bit] = u1 - u0;
           }
+        // mode 0 (the mean) carries no gradient; -0 keeps its butterflies
+        // exact and lets them fold away
+        T f[8];
+        f[0] = T(-0.0);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) force[k][tid] = fl[k];
+        for (int a = 1; a < 8; ++a) f[a] = kk * d[a] * w[a];
+        // transpose transform, z first; the upper face's modes are carried
+        // to the next slab and added before the in-plane transform
+        T fl[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const T fm = f[k], fd = f[k | 4];
+          fl[k] = fm - fd;
+          if (s > 0) fl[k] += carry[l][k];
+          carry[l][k] = fm + fd;
+        }
+        if (s > 0) {
+#pragma unroll
+          for (int bit = 1; bit < 4; bit <<= 1)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              if (k & bit) continue;
+              const T fm = fl[k], fd = fl[k | bit];
+              fl[k] = fm - fd;
+              fl[k | bit] = fm + fd;
+            }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) force[k][l][tid] = fl[k];
+        }
       }
     }
-    T pd = T(0);
-    if (out_ok) pd = plane[blo][(oy + 1) * PX + (ox + 1)];
+    T pd[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) pd[l] = out_ok ? plane[blo][l][(oy + 1) * PX + (ox + 1)] : T(0);
     __syncthreads();
     if (zs + 2 <= z1) {
       store(blo);
@@ -787,16 +818,22 @@ __global__ void __launch_bounds__((HexCfg<T, TX, TY>::NT), 4)
     }
     if (out_ok) {
       const int e00 = oy * PX + ox;
-      const T v = force[3][e00] + force[2][e00 + 1] + force[1][e00 + PX] + force[0][e00 + PX + 1];
-      qb[o] = v;
-      dot += (double)pd * (double)v;
+#pragma unroll
+      for (int l = 0; l < NL; ++l) {
+        if (!act[l]) continue;
+        const T v = force[3][l][e00] + force[2][l][e00 + 1] + force[1][l][e00 + PX] +
+                    force[0][l][e00 + PX + 1];
+        qb[l * qstride + o] = v;
+        dot[l] += (double)pd[l] * (double)v;
+      }
     }
   }
   if (pq_part) {
-    const double tot = block_sum_k(dot, red);
-    if (tid == 0) {
-      const long long nb = (long long)gridDim.x * gridDim.y;
-      pq_part[(long long)ld * nb + (long long)bz * gridDim.x + bt] = tot;
+    const long long nb = (long long)gridDim.x * gridDim.y;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const double tot = block_sum_k(dot[l], red + 4 * l);
+      if (tid == 0 && act[l]) pq_part[(long long)(ld0 + l) * nb + (long long)bz * gridDim.x + bt] = tot;
     }
   }
 }
@@ -1012,11 +1049,22 @@ hipError_t launch_kop_hex8_scalar(const Grid& g, const T* u, T* q, const uint8_t
   constexpr int TX = kHexTX, TY = kHexTY;
   const int kz = hex_kz(g, (int)sizeof(T));
   const int ntiles = ((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY);
-  dim3 grid(ntiles, (g.nz + kz - 1) / kz, nload);
+  // load cases per block (FP32): three where that leaves no block with one
+  // case alone (3, 6, ... and 5 = 3 + 2 fit best), else pairs.  FP64 keeps
+  // one: its three-case kernel needs 118 VGPRs against 74, and with 15
+  // instead of 24 waves per CU it was slower (256^3, 3 loads: 425 against
+  // 367 us per launch; FP32 198 against 236 us).
+  const int NL = sizeof(T) == 8 || nload == 1 ? 1 : ((nload == 2 || nload == 4) ? 2 : 3);
+  dim3 grid(ntiles, (g.nz + kz - 1) / kz, (nload + NL - 1) / NL);
   if (nblocks_out) *nblocks_out = grid.x * grid.y;
   const size_t lds = sizeof(T) * (size_t)(g.nphase_max > 0 ? g.nphase_max : 1);
-  hipLaunchKernelGGL((k_kop_hex8_scalar<T, TX, TY>), grid, dim3(HexCfg<T, TX, TY>::NT), lds, s,
-                     g, kz, u, q, phase, kfield, sk, ustride, qstride, st, pq_part);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, dim3(HexCfg<T, TX, TY>::NT), lds, s, g, kz, nload, u, q,
+                       phase, kfield, sk, ustride, qstride, st, pq_part);
+  };
+  if (NL == 1) go(k_kop_hex8_scalar<T, TX, TY, 1>);
+  else if (NL == 2) go(k_kop_hex8_scalar<T, TX, TY, 2>);
+  else go(k_kop_hex8_scalar<T, TX, TY, 3>);
   return hipGetLastError();
 }
 template hipError_t launch_kop_hex8_scalar<double>(const Grid&, const double*, double*,
