@@ -493,6 +493,33 @@ def test_energy_products_for_any_load_count(fh, nload):
     assert _rel(ctx.get_homogenized(), E @ C6 @ E.T) < 1e-10
 
 
+@pytest.mark.parametrize("kind", ["field", "iso"])
+@pytest.mark.parametrize("nload", [1, 2, 4, 5])
+def test_refined_scalar_solves_for_any_load_count(fh, kind, nload):
+    """The FP32 scalar hex8 operator applies the operator to up to three load
+    cases per block (one, two or three by the load count; with 4 = 2 + 2 and
+    5 = 3 + 2 the last group is partly empty): refined solves of nload
+    arbitrary gradients give E C E^T, with C from the FP64 solve of the
+    three unit gradients, for a conductivity field and a per-phase table,
+    on a grid whose x and y tiles are ragged."""
+    say("refined scalar, loads", kind, nload)
+    wl, prob = _case("hex8", "scalar", (18, 12, 8), kind=kind, seed=3)
+    ctx = _ctx(fh, wl)
+    rc, _ = ctx.solve(eta=1e-12)
+    assert rc == 0
+    C3 = ctx.get_homogenized()
+    E = np.random.default_rng(60 + nload).standard_normal((nload, 3))
+    ctx.set_load(E)
+    nbytes = ctx.workspace_size()
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    off = (-ws.data_ptr()) % 256
+    ctx.bind_workspace(ws[off:off + nbytes])
+    rc, st = ctx.solve(eta=1e-12, precision=fh.FH_FP32_REFINED, eta_inner=1e-4)
+    assert rc == 0, st
+    assert _rel(ctx.get_homogenized(), E @ C3 @ E.T) < 1e-10
+    ctx.close()
+
+
 def test_breakdown_and_itmax_statuses(fh):
     say("statuses")
     wl, prob = _spheres_case(12, (1.5, 3.0), 100.0, 2)
