@@ -64,6 +64,9 @@ CASES = [
     ("hex8", "elastic", (24, 12, 18), "iso", (1.0, 0.8, 1.2)),
     ("hex8", "elastic", (36, 18, 24), "iso", None),
     ("hex8", "elastic", (4, 2, 2), "iso", None),
+    # cubic voxels, z chunks of 8, 8 and 2: the carried face modes across a
+    # partial last chunk
+    ("hex8", "elastic", (12, 18, 18), "iso", None),
     ("hex8", "scalar", (12, 18, 6), "phase", None),
     ("hex8", "scalar", (12, 18, 6), "field", (0.5, 1.0, 1.5)),
     ("hex8", "scalar", (12, 18, 6), "iso", (1.0, 0.8, 1.2)),
